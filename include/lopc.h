@@ -1,0 +1,122 @@
+/*
+ * lopc.h -- C ABI of liblopc.so, a GPU (AMD MI355X, gfx950) implementation of
+ * the compress and decompress path of LOPC, the Local-Order-Preserving
+ * Compressor (Fallin et al., arXiv 2603.26968).
+ *
+ * What a stream holds (paper sections in brackets):
+ *   - every value x is mapped to an integer bin, the nearest integer to
+ *     x / eps with eps the absolute error bound (ABS) or eb * (max - min)
+ *     (NOA) [Sec. IV-A];
+ *   - every point gets a subbin, the least integer solution of
+ *       s(p) = max(0, max over same-bin neighbours n below p of
+ *                     s(n) + [index(n) > index(p)])
+ *     so that decoding preserves the order of every pair of neighbours, ties
+ *     broken by index [Sec. IV-B, Alg. 1, Alg. 2, Sec. IV-E];
+ *   - bins are stored as DIFFNB_k BIT_k RZE_1 and subbins as BIT_k RZE_k RZE_1
+ *     in independent 16 kB chunks [Sec. III-B, Sec. IV-C];
+ *   - decompression maps (bin, subbin) to the subbin-th representable value
+ *     above the lowest value of the bin [Sec. IV-E].
+ * The byte layout of the container is this library's own (the paper gives
+ * none); it is identical to the CPU oracle's, byte for byte.
+ *
+ * Conventions for every call:
+ *   - fields are C-order arrays (last axis fastest) of float32 or float64 with
+ *     ndim = 2 or 3 and fewer than 2^32 points; the index that breaks ties is
+ *     the linear offset;
+ *   - pointers prefixed d_ are device memory, h_ host memory; every buffer is
+ *     owned by the caller; the library never allocates device memory in the
+ *     compress/decompress calls (scratch lives in the caller's workspace);
+ *   - `stream` is a hipStream_t (NULL = default stream); all device work is
+ *     ordered on it; the calls below block until their own work on that
+ *     stream is done (they return sizes and status codes to the host);
+ *   - return value: LOPC_OK (0) or a negative lopc_status; arguments are
+ *     validated before any launch; on error the output buffers hold
+ *     unspecified bytes but nothing outside them is written;
+ *   - a context may be used by one host thread at a time.
+ */
+#ifndef LOPC_H
+#define LOPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { LOPC_F32 = 0, LOPC_F64 = 1 } lopc_dtype;
+
+/* Error-bound mode [Sec. IV-A]: ABS bounds |x - x'| by error_bound; NOA by
+ * error_bound * (max(x) - min(x)). */
+typedef enum { LOPC_EB_ABS = 0, LOPC_EB_NOA = 1 } lopc_eb_mode;
+
+typedef enum {
+  LOPC_OK = 0,
+  LOPC_E_ARG = -1,       /* bad pointer, shape, dtype, mode or workspace     */
+  LOPC_E_NONFINITE = -2, /* NaN or Inf in the field                          */
+  LOPC_E_BOUND = -3,     /* bound not finite and > 0, or NOA on zero range   */
+  LOPC_E_RANGE = -4,     /* a bin does not fit (|b| > 2^31-2 f32, 2^62 f64)  */
+  LOPC_E_CAPACITY = -5,  /* output buffer too small (required size returned) */
+  LOPC_E_FORMAT = -6,    /* malformed or corrupt stream                      */
+  LOPC_E_HIP = -7,       /* a HIP runtime call failed                        */
+  LOPC_E_NOMEM = -8,     /* host allocation failed                           */
+  LOPC_E_INTERNAL = -9   /* internal limit exceeded (e.g. repair sweeps)     */
+} lopc_status;
+
+typedef struct lopc_ctx lopc_ctx;
+
+/* Optional per-call figures of a compression. */
+typedef struct {
+  double eps;                  /* absolute bound actually applied           */
+  uint64_t repair_sweeps;      /* global sweeps of the repair to fixed point */
+  uint64_t active_tiles_total; /* tiles processed over all sweeps           */
+  uint64_t bins_bytes;         /* bytes of all bins parts                   */
+  uint64_t subbins_bytes;      /* bytes of all subbin parts                 */
+} lopc_stats;
+
+/* Context for one HIP device: device properties, pinned host slots for the
+ * status words.  Returns LOPC_E_HIP if the device cannot be used. */
+int lopc_ctx_create(int hip_device, lopc_ctx** out);
+void lopc_ctx_destroy(lopc_ctx* ctx);
+
+/* Largest stream compress can produce for this shape (every stage stored
+ * verbatim): 64 + 4*chunks + sum over chunks (16 + 2*m*k), m = points of the
+ * chunk rounded up to 64, k = 4 (f32) or 8 (f64). */
+int lopc_compress_bound(int dtype, int ndim, const int64_t* dims,
+                        size_t* bytes);
+
+/* Device workspace (bytes, 256-byte aligned pointer expected) that
+ * lopc_compress (op = 0) or lopc_decompress (op = 1) needs for this shape. */
+int lopc_workspace_size(lopc_ctx* ctx, int dtype, int ndim,
+                        const int64_t* dims, int op, size_t* bytes);
+
+/* Compress d_field (dtype, ndim, dims) with error_bound under mode into
+ * d_stream (capacity stream_cap bytes).  *h_stream_size receives the stream
+ * size -- also when LOPC_E_CAPACITY is returned, so the caller can retry.
+ * d_ws/ws_bytes: workspace of at least lopc_workspace_size(op = 0).
+ * h_stats may be NULL. */
+int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
+                  const int64_t* dims, double error_bound, int mode,
+                  void* d_stream, size_t stream_cap, size_t* h_stream_size,
+                  void* d_ws, size_t ws_bytes, void* stream,
+                  lopc_stats* h_stats);
+
+/* Parse the 64-byte header of a stream held in host memory (n >= 64).
+ * Any output pointer may be NULL.  dims receives 3 values (unused = 1). */
+int lopc_stream_info(const void* h_header, size_t n, int* dtype, int* ndim,
+                     int64_t* dims, double* eps, size_t* field_bytes);
+
+/* Decompress the stream d_stream (exactly stream_size bytes) into d_field
+ * (capacity field_cap bytes).  d_ws/ws_bytes: workspace of at least
+ * lopc_workspace_size(op = 1) for the stream's shape. */
+int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
+                    void* d_field, size_t field_cap, void* d_ws,
+                    size_t ws_bytes, void* stream);
+
+/* Static text for a status code. */
+const char* lopc_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,374 @@
+// lopc_api.cpp -- host runtime of liblopc.so: argument validation, workspace
+// layout, launch sequence, status reporting.  The public contract is in
+// include/lopc.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/lopc.h"
+#include "lopc_internal.h"
+
+using namespace lopc;
+
+struct lopc_ctx {
+  int device;
+  int num_cu;
+  // pinned host slots for small device-to-host reads
+  Params* h_prm;
+  uint32_t* h_cnt;
+};
+
+namespace {
+
+constexpr uint32_t kMaxSweeps = 1u << 16;
+constexpr int kMinmaxBlocks = 1024;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Shape {
+  int ndim;
+  int64_t d[3];  // as given (2D: d[2] = 1)
+  uint64_t n;
+  Box box;
+};
+
+int make_shape(int ndim, const int64_t* dims, Shape* s) {
+  if ((ndim != 2 && ndim != 3) || !dims) return LOPC_E_ARG;
+  s->ndim = ndim;
+  uint64_t n = 1;
+  for (int i = 0; i < 3; ++i) {
+    int64_t v = i < ndim ? dims[i] : 1;
+    if (v < 1 || v > (int64_t)kMaxPoints) return LOPC_E_ARG;
+    s->d[i] = v;
+    n *= (uint64_t)v;
+    if (n > kMaxPoints) return LOPC_E_ARG;
+  }
+  s->n = n;
+  if (ndim == 2) {
+    s->box.nz = 1;
+    s->box.ny = (int32_t)s->d[0];
+    s->box.nx = (int32_t)s->d[1];
+  } else {
+    s->box.nz = (int32_t)s->d[0];
+    s->box.ny = (int32_t)s->d[1];
+    s->box.nx = (int32_t)s->d[2];
+  }
+  s->box.n = (uint32_t)n;
+  return LOPC_OK;
+}
+
+Tiling make_tiling(const Box& b) {
+  Tiling t;
+  if (b.nz == 1) {
+    t.tz = 1; t.ty = 32; t.tx = 64;
+  } else {
+    t.tz = 8; t.ty = 8; t.tx = 32;
+  }
+  t.ntz = (b.nz + t.tz - 1) / t.tz;
+  t.nty = (b.ny + t.ty - 1) / t.ty;
+  t.ntx = (b.nx + t.tx - 1) / t.tx;
+  t.ntiles = (uint32_t)t.ntz * t.nty * t.ntx;
+  return t;
+}
+
+struct CompressLayout {
+  size_t prm, part, bins, mask, sub, stamp, counters, lookback, total;
+};
+
+CompressLayout compress_layout(const Shape& s, int dtype) {
+  const size_t k = dtype == 0 ? 4 : 8;
+  const uint64_t W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  Tiling t = make_tiling(s.box);
+  CompressLayout L;
+  size_t o = 0;
+  L.prm = o; o += align256(sizeof(Params));
+  L.part = o; o += align256(16 * kMinmaxBlocks);
+  L.bins = o; o += align256(s.n * k);
+  L.mask = o; o += align256(s.n * 2);
+  L.sub = o; o += align256(s.n * 4);
+  L.stamp = o; o += align256((size_t)t.ntiles * 4);
+  L.counters = o; o += align256(((size_t)kMaxSweeps + 2) * 4);
+  L.lookback = o; o += align256(nch * 8);
+  L.total = o;
+  return L;
+}
+
+size_t decompress_ws(const Shape& s, int dtype) {
+  const size_t k = dtype == 0 ? 4 : 8;
+  const uint64_t W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  return align256(sizeof(Params)) + align256(nch * 8);
+}
+
+int status_code(uint32_t st) {
+  if (st & ST_NONFINITE) return LOPC_E_NONFINITE;
+  if (st & ST_BOUND) return LOPC_E_BOUND;
+  if (st & ST_RANGE) return LOPC_E_RANGE;
+  if (st & ST_FORMAT) return LOPC_E_FORMAT;
+  if (st & ST_INTERNAL) return LOPC_E_INTERNAL;
+  if (st & ST_CAPACITY) return LOPC_E_CAPACITY;
+  return LOPC_OK;
+}
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    if ((expr) != hipSuccess) return LOPC_E_HIP; \
+  } while (0)
+
+uint64_t rd_u64(const uint8_t* p) {
+  uint64_t v = 0;
+  for (int i = 0; i < 8; ++i) v |= (uint64_t)p[i] << (8 * i);
+  return v;
+}
+uint32_t rd_u32(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) |
+         ((uint32_t)p[3] << 24);
+}
+double rd_f64(const uint8_t* p) {
+  uint64_t u = rd_u64(p);
+  double d;
+  std::memcpy(&d, &u, 8);
+  return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lopc_strerror(int status) {
+  switch (status) {
+    case LOPC_OK: return "ok";
+    case LOPC_E_ARG: return "invalid argument";
+    case LOPC_E_NONFINITE: return "field holds NaN or Inf";
+    case LOPC_E_BOUND: return "error bound must be finite and > 0 (NOA: field range > 0)";
+    case LOPC_E_RANGE: return "a bin number does not fit its integer type";
+    case LOPC_E_CAPACITY: return "output buffer too small";
+    case LOPC_E_FORMAT: return "malformed or corrupt stream";
+    case LOPC_E_HIP: return "HIP runtime error";
+    case LOPC_E_NOMEM: return "out of host memory";
+    case LOPC_E_INTERNAL: return "internal limit exceeded";
+    default: return "unknown status";
+  }
+}
+
+int lopc_ctx_create(int hip_device, lopc_ctx** out) {
+  if (!out) return LOPC_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 ||
+      hip_device >= count)
+    return LOPC_E_HIP;
+  HIP_TRY(hipSetDevice(hip_device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+  lopc_ctx* c = new (std::nothrow) lopc_ctx();
+  if (!c) return LOPC_E_NOMEM;
+  c->device = hip_device;
+  c->num_cu = prop.multiProcessorCount;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return LOPC_E_HIP;
+  }
+  c->h_prm = (Params*)p;
+  c->h_cnt = (uint32_t*)((uint8_t*)p + 2048);
+  *out = c;
+  return LOPC_OK;
+}
+
+void lopc_ctx_destroy(lopc_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
+  delete ctx;
+}
+
+int lopc_compress_bound(int dtype, int ndim, const int64_t* dims,
+                        size_t* bytes) {
+  if ((dtype != 0 && dtype != 1) || !bytes) return LOPC_E_ARG;
+  Shape s;
+  int st = make_shape(ndim, dims, &s);
+  if (st) return st;
+  const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  const uint64_t full = s.n / W, last = s.n - full * W;
+  uint64_t total = kHeaderBytes + 4 * nch +
+                   full * (kRecordHeaderBytes + 2 * W * k);
+  if (last) total += kRecordHeaderBytes + 2 * ((last + 63) / 64 * 64) * k;
+  *bytes = (size_t)total;
+  return LOPC_OK;
+}
+
+int lopc_workspace_size(lopc_ctx* ctx, int dtype, int ndim,
+                        const int64_t* dims, int op, size_t* bytes) {
+  (void)ctx;
+  if ((dtype != 0 && dtype != 1) || !bytes || (op != 0 && op != 1))
+    return LOPC_E_ARG;
+  Shape s;
+  int st = make_shape(ndim, dims, &s);
+  if (st) return st;
+  *bytes = op == 0 ? compress_layout(s, dtype).total : decompress_ws(s, dtype);
+  return LOPC_OK;
+}
+
+int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
+                  const int64_t* dims, double error_bound, int mode,
+                  void* d_stream, size_t stream_cap, size_t* h_stream_size,
+                  void* d_ws, size_t ws_bytes, void* stream,
+                  lopc_stats* h_stats) {
+  if (!ctx || !d_field || !d_stream || !h_stream_size || !d_ws)
+    return LOPC_E_ARG;
+  if ((dtype != 0 && dtype != 1) || (mode != 0 && mode != 1)) return LOPC_E_ARG;
+  Shape s;
+  int st = make_shape(ndim, dims, &s);
+  if (st) return st;
+  if (!std::isfinite(error_bound) || !(error_bound > 0)) return LOPC_E_BOUND;
+  CompressLayout L = compress_layout(s, dtype);
+  if (ws_bytes < L.total || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
+  hipStream_t hs = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  uint8_t* ws = (uint8_t*)d_ws;
+  Params* prm = (Params*)(ws + L.prm);
+  uint32_t* sub = (uint32_t*)(ws + L.sub);
+  uint32_t* stamp = (uint32_t*)(ws + L.stamp);
+  uint32_t* counters = (uint32_t*)(ws + L.counters);
+  uint64_t* lookback = (uint64_t*)(ws + L.lookback);
+  const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  Tiling tl = make_tiling(s.box);
+
+  HIP_TRY(hipMemsetAsync(prm, 0, sizeof(Params), hs));
+  HIP_TRY(hipMemsetAsync(sub, 0, s.n * 4, hs));
+  HIP_TRY(hipMemsetAsync(stamp, 0, (size_t)tl.ntiles * 4, hs));
+  HIP_TRY(hipMemsetAsync(counters, 0, ((size_t)kMaxSweeps + 2) * 4, hs));
+  HIP_TRY(hipMemsetAsync(lookback, 0, nch * 8, hs));
+
+  int nblocks = (int)std::min<uint64_t>(kMinmaxBlocks, (s.n + 2047) / 2048);
+  if (nblocks < 1) nblocks = 1;
+  if (mode == LOPC_EB_NOA)
+    HIP_TRY(launch_minmax(dtype, d_field, (uint32_t)s.n, (double*)(ws + L.part),
+                          nblocks, prm, hs));
+  HIP_TRY(launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
+                        nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
+                        s.d, hs));
+  HIP_TRY(launch_quant_mask(dtype, d_field, s.box, prm, ws + L.bins,
+                            (uint16_t*)(ws + L.mask), hs));
+
+  // repair: sweep the marked tiles until no tile is marked (Alg. 1 loop)
+  uint64_t sweeps = 0, active = tl.ntiles;
+  for (uint32_t sw = 0;; ++sw) {
+    HIP_TRY(launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
+                          counters, sw, hs));
+    ++sweeps;
+    HIP_TRY(hipMemcpyAsync(ctx->h_cnt, counters + sw + 2, 4, hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipMemcpyAsync(ctx->h_cnt + 1, counters, 4, hipMemcpyDeviceToHost, hs));
+    if (sw == 0)
+      HIP_TRY(hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4,
+                             hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipStreamSynchronize(hs));
+    if (ctx->h_cnt[1]) return LOPC_E_INTERNAL;
+    if (sw == 0) {
+      int code = status_code(ctx->h_prm->status);
+      if (code != LOPC_OK) {
+        *h_stream_size = 0;
+        return code;
+      }
+    }
+    const uint32_t next = ctx->h_cnt[0];
+    if (next == 0) break;
+    active += next;
+    if (sw + 1 >= kMaxSweeps) return LOPC_E_INTERNAL;
+  }
+
+  HIP_TRY(launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback, prm,
+                        (uint8_t*)d_stream, stream_cap, hs));
+  HIP_TRY(hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  const Params& hp = *ctx->h_prm;
+  *h_stream_size = (size_t)hp.stream_size;
+  if (h_stats) {
+    h_stats->eps = hp.eps;
+    h_stats->repair_sweeps = sweeps;
+    h_stats->active_tiles_total = active;
+    h_stats->bins_bytes = hp.bins_bytes;
+    h_stats->subbins_bytes = hp.sub_bytes;
+  }
+  return status_code(hp.status);
+}
+
+int lopc_stream_info(const void* h_header, size_t n, int* dtype, int* ndim,
+                     int64_t* dims, double* eps, size_t* field_bytes) {
+  const uint8_t* h = (const uint8_t*)h_header;
+  if (!h || n < kHeaderBytes) return LOPC_E_FORMAT;
+  if (rd_u32(h) != kMagic || (h[4] | (h[5] << 8)) != (int)kVersion)
+    return LOPC_E_FORMAT;
+  const int dt = h[6], nd = h[7];
+  if ((dt != 0 && dt != 1) || (nd != 2 && nd != 3)) return LOPC_E_FORMAT;
+  if (h[32] > 1 || rd_u32(h + 36) != kChunkBytes) return LOPC_E_FORMAT;
+  int64_t d[3];
+  uint64_t pts = 1;
+  for (int i = 0; i < 3; ++i) {
+    uint64_t v = rd_u64(h + 8 + 8 * i);
+    if (v < 1 || v > ((uint64_t)1 << 40)) return LOPC_E_FORMAT;
+    d[i] = (int64_t)v;
+    if (pts > ((uint64_t)1 << 48) / v) return LOPC_E_FORMAT;
+    pts *= v;
+  }
+  if (nd == 2 && d[2] != 1) return LOPC_E_FORMAT;
+  const double e = rd_f64(h + 48), v = rd_f64(h + 56);
+  if (!std::isfinite(e) || !(e > 0) || !std::isfinite(v) || !(v > 0))
+    return LOPC_E_FORMAT;
+  // inv must be the smallest binary64 with inv * eps >= 1
+  if (std::fma(v, e, -1.0) < 0 || std::fma(std::nextafter(v, 0.0), e, -1.0) >= 0)
+    return LOPC_E_FORMAT;
+  if (dtype) *dtype = dt;
+  if (ndim) *ndim = nd;
+  if (dims)
+    for (int i = 0; i < 3; ++i) dims[i] = d[i];
+  if (eps) *eps = e;
+  if (field_bytes) *field_bytes = (size_t)(pts * (dt == 0 ? 4 : 8));
+  return LOPC_OK;
+}
+
+int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
+                    void* d_field, size_t field_cap, void* d_ws,
+                    size_t ws_bytes, void* stream) {
+  if (!ctx || !d_stream || !d_field || !d_ws) return LOPC_E_ARG;
+  if (stream_size < kHeaderBytes) return LOPC_E_FORMAT;
+  hipStream_t hs = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  uint8_t* hh = (uint8_t*)ctx->h_prm;  // pinned staging for the header
+  HIP_TRY(hipMemcpyAsync(hh, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  uint8_t hdr[kHeaderBytes];
+  std::memcpy(hdr, hh, kHeaderBytes);
+  int dtype, ndim;
+  int64_t dims[3];
+  size_t fbytes;
+  int st = lopc_stream_info(hdr, kHeaderBytes, &dtype, &ndim, dims, nullptr, &fbytes);
+  if (st) return st;
+  Shape s;
+  if (make_shape(ndim, dims, &s) != LOPC_OK) return LOPC_E_ARG;  // > 2^32 points
+  const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  if (stream_size < kHeaderBytes + 4 * nch) return LOPC_E_FORMAT;
+  if (field_cap < fbytes) return LOPC_E_CAPACITY;
+  if (ws_bytes < decompress_ws(s, dtype) || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
+  uint8_t* ws = (uint8_t*)d_ws;
+  Params* prm = (Params*)ws;
+  uint64_t* offsets = (uint64_t*)(ws + align256(sizeof(Params)));
+  HIP_TRY(hipMemsetAsync(prm, 0, sizeof(Params), hs));
+  HIP_TRY(launch_offsets((const uint8_t*)d_stream, (uint32_t)nch,
+                         stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs));
+  HIP_TRY(launch_decode(dtype, (const uint8_t*)d_stream, (uint32_t)s.n, offsets,
+                        prm, d_field, hs));
+  HIP_TRY(hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4, hipMemcpyDeviceToHost, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  return status_code(ctx->h_prm->status);
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI library: it loads, exports every function that
+include/lopc.h declares, and its host-only calls (bounds, header parsing)
+agree with the oracle.  No compute call is made without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lopc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lopc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_2603_26968_amd import lopc
+    lib = ctypes.CDLL(lopc.LIB_PATH)
+    names = declared_functions()
+    assert "lopc_compress" in names and "lopc_decompress" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) <= set(lopc.EXPORTS) | set(names)
+
+
+def test_binding_names_mirror_the_abi():
+    import paper_2603_26968_amd as P
+    for name in ("lopc_compress", "lopc_decompress", "lopc_compress_bound",
+                 "lopc_workspace_size", "lopc_stream_info", "lopc_ctx_create"):
+        assert callable(getattr(P, name))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (512, 512), (70, 61), (256, 256, 256),
+                                   (1800, 3600), (3, 5, 7), (4096, 1), (1, 4097)])
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_compress_bound_matches_oracle(ref, shape, dt):
+    import paper_2603_26968_amd as P
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    assert P.lopc_compress_bound(shape, tdt) == ref.compress_bound(shape, dt)
+
+
+def test_stream_info_agrees_with_oracle(ref):
+    import paper_2603_26968_amd as P
+    rng = np.random.default_rng(0)
+    for dt in (np.float32, np.float64):
+        for shape in ((9, 13), (4, 5, 6)):
+            x = rng.standard_normal(shape).astype(dt)
+            s = ref.compress(x, 1e-2)
+            a = P.lopc_stream_info(s[:64])
+            b = ref.stream_info(s)
+            assert a["shape"] == b["shape"] and a["eps"] == b["eps"]
+            assert a["field_bytes"] == x.nbytes
+            bad = bytearray(s)
+            bad[56] ^= 1
+            with pytest.raises(P.LopcError):
+                P.lopc_stream_info(bytes(bad[:64]))
+
+
+def test_workspace_sizes():
+    import paper_2603_26968_amd as P
+    from paper_2603_26968_amd import lopc
+    for shape in ((512, 512), (256, 256, 256)):
+        c = lopc.lopc_workspace_size(None, shape, torch.float32, 0)
+        d = lopc.lopc_workspace_size(None, shape, torch.float32, 1)
+        n = int(np.prod(shape))
+        assert c >= n * 10 and 0 < d < n
+    with pytest.raises(P.LopcError):
+        lopc.lopc_workspace_size(None, (2 ** 20, 2 ** 13), torch.float32, 0)  # >= 2^32 points
