@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "lopc_internal.h"
+#include "lopc_numeric.h"
 
 namespace lopc {
 namespace {
@@ -32,28 +33,6 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
 
 __device__ __forceinline__ void set_status(Params* prm, uint32_t bits) {
   atomicOr(&prm->status, bits);
-}
-
-// ------------------------------------------------------------------ values
-// Order key: monotone in the value, -0 == +0, consecutive representable
-// values have consecutive keys.
-__device__ __forceinline__ int64_t key32(uint32_t u) {
-  return (u >> 31) ? -(int64_t)(u & 0x7fffffffu) : (int64_t)u;
-}
-__device__ __forceinline__ int64_t key64(uint64_t u) {
-  return (u >> 63) ? -(int64_t)(u & 0x7fffffffffffffffull) : (int64_t)u;
-}
-__device__ __forceinline__ uint32_t unkey32(int64_t k) {
-  return k >= 0 ? (uint32_t)k : (0x80000000u | (uint32_t)(-k));
-}
-__device__ __forceinline__ uint64_t unkey64(int64_t k) {
-  return k >= 0 ? (uint64_t)k : (0x8000000000000000ull | (uint64_t)(-k));
-}
-__device__ __forceinline__ bool finite32(uint32_t u) {
-  return (u & 0x7f800000u) != 0x7f800000u;
-}
-__device__ __forceinline__ bool finite64(uint64_t u) {
-  return (u & 0x7ff0000000000000ull) != 0x7ff0000000000000ull;
 }
 
 template <int K> struct Traits;
@@ -79,35 +58,6 @@ template <> struct Traits<8> {
   __device__ static bool finite(Raw u) { return finite64(u); }
   __device__ static double to_double(Raw u) { return __longlong_as_double((long long)u); }
 };
-
-// Quantizer (Sec. IV-A): nearest integer to the exact real y*inv, ties to
-// even, saturated to +-(2^62 + 1).  The rounded product p and the exact
-// residual r = fma(y, inv, -p) locate the real product exactly: rounding p
-// can only cross a half-integer h if p == h, and then the sign of r decides.
-__device__ __forceinline__ int64_t q_bin(double y, double inv) {
-  const double two52 = 4503599627370496.0;
-  const double two62 = 4611686018427387904.0;
-  const int64_t sat = 4611686018427387905ll;
-  double p = y * inv;
-  if (!(fabs(p) <= two62)) return p < 0 ? -sat : sat;
-  double r = fma(y, inv, -p);
-  int64_t q;
-  if (fabs(p) < two52) {
-    double fl = floor(p);
-    double fr = p - fl;
-    q = (int64_t)fl;
-    bool up = fr > 0.5 || (fr == 0.5 && (r > 0.0 || (r == 0.0 && (q & 1))));
-    q += up ? 1 : 0;
-  } else {
-    // p is an integer; the fraction of the real product is in r
-    double rf = floor(r);
-    double rr = r - rf;
-    q = (int64_t)p + (int64_t)rf;
-    bool up = rr > 0.5 || (rr == 0.5 && (q & 1));
-    q += up ? 1 : 0;
-  }
-  return q > sat ? sat : (q < -sat ? -sat : q);
-}
 
 // ------------------------------------------------------------------ stencil
 // Edges of the Freudenthal triangulation: +-d for nonzero d in {0,1}^3,

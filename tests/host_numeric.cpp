@@ -1,0 +1,19 @@
+// Host harness for the library's bit-exact scalar arithmetic
+// (paper_2603_26968_amd/csrc/lopc_numeric.h, compiled here for the CPU).
+// stdin: lines "<y bits hex> <inv bits hex>"; stdout: the bin, one per line.
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../paper_2603_26968_amd/csrc/lopc_numeric.h"
+
+int main() {
+  unsigned long long yb, ib;
+  while (std::scanf("%llx %llx", &yb, &ib) == 2) {
+    double y, inv;
+    std::memcpy(&y, &yb, 8);
+    std::memcpy(&inv, &ib, 8);
+    std::printf("%lld\n", (long long)lopc::q_bin(y, inv));
+  }
+  return 0;
+}

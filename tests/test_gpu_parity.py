@@ -44,7 +44,14 @@ def same_bits(a, b):
 
 def check(P, ref, x, eb, mode="noa", name=""):
     _say(name, x.shape, x.dtype, eb, mode)
-    want = ref.compress(x, eb, ref.NOA if mode == "noa" else ref.ABS)
+    try:
+        want = ref.compress(x, eb, ref.NOA if mode == "noa" else ref.ABS)
+    except ref.OracleError as e:
+        # the GPU must reject the same input with the same status
+        with pytest.raises(P.LopcError) as g:
+            gpu_compress(P, x, eb, mode)
+        assert g.value.code == e.code, (name, g.value.code, e.code)
+        return
     got = gpu_compress(P, x, eb, mode)
     if got != want:
         # locate the first differing byte for the report
@@ -52,7 +59,14 @@ def check(P, ref, x, eb, mode="noa", name=""):
         d = next((i for i in range(n) if got[i] != want[i]), n)
         pytest.fail(f"{name}: stream differs at byte {d} (gpu {len(got)} B, oracle {len(want)} B)")
     y = gpu_decompress(P, want)
-    assert same_bits(y, ref.decompress(want)), f"{name}: reconstruction differs"
+    z = ref.decompress(want)
+    if not same_bits(y, z):
+        b, sb = ref.decode_codes(want)
+        u = np.uint32 if x.dtype == np.float32 else np.uint64
+        bad = np.flatnonzero(y.view(u).ravel() != z.view(u).ravel())
+        rows = [f"i={i} bin={b.flat[i]} sub={sb.flat[i]} gpu={y.view(u).flat[i]:#x} "
+                f"oracle={z.view(u).flat[i]:#x}" for i in bad[:6]]
+        pytest.fail(f"{name}: {bad.size} reconstructed values differ\n" + "\n".join(rows))
 
 
 SMALL = [
@@ -201,3 +215,26 @@ def test_smooth2d_full_size(P, ref):
 
 def test_fronts2d_full_size(P, ref):
     check(P, ref, synth.fronts_field(), 1e-3, "noa", "fronts2d 1800x3600")
+
+
+def test_adversarial_bin_edges(P, ref):
+    """Values one to three ulps around the real bin edges (k + 1/2) * eps, both
+    signs, including bin 0 and large bins: the quantizer and the bin floor
+    must agree with the oracle's exact arithmetic."""
+    import math
+    for dt, eps in [(np.float64, 0.1), (np.float64, 1 / 3), (np.float32, 0.1),
+                    (np.float32, 0.007), (np.float64, 1e-7)]:
+        _, inv = ref.error_params(np.array([[0.0, 1.0]]), eps, ref.ABS)
+        vals = []
+        for k in (-4, -3, -2, -1, 0, 1, 2, 3, 50, -77, 12345):
+            for sgn in (1.0, -1.0):
+                c = sgn * (k + 0.5) / inv
+                y = dt(c)
+                for _ in range(3):
+                    y = np.nextafter(y, dt(-np.inf))
+                for _ in range(7):
+                    vals.append(y)
+                    y = np.nextafter(y, dt(np.inf))
+        x = np.array(vals, dt)
+        x = np.resize(x, (len(x) // 7, 7))
+        check(P, ref, x, eps, "abs", f"edges {dt.__name__} eps={eps}")
