@@ -1,0 +1,173 @@
+#!/usr/bin/env python
+"""Benchmark of the LOPC hot path on one MI355X.
+
+One step = compress + decompress (every step of the path: NOA range,
+quantize, order mask, repair sweeps to the fixed point, chunk encoders and
+stream assembly, decoders and reconstruction) of the 3D float32 256^3
+turbulence field (power-law GRF, P(k) ~ k^-3, + 1% noise, normalised to
+[0, 1]) at a NOA bound of 1e-3 (bit-exact).  The field is resident in HBM
+before the timed region starts.
+
+value = uncompressed bytes / (compress + decompress time), GB/s (1e9 B/s).
+
+Prints one JSON line.  Usage:
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--eb 1e-3]
+                  [--no-cpu-baseline] [--all-eb]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, public spec
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eb", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--all-eb", action="store_true",
+                    help="also time the 1e-2 and 1e-4 bounds of the same field")
+    return ap.parse_args()
+
+
+def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing):
+    import torch
+    stream_buf, ws_c, ws_d, y = bufs
+    lopc.lopc_ctx_set_timing(ctx, timing)
+    phase = {k: 0.0 for k in lopc.PHASES}
+    stats = None
+    s = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s, stats = P.compress(x, eb, "noa", stats=True, out=stream_buf, workspace=ws_c)
+        if timing:
+            ph = lopc.lopc_ctx_last_timings(ctx)
+        P.decompress(s, out=y, workspace=ws_d)
+        if timing:
+            ph2 = lopc.lopc_ctx_last_timings(ctx)
+            for k in ("range", "quant", "repair", "encode"):
+                phase[k] += ph[k]
+            for k in ("offsets", "decode"):
+                phase[k] += ph2[k]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lopc.lopc_ctx_set_timing(ctx, False)
+    return (t1 - t0), {k: v / max(steps, 1) for k, v in phase.items()}, stats, s
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                          "described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2603_26968_amd as P
+    from paper_2603_26968_amd import lopc, synth
+
+    dev = torch.device("cuda:0")
+    xh = synth.turbulence_field(seed=args.seed)
+    n, k = xh.size, xh.itemsize
+    x = torch.from_numpy(xh).to(dev)
+    ctx = lopc.context(0)
+    cap = lopc.lopc_compress_bound(x.shape, x.dtype)
+    bufs = (torch.empty(cap, dtype=torch.uint8, device=dev),
+            torch.empty(lopc.lopc_workspace_size(ctx, x.shape, x.dtype, 0), dtype=torch.uint8, device=dev),
+            torch.empty(lopc.lopc_workspace_size(ctx, x.shape, x.dtype, 1), dtype=torch.uint8, device=dev),
+            torch.empty_like(x))
+
+    run_steps(P, lopc, ctx, x, args.eb, args.warmup, bufs, False)
+    # timed region: K steps, library-recorded HIP events on the same stream
+    dt, phase, stats, s = run_steps(P, lopc, ctx, x, args.eb, args.steps, bufs, True)
+    S = int(s.numel())
+    ms_step = dt / args.steps * 1e3
+    t_c = sum(phase[p] for p in ("range", "quant", "repair", "encode"))
+    t_d = phase["offsets"] + phase["decode"]
+    value = n * k / (dt / args.steps) / 1e9
+
+    # the decoder kernel: algorithmic bytes = stream bytes read + field written
+    dec_bytes = S + n * k
+    dec_gbps = dec_bytes / (phase["decode"] * 1e-3) / 1e9 if phase["decode"] else 0.0
+    # the encoder kernel: bins + subbins read, stream written
+    kb = 4 if k == 4 else 8
+    enc_bytes = n * kb + n * 4 + S
+    enc_gbps = enc_bytes / (phase["encode"] * 1e-3) / 1e9 if phase["encode"] else 0.0
+    kernels = {
+        "decode": {"ms": phase["decode"], "bytes": dec_bytes, "GBps": dec_gbps},
+        "encode": {"ms": phase["encode"], "bytes": enc_bytes, "GBps": enc_gbps},
+    }
+    dom = max(kernels, key=lambda q: kernels[q]["ms"])
+    roof = {"bound": "hbm", "kernel": "k_decode" if dom == "decode" else "k_encode",
+            "achieved": round(kernels[dom]["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(kernels[dom]["GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": kernels[dom]["bytes"]}
+
+    extra = {}
+    if args.all_eb:
+        for eb in (1e-2, 1e-4):
+            dte, ph, st, se = run_steps(P, lopc, ctx, x, eb, 5, bufs, True)
+            extra[str(eb)] = {
+                "GBps_roundtrip": round(n * k / (dte / 5) / 1e9, 2),
+                "compress_GBps": round(n * k / (sum(ph[p] for p in ("range", "quant", "repair", "encode")) * 1e-3) / 1e9, 2),
+                "decompress_GBps": round(n * k / ((ph["offsets"] + ph["decode"]) * 1e-3) / 1e9, 2),
+                "CR": round(n * k / se.numel(), 3), "repair_sweeps": int(st["repair_sweeps"])}
+
+    out = {
+        "metric": "LOPC compress+decompress GB/s (uncompressed bytes / round-trip time), bit-exact",
+        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "turb3d: 3D float32 256^3 GRF P(k)~k^-3 + 1% noise, [0,1]; "
+                               f"NOA eb {args.eb:g}; compress + decompress",
+                   "shape": list(xh.shape), "eb": args.eb, "mode": "NOA",
+                   "arithmetic": "binary64 quantizer/decoder, 32-bit integer repair and codecs"},
+        "compress_GBps": round(n * k / (t_c * 1e-3) / 1e9, 2) if t_c else None,
+        "decompress_GBps": round(n * k / (t_d * 1e-3) / 1e9, 2) if t_d else None,
+        "phase_ms": {q: round(v, 4) for q, v in phase.items()},
+        "CR": round(n * k / S, 3), "stream_bytes": S,
+        "repair_sweeps": int(stats["repair_sweeps"]),
+        "active_tiles_total": int(stats["active_tiles_total"]),
+        "bins_bytes": int(stats["bins_bytes"]), "subbins_bytes": int(stats["subbins_bytes"]),
+        "kernels": {q: {"ms": round(v["ms"], 4), "GBps": round(v["GBps"], 1)} for q, v in kernels.items()},
+        "roofline": roof,
+    }
+    if extra:
+        out["other_eb"] = extra
+
+    if not args.no_cpu_baseline:
+        import oracle
+        if not os.path.exists(os.path.join(ROOT, "oracle", "liblopc_ref.so")):
+            oracle.build()
+        t0 = time.perf_counter()
+        ref_stream = oracle.compress(xh, args.eb, oracle.NOA)
+        ref_y = oracle.decompress(ref_stream)
+        t_cpu = time.perf_counter() - t0
+        gpu_stream = s.cpu().numpy().tobytes()
+        out["cpu_baseline"] = {"value": round(n * k / t_cpu / 1e9, 5), "unit": "GB/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "one compress + decompress of the same 256^3 field "
+                                         f"({n * k / 1e6:.0f} MB), single-threaded C oracle, "
+                                         f"{t_cpu:.1f} s"}
+        yg = bufs[3].cpu().numpy()
+        out["parity"] = {"stream_identical": gpu_stream == ref_stream,
+                         "reconstruction_identical": bool(np.array_equal(yg.view(np.uint32), ref_y.view(np.uint32)))}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

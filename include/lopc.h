@@ -116,6 +116,29 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
 /* Static text for a status code. */
 const char* lopc_strerror(int status);
 
+/* Phase timing (for benchmarks).  When enabled, each compress/decompress call
+ * records HIP events on its stream between its phases and, after its final
+ * synchronisation, stores the elapsed milliseconds of each phase:
+ *   LOPC_PHASE_RANGE    compress: NOA min/max + error parameters
+ *   LOPC_PHASE_QUANT    compress: quantize + order mask
+ *   LOPC_PHASE_REPAIR   compress: all repair sweeps (host waits included)
+ *   LOPC_PHASE_ENCODE   compress: chunk encoder + stream assembly
+ *   LOPC_PHASE_OFFSETS  decompress: record offsets
+ *   LOPC_PHASE_DECODE   decompress: chunk decoder + reconstruction
+ * lopc_ctx_last_timings copies min(n, LOPC_PHASES) values of the most recent
+ * call of each kind (unset phases are 0) and returns LOPC_OK. */
+enum {
+  LOPC_PHASE_RANGE = 0,
+  LOPC_PHASE_QUANT = 1,
+  LOPC_PHASE_REPAIR = 2,
+  LOPC_PHASE_ENCODE = 3,
+  LOPC_PHASE_OFFSETS = 4,
+  LOPC_PHASE_DECODE = 5,
+  LOPC_PHASES = 6
+};
+int lopc_ctx_set_timing(lopc_ctx* ctx, int enable);
+int lopc_ctx_last_timings(lopc_ctx* ctx, double* h_ms, int n);
+
 #ifdef __cplusplus
 }
 #endif

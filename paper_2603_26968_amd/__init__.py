@@ -13,7 +13,7 @@ _BINDING = (
     "LopcError", "compress", "decompress", "context", "lopc_compress_bound",
     "lopc_stream_info", "lopc_workspace_size", "lopc_compress", "lopc_decompress",
     "lopc_ctx_create", "lopc_ctx_destroy", "LOPC_EB_ABS", "LOPC_EB_NOA", "LOPC_F32",
-    "LOPC_F64", "Stats",
+    "LOPC_F64", "Stats", "lopc_ctx_set_timing", "lopc_ctx_last_timings",
 )
 
 

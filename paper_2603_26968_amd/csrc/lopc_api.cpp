@@ -19,6 +19,10 @@ struct lopc_ctx {
   // pinned host slots for small device-to-host reads
   Params* h_prm;
   uint32_t* h_cnt;
+  // phase timing
+  int timing;
+  hipEvent_t ev[8];
+  double ms[LOPC_PHASES];
 };
 
 namespace {
@@ -119,6 +123,17 @@ int status_code(uint32_t st) {
     if ((expr) != hipSuccess) return LOPC_E_HIP; \
   } while (0)
 
+// event i of the current call (no-op unless timing is on)
+hipError_t mark(lopc_ctx* c, int i, hipStream_t s) {
+  return c->timing ? hipEventRecord(c->ev[i], s) : hipSuccess;
+}
+// elapsed ms between events a and b (after the stream has synchronised)
+double span(lopc_ctx* c, int a, int b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
+  return (double)ms;
+}
+
 uint64_t rd_u64(const uint8_t* p) {
   uint64_t v = 0;
   for (int i = 0; i < 8; ++i) v |= (uint64_t)p[i] << (8 * i);
@@ -176,6 +191,9 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   }
   c->h_prm = (Params*)p;
   c->h_cnt = (uint32_t*)((uint8_t*)p + 2048);
+  c->timing = 0;
+  for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
+  for (int i = 0; i < LOPC_PHASES; ++i) c->ms[i] = 0.0;
   *out = c;
   return LOPC_OK;
 }
@@ -183,7 +201,25 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
 void lopc_ctx_destroy(lopc_ctx* ctx) {
   if (!ctx) return;
   if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
+  for (int i = 0; i < 8; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   delete ctx;
+}
+
+int lopc_ctx_set_timing(lopc_ctx* ctx, int enable) {
+  if (!ctx) return LOPC_E_ARG;
+  if (enable && !ctx->ev[0]) {
+    HIP_TRY(hipSetDevice(ctx->device));
+    for (int i = 0; i < 8; ++i) HIP_TRY(hipEventCreate(&ctx->ev[i]));
+  }
+  ctx->timing = enable ? 1 : 0;
+  return LOPC_OK;
+}
+
+int lopc_ctx_last_timings(lopc_ctx* ctx, double* h_ms, int n) {
+  if (!ctx || !h_ms || n < 0) return LOPC_E_ARG;
+  for (int i = 0; i < n && i < LOPC_PHASES; ++i) h_ms[i] = ctx->ms[i];
+  return LOPC_OK;
 }
 
 int lopc_compress_bound(int dtype, int ndim, const int64_t* dims,
@@ -241,6 +277,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   const uint64_t nch = (s.n + W - 1) / W;
   Tiling tl = make_tiling(s.box);
 
+  HIP_TRY(mark(ctx, 0, hs));
   HIP_TRY(hipMemsetAsync(prm, 0, sizeof(Params), hs));
   HIP_TRY(hipMemsetAsync(sub, 0, s.n * 4, hs));
   HIP_TRY(hipMemsetAsync(stamp, 0, (size_t)tl.ntiles * 4, hs));
@@ -255,8 +292,10 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   HIP_TRY(launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
                         nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
                         s.d, hs));
+  HIP_TRY(mark(ctx, 1, hs));
   HIP_TRY(launch_quant_mask(dtype, d_field, s.box, prm, ws + L.bins,
                             (uint16_t*)(ws + L.mask), hs));
+  HIP_TRY(mark(ctx, 2, hs));
 
   // repair: sweep the marked tiles until no tile is marked (Alg. 1 loop)
   uint64_t sweeps = 0, active = tl.ntiles;
@@ -284,10 +323,18 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     if (sw + 1 >= kMaxSweeps) return LOPC_E_INTERNAL;
   }
 
+  HIP_TRY(mark(ctx, 3, hs));
   HIP_TRY(launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback, prm,
                         (uint8_t*)d_stream, stream_cap, hs));
+  HIP_TRY(mark(ctx, 4, hs));
   HIP_TRY(hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
   HIP_TRY(hipStreamSynchronize(hs));
+  if (ctx->timing) {
+    ctx->ms[LOPC_PHASE_RANGE] = span(ctx, 0, 1);
+    ctx->ms[LOPC_PHASE_QUANT] = span(ctx, 1, 2);
+    ctx->ms[LOPC_PHASE_REPAIR] = span(ctx, 2, 3);
+    ctx->ms[LOPC_PHASE_ENCODE] = span(ctx, 3, 4);
+  }
   const Params& hp = *ctx->h_prm;
   *h_stream_size = (size_t)hp.stream_size;
   if (h_stats) {
@@ -362,12 +409,19 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
   Params* prm = (Params*)ws;
   uint64_t* offsets = (uint64_t*)(ws + align256(sizeof(Params)));
   HIP_TRY(hipMemsetAsync(prm, 0, sizeof(Params), hs));
+  HIP_TRY(mark(ctx, 5, hs));
   HIP_TRY(launch_offsets((const uint8_t*)d_stream, (uint32_t)nch,
                          stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs));
+  HIP_TRY(mark(ctx, 6, hs));
   HIP_TRY(launch_decode(dtype, (const uint8_t*)d_stream, (uint32_t)s.n, offsets,
                         prm, d_field, hs));
+  HIP_TRY(mark(ctx, 7, hs));
   HIP_TRY(hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4, hipMemcpyDeviceToHost, hs));
   HIP_TRY(hipStreamSynchronize(hs));
+  if (ctx->timing) {
+    ctx->ms[LOPC_PHASE_OFFSETS] = span(ctx, 5, 6);
+    ctx->ms[LOPC_PHASE_DECODE] = span(ctx, 6, 7);
+  }
   return status_code(ctx->h_prm->status);
 }
 

@@ -28,7 +28,9 @@ HEADER_BYTES = 64
 
 EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_workspace_size", "lopc_compress", "lopc_stream_info",
-           "lopc_decompress", "lopc_strerror")
+           "lopc_decompress", "lopc_strerror", "lopc_ctx_set_timing",
+           "lopc_ctx_last_timings")
+PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
 
 class LopcError(RuntimeError):
@@ -81,6 +83,10 @@ def load() -> ctypes.CDLL:
     L.lopc_decompress.restype = ci
     L.lopc_strerror.argtypes = [ci]
     L.lopc_strerror.restype = ctypes.c_char_p
+    L.lopc_ctx_set_timing.argtypes = [vp, ci]
+    L.lopc_ctx_set_timing.restype = ci
+    L.lopc_ctx_last_timings.argtypes = [vp, ctypes.POINTER(cd), ci]
+    L.lopc_ctx_last_timings.restype = ci
     _lib = L
     return L
 
@@ -96,6 +102,21 @@ def lopc_ctx_create(device: int) -> int:
 
 def lopc_ctx_destroy(ctx: int) -> None:
     load().lopc_ctx_destroy(ctx)
+
+
+def lopc_ctx_set_timing(ctx: int, enable: bool) -> None:
+    st = load().lopc_ctx_set_timing(ctx, 1 if enable else 0)
+    if st:
+        raise LopcError(st, "lopc_ctx_set_timing")
+
+
+def lopc_ctx_last_timings(ctx: int) -> dict:
+    """Milliseconds of each phase of the last compress / decompress call."""
+    buf = (ctypes.c_double * len(PHASES))()
+    st = load().lopc_ctx_last_timings(ctx, buf, len(PHASES))
+    if st:
+        raise LopcError(st, "lopc_ctx_last_timings")
+    return {name: buf[i] for i, name in enumerate(PHASES)}
 
 
 def _dims(shape):
