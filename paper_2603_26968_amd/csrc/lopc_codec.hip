@@ -1,0 +1,762 @@
+// lopc_codec.hip -- chunk encoder and decoder of liblopc.so (gfx950).
+//
+// Lossless stages of Sec. III-B / Sec. IV-C on 16 kB chunks: bins go through
+// DIFFNB_K BIT_K RZE_1, subbins through BIT_K RZE_K RZE_1.  The BIT_K output
+// of a chunk of m words is handled as 64-bit "units": unit u = j*G + g (G =
+// m/64) holds bit j of the 64 words of group g, i.e. exactly one __ballot.
+// Every RZE variant then works unit-parallel: a unit carries 8 (RZE_1), 2
+// (RZE_4) or 1 (RZE_8) bitmap bits, so bitmaps, counts and payload offsets
+// come from wave scans over units instead of per-byte work.
+//
+// Chunk offsets in the stream come from a decoupled look-back over a
+// ticket-ordered chunk queue (a workgroup only waits for chunks that started
+// before it).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "lopc_device.h"
+
+namespace lopc {
+namespace {
+
+constexpr uint32_t kMaxUnits = kChunkBytes / 8;  // 2048
+constexpr uint32_t kMaxRounds = kMaxUnits / 64;  // 32
+
+// Scratch of the unit-parallel RZE stages.
+struct Scratch {
+  uint8_t lv0[kMaxUnits + 16] __attribute__((aligned(16)));  // level-1 bitmap
+  uint8_t lv1[256 + 16] __attribute__((aligned(16)));
+  uint8_t lv2[32 + 16] __attribute__((aligned(16)));
+  uint8_t lv3[16] __attribute__((aligned(16)));
+  uint8_t kp0[kMaxUnits];  // kept bytes of the level-1 bitmap
+  uint8_t kp1[256];
+  uint8_t kp2[32];
+  uint16_t off[kMaxUnits];  // per-unit exclusive offset within its round
+  uint32_t rpre[kMaxRounds + 1];  // per-round totals, then exclusive prefix
+  uint32_t scan[kWaves + 1];
+  uint32_t nkept[4];
+  uint64_t orv[kWaves];
+  uint64_t scan64[kWaves + 1];
+  uint64_t planes;
+};
+
+__device__ __forceinline__ uint8_t* lvl(Scratch& sc, int l) {
+  return l == 0 ? sc.lv0 : (l == 1 ? sc.lv1 : (l == 2 ? sc.lv2 : sc.lv3));
+}
+__device__ __forceinline__ uint8_t* kept(Scratch& sc, int l) {
+  return l == 0 ? sc.kp0 : (l == 1 ? sc.kp1 : sc.kp2);
+}
+
+// bitmap sizes of the RZE levels for `items` items; returns the top level
+__device__ __forceinline__ int rze_levels(uint32_t items, uint32_t* sz) {
+  int top = 0;
+  sz[0] = (items + 7) / 8;
+  while (sz[top] > 8) {
+    sz[top + 1] = (sz[top] + 7) / 8;
+    ++top;
+  }
+  return top;
+}
+
+// bit b (0..7) of the result: byte b of v is nonzero
+__device__ __forceinline__ uint32_t nonzero_bytes(uint64_t v) {
+  uint64_t t = v | (v >> 4);
+  t |= t >> 2;
+  t |= t >> 1;
+  t &= 0x0101010101010101ull;
+  return (uint32_t)((t * 0x0102040810204080ull) >> 56);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t c) {
+  uint32_t x = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane() >= d) x += y;
+  }
+  return x;
+}
+
+// Turn the per-round totals sc.rpre[0..rounds) into exclusive prefixes and
+// return the grand total.  Call between barriers.
+__device__ __forceinline__ uint32_t round_prefix(Scratch& sc, uint32_t rounds) {
+  if (threadIdx.x < 64) {
+    uint32_t c = threadIdx.x < rounds ? sc.rpre[threadIdx.x] : 0u;
+    uint32_t inc = wave_incl_scan(c);
+    if (threadIdx.x < rounds) sc.rpre[threadIdx.x] = inc - c;
+    if (threadIdx.x == 63) sc.rpre[kMaxRounds] = inc;
+  }
+  __syncthreads();
+  return sc.rpre[kMaxRounds];
+}
+
+// One level of the bitmap recursion: bit i of nxt = cur[i] differs from the
+// byte before it (0 before the first); the differing bytes go to kp.
+__device__ void level_encode(const uint8_t* cur, uint32_t n, uint8_t* nxt,
+                             uint8_t* kp, uint32_t& nk, Scratch& sc) {
+  const uint32_t nb = (n + 7) / 8;  // <= 256
+  uint32_t bits = 0;
+  if (threadIdx.x < nb) {
+    uint32_t i0 = threadIdx.x * 8;
+    uint8_t prev = i0 ? cur[i0 - 1] : (uint8_t)0;
+    for (uint32_t b = 0; b < 8 && i0 + b < n; ++b) {
+      uint8_t v = cur[i0 + b];
+      bits |= (uint32_t)(v != prev) << b;
+      prev = v;
+    }
+    nxt[threadIdx.x] = (uint8_t)bits;
+  }
+  uint32_t tot;
+  uint32_t e = block_excl_scan<uint32_t>((uint32_t)__popc(bits), sc.scan, tot);
+  if (threadIdx.x < nb) {
+    uint32_t i0 = threadIdx.x * 8;
+    for (uint32_t b = 0; b < 8; ++b)
+      if ((bits >> b) & 1) kp[e++] = cur[i0 + b];
+  }
+  nk = tot;
+  __syncthreads();
+}
+
+// Inverse of level_encode: child byte i = the last kept byte at or before i
+// (0 if none), reading the kept bytes from in[pos...).  Returns false if they
+// run past in_len.
+__device__ bool level_decode(const uint8_t* par, uint32_t n, const uint8_t* in,
+                             uint32_t& pos, uint32_t in_len, uint8_t* child,
+                             Scratch& sc) {
+  const uint32_t np = (n + 7) / 8;
+  uint32_t pb = 0;
+  if (threadIdx.x < np) {
+    pb = par[threadIdx.x];
+    uint32_t valid = n - threadIdx.x * 8;
+    if (valid < 8) pb &= (1u << valid) - 1;
+  }
+  uint32_t tot;
+  uint32_t e = block_excl_scan<uint32_t>((uint32_t)__popc(pb), sc.scan, tot);
+  if (pos + tot > in_len) return false;
+  if (threadIdx.x < np + 1) {
+    uint32_t i0 = threadIdx.x * 8;
+    for (uint32_t b = 0; b < 8; ++b) {
+      uint8_t v = 0;
+      if (i0 + b < n) {
+        if ((pb >> b) & 1) ++e;
+        v = e ? in[pos + e - 1] : (uint8_t)0;
+      }
+      child[i0 + b] = v;  // bytes past n are zero padding
+    }
+  }
+  pos += tot;
+  __syncthreads();
+  return true;
+}
+
+// RZE_W over the first `len` bytes of the unit array U (zero beyond len)
+// into out.  Returns the output length; pt = 1 when the input is stored
+// verbatim because the output would not be smaller.
+template <int W>
+__device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
+                               Scratch& sc, int& pt) {
+  const uint32_t NU = (len + 7) / 8;
+  const uint32_t items = len / W;
+  const uint32_t rounds = (NU + 63) / 64;
+  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+    const uint32_t u = r * 64 + lane();
+    const uint64_t v = u < NU ? U[u] : 0ull;
+    uint32_t mi, ci;
+    if (W == 1) {
+      mi = nonzero_bytes(v);
+      ci = __popc(mi);
+      if (u < NU) sc.lv0[u] = (uint8_t)mi;
+    } else if (W == 4) {
+      mi = ((uint32_t)v != 0u) | ((uint32_t)((v >> 32) != 0ull) << 1);
+      ci = __popc(mi);
+      uint32_t b = mi | (__shfl_down(mi, 1, 64) << 2) | (__shfl_down(mi, 2, 64) << 4) |
+                   (__shfl_down(mi, 3, 64) << 6);
+      if ((lane() & 3) == 0 && u < NU) sc.lv0[u / 4] = (uint8_t)b;
+    } else {
+      mi = v != 0ull;
+      ci = mi;
+      uint64_t m = __ballot(mi);
+      if (lane() == 0) *(uint64_t*)(sc.lv0 + r * 8) = m;
+    }
+    const uint32_t inc = wave_incl_scan(ci);
+    if (u < NU) sc.off[u] = (uint16_t)(inc - ci);
+    if (lane() == 63) sc.rpre[r] = inc;
+  }
+  __syncthreads();
+  const uint32_t npay = round_prefix(sc, rounds);
+  uint32_t sz[8];
+  const int top = rze_levels(items, sz);
+  for (int l = 0; l < top; ++l) level_encode(lvl(sc, l), sz[l], lvl(sc, l + 1), kept(sc, l), sc.nkept[l], sc);
+  uint32_t out_len = sz[top] + npay * W;
+  for (int l = 0; l < top; ++l) out_len += sc.nkept[l];
+  if (out_len >= len) {
+    const uint8_t* ub = (const uint8_t*)U;
+    for (uint32_t i = threadIdx.x; i < len; i += kThreads) out[i] = ub[i];
+    pt = 1;
+    __syncthreads();
+    return len;
+  }
+  pt = 0;
+  uint32_t pos = 0;
+  {
+    const uint8_t* tb = lvl(sc, top);
+    for (uint32_t i = threadIdx.x; i < sz[top]; i += kThreads) out[i] = tb[i];
+    pos = sz[top];
+  }
+  for (int l = top - 1; l >= 0; --l) {
+    const uint8_t* kb = kept(sc, l);
+    for (uint32_t i = threadIdx.x; i < sc.nkept[l]; i += kThreads) out[pos + i] = kb[i];
+    pos += sc.nkept[l];
+  }
+  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+    const uint32_t u = r * 64 + lane();
+    if (u >= NU) continue;
+    const uint64_t v = U[u];
+    uint32_t d = pos + W * (sc.rpre[r] + sc.off[u]);
+    if (W == 1) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        uint8_t x = (uint8_t)(v >> (8 * b));
+        if (x) out[d++] = x;
+      }
+    } else if (W == 4) {
+      uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+      if (lo) {
+        put_bytes(out + d, lo, 4);
+        d += 4;
+      }
+      if (hi) put_bytes(out + d, hi, 4);
+    } else {
+      if (v) put_bytes(out + d, v, 8);
+    }
+  }
+  __syncthreads();
+  return out_len;
+}
+
+// Inverse of rze_encode: in[0, in_len) -> the first `len` bytes of U (units
+// rounded up; bytes past len are zero).  Returns false on malformed input;
+// never reads outside [in, in + in_len).
+template <int W>
+__device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
+                           uint64_t* U, Scratch& sc) {
+  const uint32_t NU = (len + 7) / 8;
+  const uint32_t items = len / W;
+  const uint32_t rounds = (NU + 63) / 64;
+  uint32_t sz[8];
+  const int top = rze_levels(items, sz);
+  if (sz[top] > in_len) return false;
+  {
+    uint8_t* tb = lvl(sc, top);
+    if (threadIdx.x < 16) tb[threadIdx.x] = threadIdx.x < sz[top] ? in[threadIdx.x] : (uint8_t)0;
+  }
+  __syncthreads();
+  uint32_t pos = sz[top];
+  for (int l = top - 1; l >= 0; --l)
+    if (!level_decode(lvl(sc, l + 1), sz[l], in, pos, in_len, lvl(sc, l), sc)) return false;
+  // lv0 holds `items` bitmap bits
+  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+    const uint32_t u = r * 64 + lane();
+    uint32_t mi = 0;
+    if (u < NU) {
+      if (W == 1) {
+        mi = sc.lv0[u];
+        uint32_t valid = items - u * 8;
+        if (valid < 8) mi &= (1u << valid) - 1;
+      } else if (W == 4) {
+        mi = (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
+      } else {
+        mi = (sc.lv0[u / 8] >> (u % 8)) & 1u;
+      }
+    }
+    const uint32_t ci = __popc(mi);
+    const uint32_t inc = wave_incl_scan(ci);
+    if (u < NU) sc.off[u] = (uint16_t)(inc - ci);
+    if (lane() == 63) sc.rpre[r] = inc;
+  }
+  __syncthreads();
+  const uint32_t npay = round_prefix(sc, rounds);
+  if (pos + npay * W != in_len) return false;
+  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+    const uint32_t u = r * 64 + lane();
+    if (u >= NU) continue;
+    uint32_t mi;
+    if (W == 1) {
+      mi = sc.lv0[u];
+      uint32_t valid = items - u * 8;
+      if (valid < 8) mi &= (1u << valid) - 1;
+    } else if (W == 4) {
+      mi = (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
+    } else {
+      mi = (sc.lv0[u / 8] >> (u % 8)) & 1u;
+    }
+    uint32_t s = pos + W * (sc.rpre[r] + sc.off[u]);
+    uint64_t v = 0;
+    if (W == 1) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b)
+        if ((mi >> b) & 1) v |= (uint64_t)in[s++] << (8 * b);
+    } else if (W == 4) {
+      if (mi & 1) {
+        v |= (uint64_t)in[s] | ((uint64_t)in[s + 1] << 8) | ((uint64_t)in[s + 2] << 16) |
+             ((uint64_t)in[s + 3] << 24);
+        s += 4;
+      }
+      if (mi & 2)
+        v |= ((uint64_t)in[s] | ((uint64_t)in[s + 1] << 8) | ((uint64_t)in[s + 2] << 16) |
+              ((uint64_t)in[s + 3] << 24)) << 32;
+    } else if (mi) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) v |= (uint64_t)in[s + b] << (8 * b);
+    }
+    U[u] = v;
+  }
+  __syncthreads();
+  return true;
+}
+
+// BIT_K of the chunk's words, given per wave in registers: wv[i] is word
+// 64*g + lane of group g = wave + kWaves*i.  Planes >= np are zero.
+template <int K, int GPW>
+__device__ void bit_encode(const typename Traits<K>::Word (&wv)[GPW], uint32_t G,
+                           uint32_t np, uint64_t* U) {
+#pragma unroll
+  for (int i = 0; i < GPW; ++i) {
+    const uint32_t g = wave() + kWaves * i;
+    if (g >= G) break;
+    uint64_t mine = 0;
+    for (uint32_t j = 0; j < np; ++j) {
+      uint64_t b = __ballot((wv[i] >> j) & 1);
+      if (lane() == (int)j) mine = b;
+    }
+    if (lane() < 8 * K) U[lane() * G + g] = mine;
+  }
+}
+
+// Planes holding a nonzero unit (bit j set: plane j not all zero).
+template <int K>
+__device__ uint64_t nonzero_planes(const uint64_t* U, uint32_t G, Scratch& sc) {
+  uint64_t any = 0;
+  if (threadIdx.x < 8 * K) {
+    const uint64_t* p = U + threadIdx.x * G;
+    for (uint32_t g = 0; g < G; ++g) any |= p[g];
+  }
+  if (threadIdx.x < 64) {
+    uint64_t m = __ballot(any != 0ull);
+    if (threadIdx.x == 0) sc.planes = m;
+  }
+  __syncthreads();
+  return sc.planes;
+}
+
+// BIT_K inverse: words[64g + lane] from the units of the nonzero planes.
+template <int K>
+__device__ void bit_decode(const uint64_t* U, uint32_t G, uint64_t planes,
+                           typename Traits<K>::Word* words) {
+  using Word = typename Traits<K>::Word;
+  const uint32_t* U32 = (const uint32_t*)U;
+  const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
+  for (uint32_t g = wave(); g < G; g += kWaves) {
+    Word w = 0;
+    uint64_t pm = planes;
+    while (pm) {
+      const uint32_t j = (uint32_t)__builtin_ctzll(pm);
+      pm &= pm - 1;
+      const uint32_t h = U32[2 * (j * G + g) + half];
+      w |= (Word)((h >> sh) & 1u) << j;
+    }
+    words[g * 64 + lane()] = w;
+  }
+}
+
+__device__ __forceinline__ uint64_t block_or(uint64_t v, Scratch& sc) {
+  // wave OR by ballots over the set bits is costly; reduce through LDS
+  for (int d = 32; d > 0; d >>= 1) v |= __shfl_xor(v, d, 64);
+  if (lane() == 0) sc.orv[wave()] = v;
+  __syncthreads();
+  uint64_t r = 0;
+  for (int w = 0; w < kWaves; ++w) r |= sc.orv[w];
+  __syncthreads();
+  return r;
+}
+
+constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62,
+                   kLbVal = (1ull << 62) - 1;
+
+// ------------------------------------------------------------------ encoder
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_encode(
+    uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
+    const uint32_t* __restrict__ sub, uint64_t* lookback, Params* prm,
+    uint8_t* stream, uint64_t cap, uint32_t nch) {
+  using Tr = Traits<K>;
+  using Word = typename Tr::Word;
+  constexpr uint32_t W = kChunkBytes / K;
+  constexpr int GPW = (int)(W / 64 / kWaves);  // groups per wave
+  __shared__ uint64_t U[kMaxUnits];
+  __shared__ uint64_t mid[kMaxUnits + 2];
+  __shared__ __attribute__((aligned(16))) uint8_t rec[kRecordHeaderBytes + 2 * kChunkBytes + 16];
+  __shared__ Scratch sc;
+  __shared__ uint32_t s_chunk;
+  __shared__ uint64_t s_excl;
+
+  if (threadIdx.x == 0) s_chunk = atomicAdd(&prm->ticket, 1u);
+  __syncthreads();
+  const uint32_t c = s_chunk;
+  if (c >= nch) return;
+  const uint32_t p0 = c * W;
+  const uint32_t nc = min(W, n - p0);
+  const uint32_t m = (nc + 63) / 64 * 64;
+  const uint32_t G = m / 64;
+  const uint32_t L = m * K;
+  const Word M = (Word)0xAAAAAAAAAAAAAAAAull;
+
+  // bins: DIFFNB_K (delta from the previous bin, 0 before the chunk, then
+  // negabinary), zero words up to m, BIT_K, RZE_1
+  Word wv[GPW];
+  uint64_t orv = 0;
+#pragma unroll
+  for (int i = 0; i < GPW; ++i) {
+    const uint32_t g = wave() + kWaves * i;
+    const uint32_t j = g * 64 + lane();
+    Word v = 0;
+    if (j < nc) {
+      Word cur = (Word)bins[p0 + j];
+      Word prev = j ? (Word)bins[p0 + j - 1] : (Word)0;
+      Word d = cur - prev;
+      v = (d + M) ^ M;
+    }
+    wv[i] = v;
+    orv |= (uint64_t)v;
+  }
+  orv = block_or(orv, sc);
+  uint32_t np = orv ? 64 - (uint32_t)__builtin_clzll(orv) : 0;
+  bit_encode<K, GPW>(wv, G, np, U);
+  __syncthreads();
+  int pt_b = 0, pt_s1 = 0, pt_s2 = 0;
+  const uint32_t blen = rze_encode<1>(U, L, rec + kRecordHeaderBytes, sc, pt_b);
+
+  // subbins: zero words up to m, BIT_K, RZE_K, RZE_1
+  orv = 0;
+#pragma unroll
+  for (int i = 0; i < GPW; ++i) {
+    const uint32_t g = wave() + kWaves * i;
+    const uint32_t j = g * 64 + lane();
+    Word v = j < nc ? (Word)sub[p0 + j] : (Word)0;
+    wv[i] = v;
+    orv |= (uint64_t)v;
+  }
+  orv = block_or(orv, sc);
+  np = orv ? 64 - (uint32_t)__builtin_clzll(orv) : 0;
+  bit_encode<K, GPW>(wv, G, np, U);
+  __syncthreads();
+  const uint32_t smid = rze_encode<K>(U, L, (uint8_t*)mid, sc, pt_s1);
+  if (threadIdx.x < 16) ((uint8_t*)mid)[smid + threadIdx.x] = 0;  // zero units past smid
+  __syncthreads();
+  const uint32_t slen = rze_encode<1>(mid, smid, rec + kRecordHeaderBytes + blen, sc, pt_s2);
+
+  uint32_t size = kRecordHeaderBytes + blen + slen;
+  const uint32_t padded = (size + 3) & ~3u;
+  if (threadIdx.x == 0) {
+    rec[0] = (uint8_t)pt_b;
+    rec[1] = (uint8_t)(pt_s1 | (pt_s2 << 1));
+    rec[2] = (uint8_t)nc;
+    rec[3] = (uint8_t)(nc >> 8);
+    put_bytes(rec + 4, blen, 4);
+    put_bytes(rec + 8, smid, 4);
+    put_bytes(rec + 12, slen, 4);
+    for (uint32_t i = size; i < padded; ++i) rec[i] = 0;
+  }
+  size = padded;
+
+  // decoupled look-back for this chunk's offset in the stream body
+  if (threadIdx.x == 0) {
+    uint64_t excl = 0;
+    if (c == 0) {
+      __hip_atomic_store(&lookback[0], kLbInc | size, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&lookback[c], kLbAgg | size, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      int64_t j = (int64_t)c - 1;
+      uint32_t spins = 0;
+      while (j >= 0) {
+        uint64_t v = __hip_atomic_load(&lookback[j], __ATOMIC_ACQUIRE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t st = v & ~kLbVal;
+        if (st == 0) {
+          if (++spins > (1u << 26)) {  // never reached when every chunk runs
+            set_status(prm, ST_INTERNAL);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += v & kLbVal;
+        if (st == kLbInc) break;
+        --j;
+      }
+      __hip_atomic_store(&lookback[c], kLbInc | (excl + size), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_excl = excl;
+    atomicAdd((unsigned long long*)&prm->bins_bytes, (unsigned long long)blen);
+    atomicAdd((unsigned long long*)&prm->sub_bytes, (unsigned long long)slen);
+  }
+  __syncthreads();
+  const uint64_t body = kHeaderBytes + 4ull * nch;
+  const uint64_t dst = body + s_excl;
+  if (threadIdx.x == 0) {
+    if (kHeaderBytes + 4ull * c + 4 <= cap)
+      *(uint32_t*)(stream + kHeaderBytes + 4ull * c) = size;
+    if (c == nch - 1) prm->stream_size = dst + size;
+  }
+  if (dst + size <= cap) {
+    for (uint32_t i = threadIdx.x; i < size / 4; i += kThreads)
+      ((uint32_t*)(stream + dst))[i] = ((const uint32_t*)rec)[i];
+  } else if (threadIdx.x == 0) {
+    set_status(prm, ST_CAPACITY);
+  }
+}
+
+// ------------------------------------------------------------------ decoder
+// Exclusive offsets of the records from the size table; the sizes must add
+// up to the stream body exactly.
+__global__ __launch_bounds__(kThreads) void k_offsets(
+    const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
+    uint64_t* offsets, Params* prm) {
+  __shared__ uint64_t sh[kWaves + 1];
+  const uint32_t per = (nch + kThreads - 1) / kThreads;
+  const uint32_t b = threadIdx.x * per, e = min(nch, b + per);
+  const uint32_t* tab = (const uint32_t*)(stream + kHeaderBytes);
+  uint64_t sum = 0;
+  for (uint32_t i = b; i < e; ++i) sum += tab[i];
+  uint64_t total;
+  uint64_t off = block_excl_scan<uint64_t>(sum, sh, total);
+  for (uint32_t i = b; i < e; ++i) {
+    offsets[i] = off;
+    off += tab[i];
+  }
+  if (threadIdx.x == 0 && total != body_bytes) set_status(prm, ST_FORMAT);
+}
+
+// Lowest representable value of bin b (as an order key): start next to the
+// real lower edge (b - 1/2) / inv and step to the first value whose bin is b.
+template <int K>
+__device__ __forceinline__ bool bin_floor_key(int64_t b, double inv,
+                                              double winv, int64_t& out) {
+  using Tr = Traits<K>;
+  if (b > Tr::kBinLimit || b < -Tr::kBinLimit) return false;
+  double c = ((double)b - 0.5) * winv;
+  int64_t k;
+  if (K == 4) {
+    float f = (float)c;
+    uint32_t u = __float_as_uint(f);
+    if (!finite32(u)) return false;
+    k = key32(u);
+  } else {
+    uint64_t u = (uint64_t)__double_as_longlong(c);
+    if (!finite64(u)) return false;
+    k = key64(u);
+  }
+  int steps = 0;
+  while (k > -Tr::kMaxKey && q_bin(Tr::to_double(Tr::unkey(k - 1)), inv) >= b) {
+    --k;
+    if (++steps > 8) return false;
+  }
+  while (q_bin(Tr::to_double(Tr::unkey(k)), inv) < b) {
+    if (k >= Tr::kMaxKey || ++steps > 8) return false;
+    ++k;
+  }
+  if (q_bin(Tr::to_double(Tr::unkey(k)), inv) != b) return false;
+  out = k;
+  return true;
+}
+
+// copy n bytes from global src (4-byte aligned base) to LDS dst
+__device__ __forceinline__ void stage(uint8_t* dst, const uint8_t* src, uint32_t n) {
+  const uint32_t nw = (n + 3) / 4;
+  for (uint32_t i = threadIdx.x; i < nw; i += kThreads)
+    ((uint32_t*)dst)[i] = ((const uint32_t*)src)[i];
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_decode(
+    const uint8_t* __restrict__ stream, uint32_t n,
+    const uint64_t* __restrict__ offsets, Params* prm,
+    typename Traits<K>::Raw* __restrict__ out) {
+  using Tr = Traits<K>;
+  using Word = typename Tr::Word;
+  constexpr uint32_t W = kChunkBytes / K;
+  __shared__ uint64_t R[kMaxUnits + 2];   // staged record part
+  __shared__ uint64_t U[kMaxUnits];       // bit-plane units
+  __shared__ uint64_t mid[kMaxUnits + 2]; // subbins after RZE_1
+  __shared__ uint64_t Wb[kMaxUnits];      // bin words
+  __shared__ Scratch sc;
+  __shared__ int s_bad;
+
+  const uint32_t nch = gridDim.x, c = blockIdx.x;
+  const uint32_t p0 = c * W, nc = min(W, n - p0);
+  const uint32_t m = (nc + 63) / 64 * 64, G = m / 64, L = m * K;
+  const uint64_t body = kHeaderBytes + 4ull * nch;
+  if (prm->status & ST_FORMAT) return;  // offsets inconsistent
+  const uint32_t rsize = ((const uint32_t*)(stream + kHeaderBytes))[c];
+  const uint8_t* rec = stream + body + offsets[c];
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (rsize < kRecordHeaderBytes || (rsize & 3)) {
+    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
+    return;
+  }
+  const double inv = __longlong_as_double(*(const long long*)(stream + 56));
+  const double winv = 1.0 / inv;
+  const uint32_t bfl = rec[0], sfl = rec[1];
+  const uint32_t npts = rec[2] | (rec[3] << 8);
+  const uint32_t blen = *(const uint32_t*)(rec + 4);
+  const uint32_t smid = *(const uint32_t*)(rec + 8);
+  const uint32_t slen = *(const uint32_t*)(rec + 12);
+  bool ok = !(bfl & ~1u) && !(sfl & ~3u) && npts == nc && blen <= L &&
+            smid <= L && slen <= L;
+  const uint32_t used = kRecordHeaderBytes + blen + slen;
+  ok = ok && ((used + 3) & ~3u) == rsize;
+  if (ok && threadIdx.x < rsize - used && rec[used + threadIdx.x] != 0) s_bad = 1;
+  __syncthreads();
+  ok = ok && !s_bad;
+  if (!ok) {
+    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
+    return;
+  }
+
+  // bins: RZE_1 -> BIT_K -> negabinary -> prefix sum
+  stage((uint8_t*)R, rec + kRecordHeaderBytes, blen);
+  __syncthreads();
+  const uint64_t* bu;
+  if (bfl & 1) {
+    ok = blen == L;
+    bu = R;
+  } else {
+    ok = rze_decode<1>((const uint8_t*)R, blen, L, U, sc);
+    bu = U;
+  }
+  if (!ok) {
+    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
+    return;
+  }
+  uint64_t planes = nonzero_planes<K>(bu, G, sc);
+  bit_decode<K>(bu, G, planes, (Word*)Wb);
+  __syncthreads();
+  {
+    // each thread owns a run of consecutive words; prefix sums modulo 2^(8K)
+    const Word M = (Word)0xAAAAAAAAAAAAAAAAull;
+    constexpr uint32_t per = W / kThreads;
+    const uint32_t b0 = threadIdx.x * per;
+    Word loc = 0;
+    Word d[per];
+#pragma unroll
+    for (uint32_t q = 0; q < per; ++q) {
+      const uint32_t i = b0 + q;
+      d[q] = i < nc ? (((Word*)Wb)[i] ^ M) - M : (Word)0;
+      loc += d[q];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan<uint64_t>((uint64_t)loc, sc.scan64, tot);
+    Word acc = (Word)run;
+#pragma unroll
+    for (uint32_t q = 0; q < per; ++q) {
+      acc += d[q];
+      ((Word*)Wb)[b0 + q] = acc;
+    }
+  }
+
+  // subbins: RZE_1 -> RZE_K -> BIT_K
+  const uint32_t soff = kRecordHeaderBytes + blen;
+  const uint32_t shift = soff & 3u;
+  stage((uint8_t*)R, rec + (soff - shift), slen + shift);
+  __syncthreads();
+  const uint8_t* sp = (const uint8_t*)R + shift;
+  if (sfl & 2) {
+    ok = slen == smid;
+    if (ok) {
+      uint8_t* mb = (uint8_t*)mid;
+      for (uint32_t i = threadIdx.x; i < smid; i += kThreads) mb[i] = sp[i];
+    }
+    __syncthreads();
+  } else {
+    ok = rze_decode<1>(sp, slen, smid, mid, sc);
+  }
+  if (ok) {
+    if (sfl & 1) {
+      ok = smid == L;
+      bu = mid;
+    } else {
+      ok = rze_decode<K>((const uint8_t*)mid, smid, L, U, sc);
+      bu = U;
+    }
+  }
+  if (!ok) {
+    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
+    return;
+  }
+  planes = nonzero_planes<K>(bu, G, sc);
+  bit_decode<K>(bu, G, planes, (Word*)R);
+  __syncthreads();
+
+  // reconstruct (Sec. IV-E)
+  bool bad = false;
+  for (uint32_t i = threadIdx.x; i < nc; i += kThreads) {
+    int64_t b;
+    if (K == 4) b = (int64_t)(int32_t)((const uint32_t*)Wb)[i];
+    else b = (int64_t)((const uint64_t*)Wb)[i];
+    const uint64_t s = (uint64_t)((const Word*)R)[i];
+    int64_t klo;
+    typename Tr::Raw v = 0;
+    if (!bin_floor_key<K>(b, inv, winv, klo) || s > (uint64_t)(Tr::kMaxKey - klo)) {
+      bad = true;
+    } else {
+      v = Tr::unkey(klo + (int64_t)s);
+      if (q_bin(Tr::to_double(v), inv) != b) bad = true;
+    }
+    out[p0 + i] = v;
+  }
+  if (bad) set_status(prm, ST_FORMAT);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_encode(int dtype, uint32_t n, const void* bins,
+                         const uint32_t* sub, uint64_t* lookback, Params* prm,
+                         uint8_t* stream, size_t cap, hipStream_t s) {
+  uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
+  uint32_t nch = (n + W - 1) / W;
+  if (dtype == 0)
+    k_encode<4><<<nch, kThreads, 0, s>>>(n, (const int32_t*)bins, sub, lookback, prm,
+                                         stream, cap, nch);
+  else
+    k_encode<8><<<nch, kThreads, 0, s>>>(n, (const int64_t*)bins, sub, lookback, prm,
+                                         stream, cap, nch);
+  return hipGetLastError();
+}
+
+hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
+                          uint64_t body_bytes, uint64_t* offsets, Params* prm,
+                          hipStream_t s) {
+  k_offsets<<<1, kThreads, 0, s>>>(stream, nch, body_bytes, offsets, prm);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
+                         const uint64_t* offsets, Params* prm, void* field,
+                         hipStream_t s) {
+  uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
+  uint32_t nch = (n + W - 1) / W;
+  if (dtype == 0)
+    k_decode<4><<<nch, kThreads, 0, s>>>(stream, n, offsets, prm, (uint32_t*)field);
+  else
+    k_decode<8><<<nch, kThreads, 0, s>>>(stream, n, offsets, prm, (uint64_t*)field);
+  return hipGetLastError();
+}
+
+}  // namespace lopc

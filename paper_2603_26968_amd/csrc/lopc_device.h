@@ -1,0 +1,93 @@
+// Device helpers shared by the kernels of liblopc.so: wave64 lane/wave ids,
+// block scans, per-dtype traits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lopc_internal.h"
+#include "lopc_numeric.h"
+
+namespace lopc {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ __forceinline__ int lane() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave() { return threadIdx.x >> 6; }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ void set_status(Params* prm, uint32_t bits) {
+  atomicOr(&prm->status, bits);
+}
+
+template <int K> struct Traits;
+template <> struct Traits<4> {
+  using Raw = uint32_t;   // bits of a value
+  using Bin = int32_t;
+  using Word = uint32_t;  // stage word
+  static constexpr int64_t kBinLimit = 2147483646ll;
+  static constexpr int64_t kMaxKey = 0x7f7fffffll;
+  __device__ static int64_t key(Raw u) { return key32(u); }
+  __device__ static Raw unkey(int64_t k) { return unkey32(k); }
+  __device__ static bool finite(Raw u) { return finite32(u); }
+  __device__ static double to_double(Raw u) { return (double)__uint_as_float(u); }
+};
+template <> struct Traits<8> {
+  using Raw = uint64_t;
+  using Bin = int64_t;
+  using Word = uint64_t;
+  static constexpr int64_t kBinLimit = 4611686018427387904ll;
+  static constexpr int64_t kMaxKey = 0x7fefffffffffffffll;
+  __device__ static int64_t key(Raw u) { return key64(u); }
+  __device__ static Raw unkey(int64_t k) { return unkey64(k); }
+  __device__ static bool finite(Raw u) { return finite64(u); }
+  __device__ static double to_double(Raw u) { return __longlong_as_double((long long)u); }
+};
+
+// ------------------------------------------------------------------ stencil
+// Edges of the Freudenthal triangulation: +-d for nonzero d in {0,1}^3,
+// listed as (dz, dy, dx); bit j of a point's mask refers to offset j.  Even
+// entries point to a higher linear index (raising weight 1), odd ones lower.
+__constant__ int8_t c_off[14][3] = {
+    {0, 0, 1},  {0, 0, -1},  {0, 1, 0},  {0, -1, 0}, {0, 1, 1},
+    {0, -1, -1}, {1, 0, 0},  {-1, 0, 0}, {1, 0, 1},  {-1, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, 1, 1},  {-1, -1, -1}};
+
+// ------------------------------------------------------------------ scans
+template <typename V>
+__device__ V block_excl_scan(V v, V* sh, V& total) {
+  V x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    V y = __shfl_up(x, d, 64);
+    if (lane() >= d) x += y;
+  }
+  if (lane() == 63) sh[wave()] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    V acc = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      V t = sh[w];
+      sh[w] = acc;
+      acc += t;
+    }
+    sh[kWaves] = acc;
+  }
+  __syncthreads();
+  V res = x - v + sh[wave()];
+  total = sh[kWaves];
+  __syncthreads();
+  return res;
+}
+
+__device__ __forceinline__ void put_bytes(uint8_t* dst, uint64_t v, int nbytes) {
+  for (int i = 0; i < nbytes; ++i) dst[i] = (uint8_t)(v >> (8 * i));
+}
+
+}  // namespace lopc

@@ -13,87 +13,10 @@
 
 #include <algorithm>
 
-#include "lopc_internal.h"
-#include "lopc_numeric.h"
+#include "lopc_device.h"
 
 namespace lopc {
 namespace {
-
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-
-__device__ __forceinline__ int lane() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave() { return threadIdx.x >> 6; }
-
-// number of set bits of m below this lane
-__device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-__device__ __forceinline__ void set_status(Params* prm, uint32_t bits) {
-  atomicOr(&prm->status, bits);
-}
-
-template <int K> struct Traits;
-template <> struct Traits<4> {
-  using Raw = uint32_t;   // bits of a value
-  using Bin = int32_t;
-  using Word = uint32_t;  // stage word
-  static constexpr int64_t kBinLimit = 2147483646ll;
-  static constexpr int64_t kMaxKey = 0x7f7fffffll;
-  __device__ static int64_t key(Raw u) { return key32(u); }
-  __device__ static Raw unkey(int64_t k) { return unkey32(k); }
-  __device__ static bool finite(Raw u) { return finite32(u); }
-  __device__ static double to_double(Raw u) { return (double)__uint_as_float(u); }
-};
-template <> struct Traits<8> {
-  using Raw = uint64_t;
-  using Bin = int64_t;
-  using Word = uint64_t;
-  static constexpr int64_t kBinLimit = 4611686018427387904ll;
-  static constexpr int64_t kMaxKey = 0x7fefffffffffffffll;
-  __device__ static int64_t key(Raw u) { return key64(u); }
-  __device__ static Raw unkey(int64_t k) { return unkey64(k); }
-  __device__ static bool finite(Raw u) { return finite64(u); }
-  __device__ static double to_double(Raw u) { return __longlong_as_double((long long)u); }
-};
-
-// ------------------------------------------------------------------ stencil
-// Edges of the Freudenthal triangulation: +-d for nonzero d in {0,1}^3,
-// listed as (dz, dy, dx); bit j of a point's mask refers to offset j.  Even
-// entries point to a higher linear index (raising weight 1), odd ones lower.
-__constant__ int8_t c_off[14][3] = {
-    {0, 0, 1},  {0, 0, -1},  {0, 1, 0},  {0, -1, 0}, {0, 1, 1},
-    {0, -1, -1}, {1, 0, 0},  {-1, 0, 0}, {1, 0, 1},  {-1, 0, -1},
-    {1, 1, 0},  {-1, -1, 0}, {1, 1, 1},  {-1, -1, -1}};
-
-// ------------------------------------------------------------------ scans
-template <typename V>
-__device__ V block_excl_scan(V v, V* sh, V& total) {
-  V x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    V y = __shfl_up(x, d, 64);
-    if (lane() >= d) x += y;
-  }
-  if (lane() == 63) sh[wave()] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    V acc = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      V t = sh[w];
-      sh[w] = acc;
-      acc += t;
-    }
-    sh[kWaves] = acc;
-  }
-  __syncthreads();
-  V res = x - v + sh[wave()];
-  total = sh[kWaves];
-  __syncthreads();
-  return res;
-}
 
 // ------------------------------------------------------------------ a0
 template <int K>
@@ -126,10 +49,6 @@ __global__ __launch_bounds__(kThreads) void k_minmax(
     part[2 * blockIdx.x] = slo[0];
     part[2 * blockIdx.x + 1] = shi[0];
   }
-}
-
-__device__ void put_bytes(uint8_t* dst, uint64_t v, int nbytes) {
-  for (int i = 0; i < nbytes; ++i) dst[i] = (uint8_t)(v >> (8 * i));
 }
 
 template <int K>
@@ -364,562 +283,6 @@ __global__ __launch_bounds__(kThreads) void k_repair(
   }
 }
 
-// ------------------------------------------------------------------ stages
-// Scratch of the RZE encoder / decoder (bitmap levels, ranks).
-struct RzeScratch {
-  uint64_t bm[2048 / 8];      // level-1 bitmap (up to 16384 items)
-  uint8_t lv1[256 + 8];       // level-2 bitmap
-  uint8_t lv2[32 + 8];        // level-3 bitmap
-  uint8_t lv3[8 + 8];         // level-4 bitmap
-  uint8_t kept0[2048];        // kept bytes of level 1
-  uint8_t kept1[256];         // kept bytes of level 2
-  uint8_t kept2[32];          // kept bytes of level 3
-  uint32_t gpos[kThreads];    // per-group exclusive counts
-  uint32_t scan[kWaves + 1];
-  uint64_t scan64[kWaves + 1];
-  uint32_t nkept[4];
-};
-
-__device__ __forceinline__ uint8_t* level_buf(RzeScratch& sc, int l) {
-  return l == 0 ? (uint8_t*)sc.bm : (l == 1 ? sc.lv1 : (l == 2 ? sc.lv2 : sc.lv3));
-}
-__device__ __forceinline__ uint8_t* kept_buf(RzeScratch& sc, int l) {
-  return l == 0 ? sc.kept0 : (l == 1 ? sc.kept1 : sc.kept2);
-}
-
-__device__ __forceinline__ int rze_levels(uint32_t items, uint32_t* sz) {
-  int top = 0;
-  sz[0] = (items + 7) / 8;
-  while (sz[top] > 8) {
-    sz[top + 1] = (sz[top] + 7) / 8;
-    ++top;
-  }
-  return top;
-}
-
-template <int W>
-__device__ __forceinline__ bool word_nonzero(const uint8_t* in, uint32_t i) {
-  if (W == 1) return in[i] != 0;
-  if (W == 4) return *(const uint32_t*)(in + 4 * i) != 0;
-  return *(const uint64_t*)(in + 8 * i) != 0;
-}
-
-// RZE_W of len bytes (LDS, W-aligned for W > 1) into out (LDS).  Returns the
-// output length; pt = stored verbatim.  len <= 16384, len % W == 0.
-template <int W>
-__device__ uint32_t rze_encode(const uint8_t* in, uint32_t len, uint8_t* out,
-                               RzeScratch& sc, int& pt) {
-  const uint32_t items = len / W;
-  const uint32_t groups = (items + 63) / 64;
-  for (uint32_t g = wave(); g < groups; g += kWaves) {
-    uint32_t it = g * 64 + lane();
-    bool nz = it < items && word_nonzero<W>(in, it);
-    uint64_t m = __ballot(nz);
-    if (lane() == 0) sc.bm[g] = m;
-  }
-  __syncthreads();
-  uint32_t total;
-  {
-    uint32_t c = threadIdx.x < groups ? (uint32_t)__popcll(sc.bm[threadIdx.x]) : 0u;
-    uint32_t e = block_excl_scan<uint32_t>(c, sc.scan, total);
-    if (threadIdx.x < groups) sc.gpos[threadIdx.x] = e;
-  }
-  const uint32_t npay = total;
-  uint32_t sz[8];
-  const int top = rze_levels(items, sz);
-  // zero the tail of the level-1 bitmap beyond its byte length
-  // (already zero: bits beyond items are never set by the ballot)
-  for (int l = 0; l < top; ++l) {
-    const uint8_t* cur = level_buf(sc, l);
-    uint8_t* nxt = level_buf(sc, l + 1);
-    uint8_t* kept = kept_buf(sc, l);
-    const uint32_t n = sz[l];
-    const uint32_t g2 = (n + 63) / 64;
-    // bitmap of bytes that differ from their predecessor
-    for (uint32_t g = wave(); g < g2; g += kWaves) {
-      uint32_t i = g * 64 + lane();
-      bool diff = i < n && cur[i] != (i ? cur[i - 1] : (uint8_t)0);
-      uint64_t m = __ballot(diff);
-      if (lane() == 0) {
-        for (int b = 0; b < 8; ++b) nxt[g * 8 + b] = (uint8_t)(m >> (8 * b));
-      }
-    }
-    __syncthreads();
-    uint32_t cnt = 0;
-    if (threadIdx.x < g2) {
-      uint64_t m = 0;
-      for (int b = 0; b < 8; ++b) m |= (uint64_t)nxt[threadIdx.x * 8 + b] << (8 * b);
-      cnt = (uint32_t)__popcll(m);
-    }
-    uint32_t kt;
-    uint32_t e = block_excl_scan<uint32_t>(cnt, sc.scan, kt);
-    if (threadIdx.x < g2) sc.gpos[threadIdx.x] = e;
-    __syncthreads();
-    for (uint32_t g = wave(); g < g2; g += kWaves) {
-      uint32_t i = g * 64 + lane();
-      uint64_t m = 0;
-      for (int b = 0; b < 8; ++b) m |= (uint64_t)nxt[g * 8 + b] << (8 * b);
-      if ((m >> lane()) & 1) kept[sc.gpos[g] + lane_prefix(m)] = cur[i];
-    }
-    if (threadIdx.x == 0) sc.nkept[l] = kt;
-    __syncthreads();
-    // restore level-1 group offsets for the payload (gpos was reused)
-  }
-  uint32_t out_len = sz[top] + npay * W;
-  for (int l = 0; l < top; ++l) out_len += sc.nkept[l];
-  if (out_len >= len) {
-    for (uint32_t i = threadIdx.x; i < len; i += kThreads) out[i] = in[i];
-    pt = 1;
-    __syncthreads();
-    return len;
-  }
-  pt = 0;
-  // top bitmap, kept bytes from the top level down, then the nonzero words
-  uint32_t pos = 0;
-  {
-    const uint8_t* tb = level_buf(sc, top);
-    for (uint32_t i = threadIdx.x; i < sz[top]; i += kThreads) out[i] = tb[i];
-    pos = sz[top];
-  }
-  for (int l = top - 1; l >= 0; --l) {
-    const uint8_t* kept = kept_buf(sc, l);
-    for (uint32_t i = threadIdx.x; i < sc.nkept[l]; i += kThreads) out[pos + i] = kept[i];
-    pos += sc.nkept[l];
-  }
-  // payload positions: recompute the level-1 group offsets
-  {
-    uint32_t c = threadIdx.x < groups ? (uint32_t)__popcll(sc.bm[threadIdx.x]) : 0u;
-    uint32_t tt;
-    uint32_t e = block_excl_scan<uint32_t>(c, sc.scan, tt);
-    if (threadIdx.x < groups) sc.gpos[threadIdx.x] = e;
-  }
-  __syncthreads();
-  for (uint32_t g = wave(); g < groups; g += kWaves) {
-    uint32_t it = g * 64 + lane();
-    uint64_t m = sc.bm[g];
-    if (it < items && ((m >> lane()) & 1)) {
-      uint32_t d = pos + (sc.gpos[g] + lane_prefix(m)) * W;
-#pragma unroll
-      for (int b = 0; b < W; ++b) out[d + b] = in[it * W + b];
-    }
-  }
-  __syncthreads();
-  return out_len;
-}
-
-// Inverse of rze_encode.  in: in_len bytes (global or LDS); out: len bytes in
-// LDS (W-aligned).  Returns false on a malformed input (reads stay inside
-// [in, in + in_len)).
-template <int W>
-__device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
-                           uint8_t* out, RzeScratch& sc) {
-  const uint32_t items = len / W;
-  uint32_t sz[8];
-  const int top = rze_levels(items, sz);
-  if (sz[top] > in_len) return false;
-  {
-    uint8_t* tb = level_buf(sc, top);
-    for (uint32_t i = threadIdx.x; i < 16; i += kThreads) tb[i] = i < sz[top] ? in[i] : 0;
-  }
-  __syncthreads();
-  uint32_t pos = sz[top];
-  for (int l = top - 1; l >= -1; --l) {
-    // parent bitmap = level l+1, describing `cn` child entries
-    const uint8_t* par = level_buf(sc, l + 1);
-    const uint32_t cn = l >= 0 ? sz[l] : items;
-    const uint32_t pw = (cn + 63) / 64;  // parent u64 words (<= 256)
-    uint64_t pm = 0;
-    if (threadIdx.x < pw) {
-      for (int b = 0; b < 8; ++b) pm |= (uint64_t)par[threadIdx.x * 8 + b] << (8 * b);
-      uint32_t valid = cn - threadIdx.x * 64;
-      if (valid < 64) pm &= (1ull << valid) - 1;
-    }
-    uint32_t cnt = threadIdx.x < pw ? (uint32_t)__popcll(pm) : 0u;
-    uint32_t total;
-    uint32_t e = block_excl_scan<uint32_t>(cnt, sc.scan, total);
-    if (threadIdx.x < pw) sc.gpos[threadIdx.x] = e;
-    __syncthreads();
-    if (l >= 0) {
-      if (pos + total > in_len) return false;
-      uint8_t* child = level_buf(sc, l);
-      for (uint32_t i = threadIdx.x; i < ((cn + 7) / 8) * 8 + 8 && i < 2048 + 8; i += kThreads) {
-        uint8_t v = 0;
-        if (i < cn) {
-          uint32_t w = i / 64, b = i % 64;
-          uint64_t m = 0;
-          for (int q = 0; q < 8; ++q) m |= (uint64_t)par[w * 8 + q] << (8 * q);
-          uint32_t valid = cn - w * 64;
-          if (valid < 64) m &= (1ull << valid) - 1;
-          uint32_t c = sc.gpos[w] + (uint32_t)__popcll(m & ((2ull << b) - 1));
-          v = c ? in[pos + c - 1] : (uint8_t)0;
-        }
-        if (l > 0 || i < 2048) child[i] = v;
-      }
-      pos += total;
-      __syncthreads();
-    } else {
-      if (pos + total * W != in_len) return false;
-      for (uint32_t i = threadIdx.x; i < items; i += kThreads) {
-        uint32_t w = i / 64, b = i % 64;
-        uint64_t m = 0;
-        for (int q = 0; q < 8; ++q) m |= (uint64_t)par[w * 8 + q] << (8 * q);
-        uint32_t valid = cn - w * 64;
-        if (valid < 64) m &= (1ull << valid) - 1;
-        bool set = (m >> b) & 1;
-        uint32_t r = sc.gpos[w] + (uint32_t)__popcll(m & ((1ull << b) - 1));
-#pragma unroll
-        for (int q = 0; q < W; ++q) out[i * W + q] = set ? in[pos + r * W + q] : (uint8_t)0;
-      }
-      __syncthreads();
-    }
-  }
-  return true;
-}
-
-// BIT_K: plane j (8K planes, lowest bit first) = bit j of every word.
-template <int K>
-__device__ void bit_encode(const uint8_t* words, uint32_t m, uint8_t* planes) {
-  using Word = typename Traits<K>::Word;
-  const uint32_t groups = m / 64, pb = m / 8;
-  for (uint32_t g = wave(); g < groups; g += kWaves) {
-    Word v = ((const Word*)words)[g * 64 + lane()];
-    uint64_t mine = 0;
-#pragma unroll
-    for (int j = 0; j < 8 * K; ++j) {
-      uint64_t b = __ballot((v >> j) & 1);
-      if (lane() == j) mine = b;
-    }
-    if (lane() < 8 * K) *(uint64_t*)(planes + lane() * pb + g * 8) = mine;
-  }
-}
-
-template <int K>
-__device__ void bit_decode(const uint8_t* planes, uint32_t m, uint8_t* words) {
-  using Word = typename Traits<K>::Word;
-  const uint32_t groups = m / 64, pb = m / 8;
-  for (uint32_t g = wave(); g < groups; g += kWaves) {
-    Word v = 0;
-#pragma unroll 8
-    for (int j = 0; j < 8 * K; ++j) {
-      uint64_t p = *(const uint64_t*)(planes + j * pb + g * 8);
-      v |= (Word)((p >> lane()) & 1) << j;
-    }
-    ((Word*)words)[g * 64 + lane()] = v;
-  }
-}
-
-// ------------------------------------------------------------------ a4-a6
-// One workgroup per 16 kB chunk; chunk ids come from a ticket counter so a
-// workgroup only ever waits for chunks that started before it (decoupled
-// look-back: every chunk publishes its record size at once and its
-// inclusive offset as soon as its predecessor's is known).
-constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62,
-                   kLbVal = (1ull << 62) - 1;
-
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_encode(
-    uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
-    const uint32_t* __restrict__ sub, uint64_t* lookback, Params* prm,
-    uint8_t* stream, uint64_t cap, uint32_t nch) {
-  using Tr = Traits<K>;
-  using Word = typename Tr::Word;
-  constexpr uint32_t W = kChunkBytes / K;
-  __shared__ __attribute__((aligned(16))) uint8_t bufA[kChunkBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t bufB[kChunkBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t rec[kRecordHeaderBytes + 2 * kChunkBytes];
-  __shared__ RzeScratch sc;
-  __shared__ uint32_t s_chunk;
-  __shared__ uint64_t s_excl;
-
-  if (threadIdx.x == 0) s_chunk = atomicAdd(&prm->ticket, 1u);
-  __syncthreads();
-  const uint32_t c = s_chunk;
-  if (c >= nch) return;
-  const uint32_t p0 = c * W;
-  const uint32_t nc = min(W, n - p0);
-  const uint32_t m = (nc + 63) / 64 * 64;
-  const uint32_t L = m * K;
-  const Word M = (Word)0xAAAAAAAAAAAAAAAAull;
-
-  // bins: DIFFNB_K (delta from the previous bin, 0 before the chunk, then
-  // negabinary), zero words up to m, BIT_K, RZE_1
-  for (uint32_t i = threadIdx.x; i < m; i += kThreads) {
-    Word v = 0;
-    if (i < nc) {
-      Word cur = (Word)bins[p0 + i];
-      Word prev = i ? (Word)bins[p0 + i - 1] : (Word)0;
-      Word d = cur - prev;
-      v = (d + M) ^ M;
-    }
-    ((Word*)bufA)[i] = v;
-  }
-  __syncthreads();
-  bit_encode<K>(bufA, m, bufB);
-  __syncthreads();
-  int pt_b = 0, pt_s1 = 0, pt_s2 = 0;
-  const uint32_t blen = rze_encode<1>(bufB, L, rec + kRecordHeaderBytes, sc, pt_b);
-
-  // subbins: zero words up to m, BIT_K, RZE_K, RZE_1
-  for (uint32_t i = threadIdx.x; i < m; i += kThreads)
-    ((Word*)bufA)[i] = i < nc ? (Word)sub[p0 + i] : (Word)0;
-  __syncthreads();
-  bit_encode<K>(bufA, m, bufB);
-  __syncthreads();
-  const uint32_t smid = rze_encode<K>(bufB, L, bufA, sc, pt_s1);
-  const uint32_t slen =
-      rze_encode<1>(bufA, smid, rec + kRecordHeaderBytes + blen, sc, pt_s2);
-
-  uint32_t size = kRecordHeaderBytes + blen + slen;
-  const uint32_t padded = (size + 3) & ~3u;
-  if (threadIdx.x == 0) {
-    rec[0] = (uint8_t)pt_b;
-    rec[1] = (uint8_t)(pt_s1 | (pt_s2 << 1));
-    rec[2] = (uint8_t)nc;
-    rec[3] = (uint8_t)(nc >> 8);
-    put_bytes(rec + 4, blen, 4);
-    put_bytes(rec + 8, smid, 4);
-    put_bytes(rec + 12, slen, 4);
-    for (uint32_t i = size; i < padded; ++i) rec[i] = 0;
-  }
-  size = padded;
-
-  // look-back for this chunk's offset in the stream body
-  if (threadIdx.x == 0) {
-    uint64_t excl = 0;
-    if (c == 0) {
-      __hip_atomic_store(&lookback[0], kLbInc | size, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&lookback[c], kLbAgg | size, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int64_t j = (int64_t)c - 1;
-      uint32_t spins = 0;
-      while (j >= 0) {
-        uint64_t v = __hip_atomic_load(&lookback[j], __ATOMIC_ACQUIRE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t st = v & ~kLbVal;
-        if (st == 0) {
-          if (++spins > (1u << 26)) {  // never reached when every chunk runs
-            set_status(prm, ST_INTERNAL);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += v & kLbVal;
-        if (st == kLbInc) break;
-        --j;
-      }
-      __hip_atomic_store(&lookback[c], kLbInc | (excl + size), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_excl = excl;
-    atomicAdd((unsigned long long*)&prm->bins_bytes, (unsigned long long)blen);
-    atomicAdd((unsigned long long*)&prm->sub_bytes, (unsigned long long)slen);
-  }
-  __syncthreads();
-  const uint64_t body = kHeaderBytes + 4ull * nch;
-  const uint64_t dst = body + s_excl;
-  if (threadIdx.x == 0) {
-    if (kHeaderBytes + 4ull * c + 4 <= cap)
-      *(uint32_t*)(stream + kHeaderBytes + 4ull * c) = size;
-    if (c == nch - 1) prm->stream_size = dst + size;
-  }
-  if (dst + size <= cap) {
-    for (uint32_t i = threadIdx.x; i < size / 4; i += kThreads)
-      ((uint32_t*)(stream + dst))[i] = ((const uint32_t*)rec)[i];
-  } else if (threadIdx.x == 0) {
-    set_status(prm, ST_CAPACITY);
-  }
-}
-
-// ------------------------------------------------------------------ a7, a8
-// Exclusive offsets of the records from the size table; the sizes must add
-// up to the stream body exactly.
-__global__ __launch_bounds__(kThreads) void k_offsets(
-    const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
-    uint64_t* offsets, Params* prm) {
-  __shared__ uint64_t sh[kWaves + 1];
-  const uint32_t per = (nch + kThreads - 1) / kThreads;
-  const uint32_t b = threadIdx.x * per, e = min(nch, b + per);
-  const uint32_t* tab = (const uint32_t*)(stream + kHeaderBytes);
-  uint64_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += tab[i];
-  uint64_t total;
-  uint64_t off = block_excl_scan<uint64_t>(sum, sh, total);
-  for (uint32_t i = b; i < e; ++i) {
-    offsets[i] = off;
-    off += tab[i];
-  }
-  if (threadIdx.x == 0 && total != body_bytes) set_status(prm, ST_FORMAT);
-}
-
-// Lowest representable value of bin b (as an order key): start next to the
-// real lower edge (b - 1/2) / inv and step to the first value whose bin is b.
-template <int K>
-__device__ __forceinline__ bool bin_floor_key(int64_t b, double inv,
-                                              double winv, int64_t& out) {
-  using Tr = Traits<K>;
-  if (b > Tr::kBinLimit || b < -Tr::kBinLimit) return false;
-  double c = ((double)b - 0.5) * winv;
-  int64_t k;
-  if (K == 4) {
-    float f = (float)c;
-    uint32_t u = __float_as_uint(f);
-    if (!finite32(u)) return false;
-    k = key32(u);
-  } else {
-    uint64_t u = (uint64_t)__double_as_longlong(c);
-    if (!finite64(u)) return false;
-    k = key64(u);
-  }
-  int steps = 0;
-  while (k > -Tr::kMaxKey && q_bin(Tr::to_double(Tr::unkey(k - 1)), inv) >= b) {
-    --k;
-    if (++steps > 8) return false;
-  }
-  while (q_bin(Tr::to_double(Tr::unkey(k)), inv) < b) {
-    if (k >= Tr::kMaxKey || ++steps > 8) return false;
-    ++k;
-  }
-  if (q_bin(Tr::to_double(Tr::unkey(k)), inv) != b) return false;
-  out = k;
-  return true;
-}
-
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_decode(
-    const uint8_t* __restrict__ stream, uint32_t n,
-    const uint64_t* __restrict__ offsets, Params* prm,
-    typename Traits<K>::Raw* __restrict__ out) {
-  using Tr = Traits<K>;
-  using Word = typename Tr::Word;
-  constexpr uint32_t W = kChunkBytes / K;
-  __shared__ __attribute__((aligned(16))) uint8_t P[kChunkBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t Wb[kChunkBytes];
-  __shared__ __attribute__((aligned(16))) uint8_t Mb[kChunkBytes];
-  __shared__ RzeScratch sc;
-  __shared__ uint64_t sh64[kWaves + 1];
-  __shared__ int s_bad;
-
-  const uint32_t nch = gridDim.x, c = blockIdx.x;
-  const uint32_t p0 = c * W, nc = min(W, n - p0);
-  const uint32_t m = (nc + 63) / 64 * 64, L = m * K;
-  const uint64_t body = kHeaderBytes + 4ull * nch;
-  const uint32_t rsize = ((const uint32_t*)(stream + kHeaderBytes))[c];
-  const uint8_t* rec = stream + body + offsets[c];
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
-  if (rsize < kRecordHeaderBytes || (rsize & 3) || (prm->status & ST_FORMAT)) {
-    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
-    return;
-  }
-  double inv = __longlong_as_double(*(const long long*)(stream + 56));
-  double winv = 1.0 / inv;
-  const uint32_t bfl = rec[0], sfl = rec[1];
-  const uint32_t npts = rec[2] | (rec[3] << 8);
-  const uint32_t blen = *(const uint32_t*)(rec + 4);
-  const uint32_t smid = *(const uint32_t*)(rec + 8);
-  const uint32_t slen = *(const uint32_t*)(rec + 12);
-  bool ok = !(bfl & ~1u) && !(sfl & ~3u) && npts == nc && blen <= L &&
-            smid <= L && slen <= L;
-  const uint32_t used = kRecordHeaderBytes + blen + slen;
-  ok = ok && ((used + 3) & ~3u) == rsize;
-  if (ok && threadIdx.x < rsize - used && rec[used + threadIdx.x] != 0) s_bad = 1;
-  __syncthreads();
-  ok = ok && !s_bad;
-  if (!ok) {
-    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
-    return;
-  }
-  const uint8_t* bp = rec + kRecordHeaderBytes;
-  const uint8_t* sp = bp + blen;
-
-  // bins: RZE_1 -> BIT_K -> negabinary -> prefix sum
-  if (bfl & 1) {
-    if (blen != L) ok = false;
-    else
-      for (uint32_t i = threadIdx.x; i < L; i += kThreads) P[i] = bp[i];
-  } else {
-    ok = rze_decode<1>(bp, blen, L, P, sc);
-  }
-  __syncthreads();
-  if (!ok) {
-    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
-    return;
-  }
-  bit_decode<K>(P, m, Wb);
-  __syncthreads();
-  {
-    // each thread owns a run of consecutive words; prefix sums modulo 2^(8K)
-    const Word M = (Word)0xAAAAAAAAAAAAAAAAull;
-    constexpr uint32_t per = W / kThreads;
-    const uint32_t b0 = threadIdx.x * per;
-    Word loc = 0;
-    for (uint32_t q = 0; q < per; ++q) {
-      uint32_t i = b0 + q;
-      if (i < nc) loc += (((Word*)Wb)[i] ^ M) - M;
-    }
-    uint64_t tot;
-    uint64_t run = block_excl_scan<uint64_t>((uint64_t)loc, sh64, tot);
-    Word acc = (Word)run;
-    for (uint32_t q = 0; q < per; ++q) {
-      uint32_t i = b0 + q;
-      if (i < nc) {
-        acc += (((Word*)Wb)[i] ^ M) - M;
-        ((Word*)Wb)[i] = acc;
-      }
-    }
-  }
-  __syncthreads();
-
-  // subbins: RZE_1 -> RZE_K -> BIT_K
-  if (sfl & 2) {
-    if (slen != smid) ok = false;
-    else
-      for (uint32_t i = threadIdx.x; i < smid; i += kThreads) Mb[i] = sp[i];
-  } else {
-    ok = rze_decode<1>(sp, slen, smid, Mb, sc);
-  }
-  __syncthreads();
-  if (ok) {
-    if (sfl & 1) {
-      if (smid != L) ok = false;
-      else
-        for (uint32_t i = threadIdx.x; i < L; i += kThreads) P[i] = Mb[i];
-    } else {
-      ok = rze_decode<K>(Mb, smid, L, P, sc);
-    }
-  }
-  __syncthreads();
-  if (!ok) {
-    if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
-    return;
-  }
-  bit_decode<K>(P, m, Mb);
-  __syncthreads();
-
-  // reconstruct (Sec. IV-E)
-  bool bad = false;
-  for (uint32_t i = threadIdx.x; i < nc; i += kThreads) {
-    int64_t b;
-    if (K == 4) b = (int64_t)(int32_t)((const uint32_t*)Wb)[i];
-    else b = (int64_t)((const uint64_t*)Wb)[i];
-    uint64_t s = (uint64_t)((const Word*)Mb)[i];
-    int64_t klo;
-    typename Tr::Raw v = 0;
-    if (!bin_floor_key<K>(b, inv, winv, klo) ||
-        s > (uint64_t)(Tr::kMaxKey - klo)) {
-      bad = true;
-    } else {
-      v = Tr::unkey(klo + (int64_t)s);
-      if (q_bin(Tr::to_double(v), inv) != b) bad = true;
-    }
-    out[p0 + i] = v;
-  }
-  if (bad) set_status(prm, ST_FORMAT);
-}
-
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -967,39 +330,6 @@ hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
     k_repair<1, 32, 64><<<t.ntiles, kThreads, 0, s>>>(box, t, mask, sub, stamp, counters, sweep);
   else
     k_repair<8, 8, 32><<<t.ntiles, kThreads, 0, s>>>(box, t, mask, sub, stamp, counters, sweep);
-  return hipGetLastError();
-}
-
-hipError_t launch_encode(int dtype, uint32_t n, const void* bins,
-                         const uint32_t* sub, uint64_t* lookback, Params* prm,
-                         uint8_t* stream, size_t cap, hipStream_t s) {
-  uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
-  uint32_t nch = (n + W - 1) / W;
-  if (dtype == 0)
-    k_encode<4><<<nch, kThreads, 0, s>>>(n, (const int32_t*)bins, sub, lookback, prm,
-                                         stream, cap, nch);
-  else
-    k_encode<8><<<nch, kThreads, 0, s>>>(n, (const int64_t*)bins, sub, lookback, prm,
-                                         stream, cap, nch);
-  return hipGetLastError();
-}
-
-hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
-                          uint64_t body_bytes, uint64_t* offsets, Params* prm,
-                          hipStream_t s) {
-  k_offsets<<<1, kThreads, 0, s>>>(stream, nch, body_bytes, offsets, prm);
-  return hipGetLastError();
-}
-
-hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
-                         const uint64_t* offsets, Params* prm, void* field,
-                         hipStream_t s) {
-  uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
-  uint32_t nch = (n + W - 1) / W;
-  if (dtype == 0)
-    k_decode<4><<<nch, kThreads, 0, s>>>(stream, n, offsets, prm, (uint32_t*)field);
-  else
-    k_decode<8><<<nch, kThreads, 0, s>>>(stream, n, offsets, prm, (uint64_t*)field);
   return hipGetLastError();
 }
 
