@@ -79,8 +79,12 @@ Tiling make_tiling(const Box& b) {
 }
 
 struct CompressLayout {
-  size_t prm, part, bins, mask, sub, stamp, counters, lookback, total;
+  size_t prm, part, bins, mask, sub, stamp, counters, lookback, parts, total;
 };
+
+// repair counters: [0] internal error flag; then two banks (sweep parity) of
+// 64 spread counters of tiles marked for the next sweep
+constexpr size_t kCounterWords = 1 + 2 * 64;
 
 CompressLayout compress_layout(const Shape& s, int dtype) {
   const size_t k = dtype == 0 ? 4 : 8;
@@ -95,8 +99,9 @@ CompressLayout compress_layout(const Shape& s, int dtype) {
   L.mask = o; o += align256(s.n * 2);
   L.sub = o; o += align256(s.n * 4);
   L.stamp = o; o += align256((size_t)t.ntiles * 4);
-  L.counters = o; o += align256(((size_t)kMaxSweeps + 2) * 4);
+  L.counters = o; o += align256(kCounterWords * 4);
   L.lookback = o; o += align256(nch * 8);
+  L.parts = o; o += align256(nch * 8);
   L.total = o;
   return L;
 }
@@ -281,7 +286,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   HIP_TRY(hipMemsetAsync(prm, 0, sizeof(Params), hs));
   HIP_TRY(hipMemsetAsync(sub, 0, s.n * 4, hs));
   HIP_TRY(hipMemsetAsync(stamp, 0, (size_t)tl.ntiles * 4, hs));
-  HIP_TRY(hipMemsetAsync(counters, 0, ((size_t)kMaxSweeps + 2) * 4, hs));
+  HIP_TRY(hipMemsetAsync(counters, 0, kCounterWords * 4, hs));
   HIP_TRY(hipMemsetAsync(lookback, 0, nch * 8, hs));
 
   int nblocks = (int)std::min<uint64_t>(kMinmaxBlocks, (s.n + 2047) / 2048);
@@ -303,13 +308,15 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     HIP_TRY(launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
                           counters, sw, hs));
     ++sweeps;
-    HIP_TRY(hipMemcpyAsync(ctx->h_cnt, counters + sw + 2, 4, hipMemcpyDeviceToHost, hs));
-    HIP_TRY(hipMemcpyAsync(ctx->h_cnt + 1, counters, 4, hipMemcpyDeviceToHost, hs));
+    uint32_t* bank = counters + 1 + 64 * (sw & 1);
+    HIP_TRY(hipMemcpyAsync(ctx->h_cnt, bank, 64 * 4, hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipMemcpyAsync(ctx->h_cnt + 64, counters, 4, hipMemcpyDeviceToHost, hs));
+    HIP_TRY(hipMemsetAsync(bank, 0, 64 * 4, hs));  // reused two sweeps later
     if (sw == 0)
       HIP_TRY(hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4,
                              hipMemcpyDeviceToHost, hs));
     HIP_TRY(hipStreamSynchronize(hs));
-    if (ctx->h_cnt[1]) return LOPC_E_INTERNAL;
+    if (ctx->h_cnt[64]) return LOPC_E_INTERNAL;
     if (sw == 0) {
       int code = status_code(ctx->h_prm->status);
       if (code != LOPC_OK) {
@@ -317,16 +324,20 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
         return code;
       }
     }
-    const uint32_t next = ctx->h_cnt[0];
+    uint64_t next = 0;
+    for (int i = 0; i < 64; ++i) next += ctx->h_cnt[i];
     if (next == 0) break;
     active += next;
     if (sw + 1 >= kMaxSweeps) return LOPC_E_INTERNAL;
   }
 
   HIP_TRY(mark(ctx, 3, hs));
-  HIP_TRY(launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback, prm,
-                        (uint8_t*)d_stream, stream_cap, hs));
+  HIP_TRY(launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
+                        (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream,
+                        stream_cap, hs));
   HIP_TRY(mark(ctx, 4, hs));
+  if (h_stats)
+    HIP_TRY(launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
   HIP_TRY(hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
   HIP_TRY(hipStreamSynchronize(hs));
   if (ctx->timing) {

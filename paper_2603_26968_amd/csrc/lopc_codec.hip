@@ -21,6 +21,8 @@
 namespace lopc {
 namespace {
 
+constexpr int kCT = 512;        // threads of a codec workgroup
+constexpr int kCW = kCT / 64;   // its waves
 constexpr uint32_t kMaxUnits = kChunkBytes / 8;  // 2048
 constexpr uint32_t kMaxRounds = kMaxUnits / 64;  // 32
 
@@ -35,10 +37,10 @@ struct Scratch {
   uint8_t kp2[32];
   uint16_t off[kMaxUnits];  // per-unit exclusive offset within its round
   uint32_t rpre[kMaxRounds + 1];  // per-round totals, then exclusive prefix
-  uint32_t scan[kWaves + 1];
+  uint32_t scan[kCW + 1];
   uint32_t nkept[4];
-  uint64_t orv[kWaves];
-  uint64_t scan64[kWaves + 1];
+  uint64_t orv[kCW];
+  uint64_t scan64[kCW + 1];
   uint64_t planes;
 };
 
@@ -109,7 +111,7 @@ __device__ void level_encode(const uint8_t* cur, uint32_t n, uint8_t* nxt,
     nxt[threadIdx.x] = (uint8_t)bits;
   }
   uint32_t tot;
-  uint32_t e = block_excl_scan<uint32_t>((uint32_t)__popc(bits), sc.scan, tot);
+  uint32_t e = block_excl_scan<uint32_t, kCW>((uint32_t)__popc(bits), sc.scan, tot);
   if (threadIdx.x < nb) {
     uint32_t i0 = threadIdx.x * 8;
     for (uint32_t b = 0; b < 8; ++b)
@@ -133,7 +135,7 @@ __device__ bool level_decode(const uint8_t* par, uint32_t n, const uint8_t* in,
     if (valid < 8) pb &= (1u << valid) - 1;
   }
   uint32_t tot;
-  uint32_t e = block_excl_scan<uint32_t>((uint32_t)__popc(pb), sc.scan, tot);
+  uint32_t e = block_excl_scan<uint32_t, kCW>((uint32_t)__popc(pb), sc.scan, tot);
   if (pos + tot > in_len) return false;
   if (threadIdx.x < np + 1) {
     uint32_t i0 = threadIdx.x * 8;
@@ -160,7 +162,7 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
   const uint32_t rounds = (NU + 63) / 64;
-  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+  for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
     const uint64_t v = u < NU ? U[u] : 0ull;
     uint32_t mi, ci;
@@ -193,7 +195,7 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
   for (int l = 0; l < top; ++l) out_len += sc.nkept[l];
   if (out_len >= len) {
     const uint8_t* ub = (const uint8_t*)U;
-    for (uint32_t i = threadIdx.x; i < len; i += kThreads) out[i] = ub[i];
+    for (uint32_t i = threadIdx.x; i < len; i += kCT) out[i] = ub[i];
     pt = 1;
     __syncthreads();
     return len;
@@ -202,15 +204,15 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
   uint32_t pos = 0;
   {
     const uint8_t* tb = lvl(sc, top);
-    for (uint32_t i = threadIdx.x; i < sz[top]; i += kThreads) out[i] = tb[i];
+    for (uint32_t i = threadIdx.x; i < sz[top]; i += kCT) out[i] = tb[i];
     pos = sz[top];
   }
   for (int l = top - 1; l >= 0; --l) {
     const uint8_t* kb = kept(sc, l);
-    for (uint32_t i = threadIdx.x; i < sc.nkept[l]; i += kThreads) out[pos + i] = kb[i];
+    for (uint32_t i = threadIdx.x; i < sc.nkept[l]; i += kCT) out[pos + i] = kb[i];
     pos += sc.nkept[l];
   }
-  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+  for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
     if (u >= NU) continue;
     const uint64_t v = U[u];
@@ -257,7 +259,7 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
   for (int l = top - 1; l >= 0; --l)
     if (!level_decode(lvl(sc, l + 1), sz[l], in, pos, in_len, lvl(sc, l), sc)) return false;
   // lv0 holds `items` bitmap bits
-  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+  for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
     uint32_t mi = 0;
     if (u < NU) {
@@ -279,7 +281,7 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
   __syncthreads();
   const uint32_t npay = round_prefix(sc, rounds);
   if (pos + npay * W != in_len) return false;
-  for (uint32_t r = wave(); r < rounds; r += kWaves) {
+  for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
     if (u >= NU) continue;
     uint32_t mi;
@@ -318,13 +320,13 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
 }
 
 // BIT_K of the chunk's words, given per wave in registers: wv[i] is word
-// 64*g + lane of group g = wave + kWaves*i.  Planes >= np are zero.
+// 64*g + lane of group g = wave + kCW*i.  Planes >= np are zero.
 template <int K, int GPW>
 __device__ void bit_encode(const typename Traits<K>::Word (&wv)[GPW], uint32_t G,
                            uint32_t np, uint64_t* U) {
 #pragma unroll
   for (int i = 0; i < GPW; ++i) {
-    const uint32_t g = wave() + kWaves * i;
+    const uint32_t g = wave() + kCW * i;
     if (g >= G) break;
     uint64_t mine = 0;
     for (uint32_t j = 0; j < np; ++j) {
@@ -358,7 +360,7 @@ __device__ void bit_decode(const uint64_t* U, uint32_t G, uint64_t planes,
   using Word = typename Traits<K>::Word;
   const uint32_t* U32 = (const uint32_t*)U;
   const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
-  for (uint32_t g = wave(); g < G; g += kWaves) {
+  for (uint32_t g = wave(); g < G; g += kCW) {
     Word w = 0;
     uint64_t pm = planes;
     while (pm) {
@@ -377,7 +379,7 @@ __device__ __forceinline__ uint64_t block_or(uint64_t v, Scratch& sc) {
   if (lane() == 0) sc.orv[wave()] = v;
   __syncthreads();
   uint64_t r = 0;
-  for (int w = 0; w < kWaves; ++w) r |= sc.orv[w];
+  for (int w = 0; w < kCW; ++w) r |= sc.orv[w];
   __syncthreads();
   return r;
 }
@@ -387,14 +389,14 @@ constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62,
 
 // ------------------------------------------------------------------ encoder
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_encode(
+__global__ __launch_bounds__(kCT) void k_encode(
     uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
-    const uint32_t* __restrict__ sub, uint64_t* lookback, Params* prm,
-    uint8_t* stream, uint64_t cap, uint32_t nch) {
+    const uint32_t* __restrict__ sub, uint64_t* lookback, uint32_t* parts,
+    Params* prm, uint8_t* stream, uint64_t cap, uint32_t nch) {
   using Tr = Traits<K>;
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
-  constexpr int GPW = (int)(W / 64 / kWaves);  // groups per wave
+  constexpr int GPW = (int)(W / 64 / kCW);  // groups per wave
   __shared__ uint64_t U[kMaxUnits];
   __shared__ uint64_t mid[kMaxUnits + 2];
   __shared__ __attribute__((aligned(16))) uint8_t rec[kRecordHeaderBytes + 2 * kChunkBytes + 16];
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(
   uint64_t orv = 0;
 #pragma unroll
   for (int i = 0; i < GPW; ++i) {
-    const uint32_t g = wave() + kWaves * i;
+    const uint32_t g = wave() + kCW * i;
     const uint32_t j = g * 64 + lane();
     Word v = 0;
     if (j < nc) {
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(
   orv = 0;
 #pragma unroll
   for (int i = 0; i < GPW; ++i) {
-    const uint32_t g = wave() + kWaves * i;
+    const uint32_t g = wave() + kCW * i;
     const uint32_t j = g * 64 + lane();
     Word v = j < nc ? (Word)sub[p0 + j] : (Word)0;
     wv[i] = v;
@@ -502,8 +504,8 @@ __global__ __launch_bounds__(kThreads) void k_encode(
                          __HIP_MEMORY_SCOPE_AGENT);
     }
     s_excl = excl;
-    atomicAdd((unsigned long long*)&prm->bins_bytes, (unsigned long long)blen);
-    atomicAdd((unsigned long long*)&prm->sub_bytes, (unsigned long long)slen);
+    parts[2 * c] = blen;
+    parts[2 * c + 1] = slen;
   }
   __syncthreads();
   const uint64_t body = kHeaderBytes + 4ull * nch;
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(
     if (c == nch - 1) prm->stream_size = dst + size;
   }
   if (dst + size <= cap) {
-    for (uint32_t i = threadIdx.x; i < size / 4; i += kThreads)
+    for (uint32_t i = threadIdx.x; i < size / 4; i += kCT)
       ((uint32_t*)(stream + dst))[i] = ((const uint32_t*)rec)[i];
   } else if (threadIdx.x == 0) {
     set_status(prm, ST_CAPACITY);
@@ -540,6 +542,24 @@ __global__ __launch_bounds__(kThreads) void k_offsets(
     off += tab[i];
   }
   if (threadIdx.x == 0 && total != body_bytes) set_status(prm, ST_FORMAT);
+}
+
+// Totals of the bins and subbin parts over all chunks (statistics only).
+__global__ __launch_bounds__(kThreads) void k_sum_parts(const uint32_t* parts,
+                                                        uint32_t nch, Params* prm) {
+  __shared__ uint64_t sh[kWaves + 1];
+  uint64_t b = 0, u = 0;
+  for (uint32_t i = threadIdx.x; i < nch; i += kThreads) {
+    b += parts[2 * i];
+    u += parts[2 * i + 1];
+  }
+  uint64_t tb, tu;
+  block_excl_scan<uint64_t>(b, sh, tb);
+  block_excl_scan<uint64_t>(u, sh, tu);
+  if (threadIdx.x == 0) {
+    prm->bins_bytes = tb;
+    prm->sub_bytes = tu;
+  }
 }
 
 // Lowest representable value of bin b (as an order key): start next to the
@@ -578,12 +598,12 @@ __device__ __forceinline__ bool bin_floor_key(int64_t b, double inv,
 // copy n bytes from global src (4-byte aligned base) to LDS dst
 __device__ __forceinline__ void stage(uint8_t* dst, const uint8_t* src, uint32_t n) {
   const uint32_t nw = (n + 3) / 4;
-  for (uint32_t i = threadIdx.x; i < nw; i += kThreads)
+  for (uint32_t i = threadIdx.x; i < nw; i += kCT)
     ((uint32_t*)dst)[i] = ((const uint32_t*)src)[i];
 }
 
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_decode(
+__global__ __launch_bounds__(kCT) void k_decode(
     const uint8_t* __restrict__ stream, uint32_t n,
     const uint64_t* __restrict__ offsets, Params* prm,
     typename Traits<K>::Raw* __restrict__ out) {
@@ -650,7 +670,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(
   {
     // each thread owns a run of consecutive words; prefix sums modulo 2^(8K)
     const Word M = (Word)0xAAAAAAAAAAAAAAAAull;
-    constexpr uint32_t per = W / kThreads;
+    constexpr uint32_t per = W / kCT;
     const uint32_t b0 = threadIdx.x * per;
     Word loc = 0;
     Word d[per];
@@ -661,7 +681,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(
       loc += d[q];
     }
     uint64_t tot;
-    uint64_t run = block_excl_scan<uint64_t>((uint64_t)loc, sc.scan64, tot);
+    uint64_t run = block_excl_scan<uint64_t, kCW>((uint64_t)loc, sc.scan64, tot);
     Word acc = (Word)run;
 #pragma unroll
     for (uint32_t q = 0; q < per; ++q) {
@@ -680,7 +700,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(
     ok = slen == smid;
     if (ok) {
       uint8_t* mb = (uint8_t*)mid;
-      for (uint32_t i = threadIdx.x; i < smid; i += kThreads) mb[i] = sp[i];
+      for (uint32_t i = threadIdx.x; i < smid; i += kCT) mb[i] = sp[i];
     }
     __syncthreads();
   } else {
@@ -705,7 +725,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(
 
   // reconstruct (Sec. IV-E)
   bool bad = false;
-  for (uint32_t i = threadIdx.x; i < nc; i += kThreads) {
+  for (uint32_t i = threadIdx.x; i < nc; i += kCT) {
     int64_t b;
     if (K == 4) b = (int64_t)(int32_t)((const uint32_t*)Wb)[i];
     else b = (int64_t)((const uint64_t*)Wb)[i];
@@ -716,7 +736,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(
       bad = true;
     } else {
       v = Tr::unkey(klo + (int64_t)s);
-      if (q_bin(Tr::to_double(v), inv) != b) bad = true;
+      if (s && q_bin(Tr::to_double(v), inv) != b) bad = true;
     }
     out[p0 + i] = v;
   }
@@ -727,23 +747,29 @@ __global__ __launch_bounds__(kThreads) void k_decode(
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_encode(int dtype, uint32_t n, const void* bins,
-                         const uint32_t* sub, uint64_t* lookback, Params* prm,
-                         uint8_t* stream, size_t cap, hipStream_t s) {
+                         const uint32_t* sub, uint64_t* lookback, uint32_t* parts,
+                         Params* prm, uint8_t* stream, size_t cap, hipStream_t s) {
   uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
   uint32_t nch = (n + W - 1) / W;
   if (dtype == 0)
-    k_encode<4><<<nch, kThreads, 0, s>>>(n, (const int32_t*)bins, sub, lookback, prm,
-                                         stream, cap, nch);
+    k_encode<4><<<nch, kCT, 0, s>>>(n, (const int32_t*)bins, sub, lookback, parts, prm,
+                                    stream, cap, nch);
   else
-    k_encode<8><<<nch, kThreads, 0, s>>>(n, (const int64_t*)bins, sub, lookback, prm,
-                                         stream, cap, nch);
+    k_encode<8><<<nch, kCT, 0, s>>>(n, (const int64_t*)bins, sub, lookback, parts, prm,
+                                    stream, cap, nch);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const uint32_t* parts, uint32_t nch, Params* prm,
+                            hipStream_t s) {
+  k_sum_parts<<<1, kThreads, 0, s>>>(parts, nch, prm);
   return hipGetLastError();
 }
 
 hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
                           uint64_t body_bytes, uint64_t* offsets, Params* prm,
                           hipStream_t s) {
-  k_offsets<<<1, kThreads, 0, s>>>(stream, nch, body_bytes, offsets, prm);
+  k_offsets<<<1, kCT, 0, s>>>(stream, nch, body_bytes, offsets, prm);
   return hipGetLastError();
 }
 
@@ -753,9 +779,9 @@ hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
   uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
   uint32_t nch = (n + W - 1) / W;
   if (dtype == 0)
-    k_decode<4><<<nch, kThreads, 0, s>>>(stream, n, offsets, prm, (uint32_t*)field);
+    k_decode<4><<<nch, kCT, 0, s>>>(stream, n, offsets, prm, (uint32_t*)field);
   else
-    k_decode<8><<<nch, kThreads, 0, s>>>(stream, n, offsets, prm, (uint64_t*)field);
+    k_decode<8><<<nch, kCT, 0, s>>>(stream, n, offsets, prm, (uint64_t*)field);
   return hipGetLastError();
 }
 

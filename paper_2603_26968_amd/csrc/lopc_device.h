@@ -60,7 +60,9 @@ __constant__ int8_t c_off[14][3] = {
     {1, 1, 0},  {-1, -1, 0}, {1, 1, 1},  {-1, -1, -1}};
 
 // ------------------------------------------------------------------ scans
-template <typename V>
+// Exclusive scan of v over a block of NW waves; sh needs NW + 1 slots;
+// total receives the block sum.  Every thread of the block must call it.
+template <typename V, int NW = kWaves>
 __device__ V block_excl_scan(V v, V* sh, V& total) {
   V x = v;
 #pragma unroll
@@ -72,16 +74,16 @@ __device__ V block_excl_scan(V v, V* sh, V& total) {
   __syncthreads();
   if (threadIdx.x == 0) {
     V acc = 0;
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < NW; ++w) {
       V t = sh[w];
       sh[w] = acc;
       acc += t;
     }
-    sh[kWaves] = acc;
+    sh[NW] = acc;
   }
   __syncthreads();
   V res = x - v + sh[wave()];
-  total = sh[kWaves];
+  total = sh[NW];
   __syncthreads();
   return res;
 }

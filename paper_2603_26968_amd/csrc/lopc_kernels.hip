@@ -270,6 +270,9 @@ __global__ __launch_bounds__(kThreads) void k_repair(
     }
   }
   edge = __syncthreads_or(edge);
+  // mark the 26 neighbour tiles for the next sweep; one atomic per block
+  // adds the number of newly marked tiles to one of 64 spread counters
+  bool newly = false;
   if (edge && threadIdx.x < 27) {
     int dz = (int)threadIdx.x / 9 - 1, dy = ((int)threadIdx.x / 3) % 3 - 1,
         dx = (int)threadIdx.x % 3 - 1;
@@ -278,8 +281,13 @@ __global__ __launch_bounds__(kThreads) void k_repair(
         ny < tl.nty && nx >= 0 && nx < tl.ntx) {
       uint32_t u = ((uint32_t)nz * tl.nty + ny) * tl.ntx + nx;
       uint32_t prev = atomicMax(&stamp[u], sweep + 1);
-      if (prev < sweep + 1) atomicAdd(&counters[sweep + 2], 1u);
+      newly = prev < sweep + 1;
     }
+  }
+  if (threadIdx.x < 64) {
+    uint64_t m = __ballot(newly);
+    if (threadIdx.x == 0 && m)
+      atomicAdd(&counters[1 + 64 * (sweep & 1) + (t & 63)], (uint32_t)__popcll(m));
   }
 }
 
