@@ -116,6 +116,13 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
 /* Static text for a status code. */
 const char* lopc_strerror(int status);
 
+/* After LOPC_E_HIP: the HIP error string and the failing call of the most
+ * recent failure on this context (*code receives the hipError_t value; may be
+ * NULL).  The text stays valid until the next call on this thread.  Setting
+ * the environment variable LOPC_SYNC_CHECK=1 before lopc_ctx_create makes
+ * every call synchronise after each launch so that a failure names its kernel. */
+const char* lopc_ctx_last_hip_error(lopc_ctx* ctx, int* code);
+
 /* Phase timing (for benchmarks).  When enabled, each compress/decompress call
  * records HIP events on its stream between its phases and, after its final
  * synchronisation, stores the elapsed milliseconds of each phase:

@@ -5,6 +5,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -19,6 +21,10 @@ struct lopc_ctx {
   // pinned host slots for small device-to-host reads
   Params* h_prm;
   uint32_t* h_cnt;
+  // last HIP failure (for diagnostics)
+  int hip_error;
+  char hip_where[64];
+  int sync_check;  // LOPC_SYNC_CHECK=1: synchronise after every launch
   // phase timing
   int timing;
   hipEvent_t ev[8];
@@ -128,6 +134,18 @@ int status_code(uint32_t st) {
     if ((expr) != hipSuccess) return LOPC_E_HIP; \
   } while (0)
 
+// like HIP_TRY, but records the error and the call site in the context
+#define HIP_CTX(c, expr)                                              \
+  do {                                                                \
+    hipError_t e_ = (expr);                                           \
+    if (e_ == hipSuccess && (c)->sync_check) e_ = hipDeviceSynchronize(); \
+    if (e_ != hipSuccess) {                                           \
+      (c)->hip_error = (int)e_;                                       \
+      std::strncpy((c)->hip_where, #expr, sizeof((c)->hip_where) - 1); \
+      return LOPC_E_HIP;                                              \
+    }                                                                 \
+  } while (0)
+
 // event i of the current call (no-op unless timing is on)
 hipError_t mark(lopc_ctx* c, int i, hipStream_t s) {
   return c->timing ? hipEventRecord(c->ev[i], s) : hipSuccess;
@@ -197,6 +215,12 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->h_prm = (Params*)p;
   c->h_cnt = (uint32_t*)((uint8_t*)p + 2048);
   c->timing = 0;
+  c->hip_error = 0;
+  c->hip_where[0] = 0;
+  {
+    const char* v = std::getenv("LOPC_SYNC_CHECK");
+    c->sync_check = v && v[0] == '1';
+  }
   for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
   for (int i = 0; i < LOPC_PHASES; ++i) c->ms[i] = 0.0;
   *out = c;
@@ -219,6 +243,16 @@ int lopc_ctx_set_timing(lopc_ctx* ctx, int enable) {
   }
   ctx->timing = enable ? 1 : 0;
   return LOPC_OK;
+}
+
+const char* lopc_ctx_last_hip_error(lopc_ctx* ctx, int* code) {
+  if (!ctx) return "";
+  if (code) *code = ctx->hip_error;
+  static thread_local char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s (%s)",
+                ctx->hip_error ? hipGetErrorString((hipError_t)ctx->hip_error) : "no error",
+                ctx->hip_where);
+  return buf;
 }
 
 int lopc_ctx_last_timings(lopc_ctx* ctx, double* h_ms, int n) {
@@ -270,7 +304,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   CompressLayout L = compress_layout(s, dtype);
   if (ws_bytes < L.total || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
   hipStream_t hs = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_CTX(ctx, hipSetDevice(ctx->device));
 
   uint8_t* ws = (uint8_t*)d_ws;
   Params* prm = (Params*)(ws + L.prm);
@@ -282,40 +316,40 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   const uint64_t nch = (s.n + W - 1) / W;
   Tiling tl = make_tiling(s.box);
 
-  HIP_TRY(mark(ctx, 0, hs));
-  HIP_TRY(hipMemsetAsync(prm, 0, sizeof(Params), hs));
-  HIP_TRY(hipMemsetAsync(sub, 0, s.n * 4, hs));
-  HIP_TRY(hipMemsetAsync(stamp, 0, (size_t)tl.ntiles * 4, hs));
-  HIP_TRY(hipMemsetAsync(counters, 0, kCounterWords * 4, hs));
-  HIP_TRY(hipMemsetAsync(lookback, 0, nch * 8, hs));
+  HIP_CTX(ctx, mark(ctx, 0, hs));
+  HIP_CTX(ctx, hipMemsetAsync(prm, 0, sizeof(Params), hs));
+  HIP_CTX(ctx, hipMemsetAsync(sub, 0, s.n * 4, hs));
+  HIP_CTX(ctx, hipMemsetAsync(stamp, 0, (size_t)tl.ntiles * 4, hs));
+  HIP_CTX(ctx, hipMemsetAsync(counters, 0, kCounterWords * 4, hs));
+  HIP_CTX(ctx, hipMemsetAsync(lookback, 0, nch * 8, hs));
 
   int nblocks = (int)std::min<uint64_t>(kMinmaxBlocks, (s.n + 2047) / 2048);
   if (nblocks < 1) nblocks = 1;
   if (mode == LOPC_EB_NOA)
-    HIP_TRY(launch_minmax(dtype, d_field, (uint32_t)s.n, (double*)(ws + L.part),
+    HIP_CTX(ctx, launch_minmax(dtype, d_field, (uint32_t)s.n, (double*)(ws + L.part),
                           nblocks, prm, hs));
-  HIP_TRY(launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
+  HIP_CTX(ctx, launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
                         nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
                         s.d, hs));
-  HIP_TRY(mark(ctx, 1, hs));
-  HIP_TRY(launch_quant_mask(dtype, d_field, s.box, prm, ws + L.bins,
+  HIP_CTX(ctx, mark(ctx, 1, hs));
+  HIP_CTX(ctx, launch_quant_mask(dtype, d_field, s.box, prm, ws + L.bins,
                             (uint16_t*)(ws + L.mask), hs));
-  HIP_TRY(mark(ctx, 2, hs));
+  HIP_CTX(ctx, mark(ctx, 2, hs));
 
   // repair: sweep the marked tiles until no tile is marked (Alg. 1 loop)
   uint64_t sweeps = 0, active = tl.ntiles;
   for (uint32_t sw = 0;; ++sw) {
-    HIP_TRY(launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
+    HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
                           counters, sw, hs));
     ++sweeps;
     uint32_t* bank = counters + 1 + 64 * (sw & 1);
-    HIP_TRY(hipMemcpyAsync(ctx->h_cnt, bank, 64 * 4, hipMemcpyDeviceToHost, hs));
-    HIP_TRY(hipMemcpyAsync(ctx->h_cnt + 64, counters, 4, hipMemcpyDeviceToHost, hs));
-    HIP_TRY(hipMemsetAsync(bank, 0, 64 * 4, hs));  // reused two sweeps later
+    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_cnt, bank, 64 * 4, hipMemcpyDeviceToHost, hs));
+    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_cnt + 64, counters, 4, hipMemcpyDeviceToHost, hs));
+    HIP_CTX(ctx, hipMemsetAsync(bank, 0, 64 * 4, hs));  // reused two sweeps later
     if (sw == 0)
-      HIP_TRY(hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4,
+      HIP_CTX(ctx, hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4,
                              hipMemcpyDeviceToHost, hs));
-    HIP_TRY(hipStreamSynchronize(hs));
+    HIP_CTX(ctx, hipStreamSynchronize(hs));
     if (ctx->h_cnt[64]) return LOPC_E_INTERNAL;
     if (sw == 0) {
       int code = status_code(ctx->h_prm->status);
@@ -331,15 +365,15 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     if (sw + 1 >= kMaxSweeps) return LOPC_E_INTERNAL;
   }
 
-  HIP_TRY(mark(ctx, 3, hs));
-  HIP_TRY(launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
+  HIP_CTX(ctx, mark(ctx, 3, hs));
+  HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
                         (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream,
                         stream_cap, hs));
-  HIP_TRY(mark(ctx, 4, hs));
+  HIP_CTX(ctx, mark(ctx, 4, hs));
   if (h_stats)
-    HIP_TRY(launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
-  HIP_TRY(hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
-  HIP_TRY(hipStreamSynchronize(hs));
+    HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+  HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
+  HIP_CTX(ctx, hipStreamSynchronize(hs));
   if (ctx->timing) {
     ctx->ms[LOPC_PHASE_RANGE] = span(ctx, 0, 1);
     ctx->ms[LOPC_PHASE_QUANT] = span(ctx, 1, 2);
@@ -398,10 +432,10 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
   if (!ctx || !d_stream || !d_field || !d_ws) return LOPC_E_ARG;
   if (stream_size < kHeaderBytes) return LOPC_E_FORMAT;
   hipStream_t hs = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_CTX(ctx, hipSetDevice(ctx->device));
   uint8_t* hh = (uint8_t*)ctx->h_prm;  // pinned staging for the header
-  HIP_TRY(hipMemcpyAsync(hh, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, hs));
-  HIP_TRY(hipStreamSynchronize(hs));
+  HIP_CTX(ctx, hipMemcpyAsync(hh, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, hs));
+  HIP_CTX(ctx, hipStreamSynchronize(hs));
   uint8_t hdr[kHeaderBytes];
   std::memcpy(hdr, hh, kHeaderBytes);
   int dtype, ndim;
@@ -419,16 +453,16 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
   uint8_t* ws = (uint8_t*)d_ws;
   Params* prm = (Params*)ws;
   uint64_t* offsets = (uint64_t*)(ws + align256(sizeof(Params)));
-  HIP_TRY(hipMemsetAsync(prm, 0, sizeof(Params), hs));
-  HIP_TRY(mark(ctx, 5, hs));
-  HIP_TRY(launch_offsets((const uint8_t*)d_stream, (uint32_t)nch,
+  HIP_CTX(ctx, hipMemsetAsync(prm, 0, sizeof(Params), hs));
+  HIP_CTX(ctx, mark(ctx, 5, hs));
+  HIP_CTX(ctx, launch_offsets((const uint8_t*)d_stream, (uint32_t)nch,
                          stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs));
-  HIP_TRY(mark(ctx, 6, hs));
-  HIP_TRY(launch_decode(dtype, (const uint8_t*)d_stream, (uint32_t)s.n, offsets,
+  HIP_CTX(ctx, mark(ctx, 6, hs));
+  HIP_CTX(ctx, launch_decode(dtype, (const uint8_t*)d_stream, (uint32_t)s.n, offsets,
                         prm, d_field, hs));
-  HIP_TRY(mark(ctx, 7, hs));
-  HIP_TRY(hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4, hipMemcpyDeviceToHost, hs));
-  HIP_TRY(hipStreamSynchronize(hs));
+  HIP_CTX(ctx, mark(ctx, 7, hs));
+  HIP_CTX(ctx, hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4, hipMemcpyDeviceToHost, hs));
+  HIP_CTX(ctx, hipStreamSynchronize(hs));
   if (ctx->timing) {
     ctx->ms[LOPC_PHASE_OFFSETS] = span(ctx, 5, 6);
     ctx->ms[LOPC_PHASE_DECODE] = span(ctx, 6, 7);

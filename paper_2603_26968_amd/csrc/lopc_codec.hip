@@ -769,7 +769,7 @@ hipError_t launch_sum_parts(const uint32_t* parts, uint32_t nch, Params* prm,
 hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
                           uint64_t body_bytes, uint64_t* offsets, Params* prm,
                           hipStream_t s) {
-  k_offsets<<<1, kCT, 0, s>>>(stream, nch, body_bytes, offsets, prm);
+  k_offsets<<<1, kThreads, 0, s>>>(stream, nch, body_bytes, offsets, prm);
   return hipGetLastError();
 }
 

@@ -29,13 +29,15 @@ HEADER_BYTES = 64
 EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_workspace_size", "lopc_compress", "lopc_stream_info",
            "lopc_decompress", "lopc_strerror", "lopc_ctx_set_timing",
-           "lopc_ctx_last_timings")
+           "lopc_ctx_last_timings", "lopc_ctx_last_hip_error")
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
 
 class LopcError(RuntimeError):
-    def __init__(self, code: int, what: str = ""):
+    def __init__(self, code: int, what: str = "", ctx: int | None = None):
         msg = load().lopc_strerror(code).decode()
+        if code == LOPC_E_HIP and ctx:
+            msg += ": " + load().lopc_ctx_last_hip_error(ctx, None).decode()
         super().__init__(f"{what}: {msg} (status {code})" if what else msg)
         self.code = code
 
@@ -87,6 +89,8 @@ def load() -> ctypes.CDLL:
     L.lopc_ctx_set_timing.restype = ci
     L.lopc_ctx_last_timings.argtypes = [vp, ctypes.POINTER(cd), ci]
     L.lopc_ctx_last_timings.restype = ci
+    L.lopc_ctx_last_hip_error.argtypes = [vp, ctypes.POINTER(ci)]
+    L.lopc_ctx_last_hip_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -232,7 +236,7 @@ def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = Fals
                                   _mode(mode), out.data_ptr(), out.numel(),
                                   workspace.data_ptr(), workspace.numel(), s)
     if st:
-        raise LopcError(st, "lopc_compress")
+        raise LopcError(st, "lopc_compress", ctx)
     res = out[:size]
     return (res, stt.as_dict()) if stats else res
 
@@ -257,7 +261,7 @@ def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
                          out.numel() * out.element_size(), workspace.data_ptr(),
                          workspace.numel(), s)
     if st:
-        raise LopcError(st, "lopc_decompress")
+        raise LopcError(st, "lopc_decompress", ctx)
     return out
 
 
