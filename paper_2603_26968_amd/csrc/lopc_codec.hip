@@ -10,7 +10,10 @@
 //
 // Chunk offsets in the stream come from a decoupled look-back over a
 // ticket-ordered chunk queue (a workgroup only waits for chunks that started
-// before it).
+// before it).  A look-back word packs its state and size into 64 bits, so it
+// carries no other data and relaxed device-scope atomics suffice: release or
+// acquire at that scope would write back / invalidate the per-XCD L2 on every
+// publication.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -477,15 +480,15 @@ __global__ __launch_bounds__(kCT) void k_encode(
   if (threadIdx.x == 0) {
     uint64_t excl = 0;
     if (c == 0) {
-      __hip_atomic_store(&lookback[0], kLbInc | size, __ATOMIC_RELEASE,
+      __hip_atomic_store(&lookback[0], kLbInc | size, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      __hip_atomic_store(&lookback[c], kLbAgg | size, __ATOMIC_RELEASE,
+      __hip_atomic_store(&lookback[c], kLbAgg | size, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
       int64_t j = (int64_t)c - 1;
       uint32_t spins = 0;
       while (j >= 0) {
-        uint64_t v = __hip_atomic_load(&lookback[j], __ATOMIC_ACQUIRE,
+        uint64_t v = __hip_atomic_load(&lookback[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
         uint64_t st = v & ~kLbVal;
         if (st == 0) {
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(kCT) void k_encode(
         if (st == kLbInc) break;
         --j;
       }
-      __hip_atomic_store(&lookback[c], kLbInc | (excl + size), __ATOMIC_RELEASE,
+      __hip_atomic_store(&lookback[c], kLbInc | (excl + size), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     }
     s_excl = excl;
