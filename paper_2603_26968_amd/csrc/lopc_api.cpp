@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -85,12 +86,13 @@ Tiling make_tiling(const Box& b) {
 }
 
 struct CompressLayout {
-  size_t prm, part, bins, mask, sub, stamp, counters, lookback, parts, total;
+  size_t prm, counters, stamp, lookback, parts, zero_end;  // zeroed prefix
+  size_t part, bins, mask, sub, total;
 };
 
-// repair counters: [0] internal error flag; then two banks (sweep parity) of
-// 64 spread counters of tiles marked for the next sweep
-constexpr size_t kCounterWords = 1 + 2 * 64;
+// repair counters: [0] internal error flag, [1 + s % 64] tiles marked for
+// sweep s (a ring the host clears after reading)
+constexpr size_t kCounterWords = 1 + 64;
 
 CompressLayout compress_layout(const Shape& s, int dtype) {
   const size_t k = dtype == 0 ? 4 : 8;
@@ -100,14 +102,15 @@ CompressLayout compress_layout(const Shape& s, int dtype) {
   CompressLayout L;
   size_t o = 0;
   L.prm = o; o += align256(sizeof(Params));
+  L.counters = o; o += align256(kCounterWords * 4);
+  L.stamp = o; o += align256((size_t)t.ntiles * 4);
+  L.lookback = o; o += align256(nch * 8);
+  L.parts = o; o += align256(nch * 8);
+  L.zero_end = o;
   L.part = o; o += align256(16 * kMinmaxBlocks);
   L.bins = o; o += align256(s.n * k);
   L.mask = o; o += align256(s.n * 2);
   L.sub = o; o += align256(s.n * 4);
-  L.stamp = o; o += align256((size_t)t.ntiles * 4);
-  L.counters = o; o += align256(kCounterWords * 4);
-  L.lookback = o; o += align256(nch * 8);
-  L.parts = o; o += align256(nch * 8);
   L.total = o;
   return L;
 }
@@ -317,52 +320,63 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   Tiling tl = make_tiling(s.box);
 
   HIP_CTX(ctx, mark(ctx, 0, hs));
-  HIP_CTX(ctx, hipMemsetAsync(prm, 0, sizeof(Params), hs));
-  HIP_CTX(ctx, hipMemsetAsync(sub, 0, s.n * 4, hs));
-  HIP_CTX(ctx, hipMemsetAsync(stamp, 0, (size_t)tl.ntiles * 4, hs));
-  HIP_CTX(ctx, hipMemsetAsync(counters, 0, kCounterWords * 4, hs));
-  HIP_CTX(ctx, hipMemsetAsync(lookback, 0, nch * 8, hs));
+  HIP_CTX(ctx, hipMemsetAsync(ws, 0, L.zero_end, hs));
 
   int nblocks = (int)std::min<uint64_t>(kMinmaxBlocks, (s.n + 2047) / 2048);
   if (nblocks < 1) nblocks = 1;
   if (mode == LOPC_EB_NOA)
     HIP_CTX(ctx, launch_minmax(dtype, d_field, (uint32_t)s.n, (double*)(ws + L.part),
-                          nblocks, prm, hs));
+                               nblocks, prm, hs));
   HIP_CTX(ctx, launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
-                        nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
-                        s.d, hs));
+                             nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
+                             s.d, hs));
   HIP_CTX(ctx, mark(ctx, 1, hs));
-  HIP_CTX(ctx, launch_quant_mask(dtype, d_field, s.box, prm, ws + L.bins,
-                            (uint16_t*)(ws + L.mask), hs));
+  // quantize + order flags + first relaxation, fused per tile
+  HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
+                            (uint16_t*)(ws + L.mask), sub, stamp, counters, hs));
   HIP_CTX(ctx, mark(ctx, 2, hs));
 
-  // repair: sweep the marked tiles until no tile is marked (Alg. 1 loop)
-  uint64_t sweeps = 0, active = tl.ntiles;
-  for (uint32_t sw = 0;; ++sw) {
-    HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
-                          counters, sw, hs));
-    ++sweeps;
-    uint32_t* bank = counters + 1 + 64 * (sw & 1);
-    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_cnt, bank, 64 * 4, hipMemcpyDeviceToHost, hs));
-    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_cnt + 64, counters, 4, hipMemcpyDeviceToHost, hs));
-    HIP_CTX(ctx, hipMemsetAsync(bank, 0, 64 * 4, hs));  // reused two sweeps later
-    if (sw == 0)
-      HIP_CTX(ctx, hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4,
-                             hipMemcpyDeviceToHost, hs));
+  // repair sweeps (Alg. 1 loop at tile granularity), enqueued in batches; a
+  // sweep with no marked tile costs one empty launch.  One read of the status
+  // and the per-sweep counters per batch.
+  uint64_t sweeps = 1, active = tl.ntiles;
+  uint32_t next = 1;  // first sweep of the next batch
+  uint32_t batch = 2;
+  const size_t report = L.counters + kCounterWords * 4;  // Params + counters
+  for (;;) {
+    for (uint32_t b = 0; b < batch; ++b)
+      HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
+                                 counters, next + b, hs));
+    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
     HIP_CTX(ctx, hipStreamSynchronize(hs));
-    if (ctx->h_cnt[64]) return LOPC_E_INTERNAL;
-    if (sw == 0) {
-      int code = status_code(ctx->h_prm->status);
-      if (code != LOPC_OK) {
-        *h_stream_size = 0;
-        return code;
+    const uint32_t* hc = (const uint32_t*)((const uint8_t*)ctx->h_prm + L.counters);
+    if (hc[0]) return LOPC_E_INTERNAL;
+    int code = status_code(ctx->h_prm->status);
+    if (code != LOPC_OK && code != LOPC_E_CAPACITY) {
+      *h_stream_size = 0;
+      return code;
+    }
+    // marks for sweep t are hc[1 + t % 64]; sweep t ran iff they are nonzero
+    bool done = false;
+    for (uint32_t t = next; t <= next + batch; ++t) {
+      const uint32_t m = hc[1 + (t & 63)];
+      if (m == 0) {
+        done = true;
+        break;
+      }
+      if (t < next + batch) {
+        ++sweeps;
+        active += m;
       }
     }
-    uint64_t next = 0;
-    for (int i = 0; i < 64; ++i) next += ctx->h_cnt[i];
-    if (next == 0) break;
-    active += next;
-    if (sw + 1 >= kMaxSweeps) return LOPC_E_INTERNAL;
+    if (done) break;
+    // clear the ring slots consumed by this batch (marks for sweep next+batch
+    // stay: the next batch starts with it)
+    for (uint32_t t = next; t < next + batch; ++t)
+      HIP_CTX(ctx, hipMemsetAsync(counters + 1 + (t & 63), 0, 4, hs));
+    next += batch;
+    batch = std::min<uint32_t>(batch * 2, 16);
+    if (next + batch >= kMaxSweeps) return LOPC_E_INTERNAL;
   }
 
   HIP_CTX(ctx, mark(ctx, 3, hs));

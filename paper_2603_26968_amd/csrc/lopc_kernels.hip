@@ -118,125 +118,67 @@ __global__ __launch_bounds__(kThreads) void k_params(
   }
 }
 
-// ------------------------------------------------------------------ a1, a2
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_quant(
-    const typename Traits<K>::Raw* x, uint32_t n, Params* prm,
-    typename Traits<K>::Bin* bins) {
-  using Tr = Traits<K>;
-  const double inv = prm->inv;
-  bool bad_v = false, bad_r = false;
-  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += gridDim.x * kThreads) {
-    typename Tr::Raw u = x[i];
-    bad_v |= !Tr::finite(u);
-    int64_t b = q_bin(Tr::to_double(u), inv);
-    bad_r |= (b > Tr::kBinLimit || b < -Tr::kBinLimit);
-    bins[i] = (typename Tr::Bin)b;
-  }
-  if (bad_v) set_status(prm, ST_NONFINITE);
-  if (bad_r) set_status(prm, ST_RANGE);
-}
-
-// One thread per point: bit j of mask[p] is set when neighbour p + off[j]
-// is in the grid, has the same bin, and comes before p in the order
-// (value, index) -- the flags of Alg. 1.
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_mask(
-    const typename Traits<K>::Raw* x, Box box,
-    const typename Traits<K>::Bin* bins, uint16_t* mask) {
-  using Tr = Traits<K>;
-  const int ix = blockIdx.x * kThreads + threadIdx.x;
-  if (ix >= box.nx) return;
-  for (int64_t row = blockIdx.y; row < (int64_t)box.nz * box.ny;
-       row += gridDim.y) {
-    const int iz = (int)(row / box.ny), iy = (int)(row % box.ny);
-    const uint32_t p = (uint32_t)(row * box.nx + ix);
-    const int64_t kp = Tr::key(x[p]);
-    const typename Tr::Bin bp = bins[p];
-    uint32_t m = 0;
-#pragma unroll
-    for (int j = 0; j < 14; ++j) {
-      int z = iz + c_off[j][0], y = iy + c_off[j][1], xx = ix + c_off[j][2];
-      if (z < 0 || z >= box.nz || y < 0 || y >= box.ny || xx < 0 || xx >= box.nx)
-        continue;
-      uint32_t q = (uint32_t)(((int64_t)z * box.ny + y) * box.nx + xx);
-      if (bins[q] != bp) continue;
-      int64_t kq = Tr::key(x[q]);
-      bool below = kq < kp || (kq == kp && (j & 1));  // odd j: lower index
-      if (below) m |= 1u << j;
-    }
-    mask[p] = (uint16_t)m;
-  }
-}
-
 // ------------------------------------------------------------------ a3
-// One workgroup per tile: subbins of the tile plus a one-point halo in LDS,
-// relaxed in place (monotone, so concurrent reads of stale values are
-// harmless) until nothing changes; halo values come from the global array
-// and are treated as fixed.  A tile whose boundary changed marks its 26
-// neighbour tiles for the next sweep; the host sweeps until no tile is
-// marked.  Every subbin only grows and stays below the least fixed point,
-// so the result is that fixed point, whatever the order of tiles.
+// Tiles of the subbin repair.  A workgroup owns a TZ x TY x TX tile and keeps
+// the subbins of the tile plus a one-point halo in LDS.  It relaxes them in
+// place until nothing changes (the raising rule of Alg. 2 with the halo held
+// fixed; every value only grows and stays below the least fixed point, so
+// concurrent reads of stale values are harmless), writes back what changed,
+// and, if a boundary value changed, marks the 26 neighbour tiles for the next
+// sweep.  Sweeps repeat until no tile is marked; the result is the least
+// fixed point whatever the order in which tiles run.
 template <int TZ, int TY, int TX>
-__global__ __launch_bounds__(kThreads) void k_repair(
-    Box box, Tiling tl, const uint16_t* __restrict__ mask,
-    uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
-    uint32_t sweep) {
-  constexpr int ZO = TZ == 1 ? 0 : 1;  // 2D tiles carry no z halo
-  constexpr int HZ = TZ + 2 * ZO, HY = TY + 2, HX = TX + 2;
-  constexpr int NPT = TZ * TY * TX;
-  constexpr int PER = NPT / kThreads;
+struct TileGeom {
+  static constexpr int ZO = TZ == 1 ? 0 : 1;  // 2D tiles carry no z halo
+  static constexpr int HZ = TZ + 2 * ZO, HY = TY + 2, HX = TX + 2;
+  static constexpr int H = HZ * HY * HX;
+  static constexpr int NPT = TZ * TY * TX;
+  static constexpr int PER = NPT / kThreads;
   static_assert(NPT % kThreads == 0, "tile must be a multiple of the block");
-  __shared__ uint32_t S[HZ * HY * HX];
-  __shared__ uint16_t Mk[NPT];
-
-  const uint32_t t = blockIdx.x;
-  if (stamp[t] < sweep) return;
-  const int tz = (int)(t / (uint32_t)(tl.nty * tl.ntx));
-  const int ty = (int)((t / (uint32_t)tl.ntx) % (uint32_t)tl.nty);
-  const int tx = (int)(t % (uint32_t)tl.ntx);
-  const int z0 = tz * TZ, y0 = ty * TY, x0 = tx * TX;
-
-  for (int i = threadIdx.x; i < HZ * HY * HX; i += kThreads) {
-    int hz = i / (HY * HX), hy = (i / HX) % HY, hx = i % HX;
-    int z = z0 + hz - ZO, y = y0 + hy - 1, x = x0 + hx - 1;
-    uint32_t v = 0;
-    if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx)
-      v = sub[((int64_t)z * box.ny + y) * box.nx + x];
-    S[i] = v;
-  }
-  for (int i = threadIdx.x; i < NPT; i += kThreads) {
+  // halo-local index of interior point i
+  __device__ static int local(int i) {
     int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
-    int z = z0 + iz, y = y0 + iy, x = x0 + ix;
-    uint16_t m = 0;
-    if (z < box.nz && y < box.ny && x < box.nx)
-      m = mask[((int64_t)z * box.ny + y) * box.nx + x];
-    Mk[i] = m;
+    return ((iz + ZO) * HY + iy + 1) * HX + ix + 1;
   }
+  __device__ static bool on_edge(int i) {
+    int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
+    return (TZ > 1 && (iz == 0 || iz == TZ - 1)) || iy == 0 || iy == TY - 1 ||
+           ix == 0 || ix == TX - 1;
+  }
+};
+
+struct TileCoord {
+  int tz, ty, tx, z0, y0, x0;
+};
+
+template <int TZ, int TY, int TX>
+__device__ __forceinline__ TileCoord tile_coord(uint32_t t, const Tiling& tl) {
+  TileCoord c;
+  c.tz = (int)(t / (uint32_t)(tl.nty * tl.ntx));
+  c.ty = (int)((t / (uint32_t)tl.ntx) % (uint32_t)tl.nty);
+  c.tx = (int)(t % (uint32_t)tl.ntx);
+  c.z0 = c.tz * TZ;
+  c.y0 = c.ty * TY;
+  c.x0 = c.tx * TX;
+  return c;
+}
+
+// local fixed point of the tile (masks of the owned points in registers)
+template <int TZ, int TY, int TX>
+__device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters) {
+  using G = TileGeom<TZ, TY, TX>;
   int doff[14];
 #pragma unroll
   for (int j = 0; j < 14; ++j)
-    doff[j] = c_off[j][0] * (HY * HX) + c_off[j][1] * HX + c_off[j][2];
-  __syncthreads();
-
-  uint32_t old[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    int i = threadIdx.x + k * kThreads;
-    int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
-    old[k] = S[((iz + ZO) * HY + iy + 1) * HX + ix + 1];
-  }
+    doff[j] = c_off[j][0] * (G::HY * G::HX) + c_off[j][1] * G::HX + c_off[j][2];
   int iters = 0;
   for (;;) {
     int changed = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      int i = threadIdx.x + k * kThreads;
-      uint32_t m = Mk[i];
+    for (int k = 0; k < G::PER; ++k) {
+      uint32_t m = mk[k];
       if (!m) continue;
-      int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
-      int li = ((iz + ZO) * HY + iy + 1) * HX + ix + 1;
+      const int li = G::local(threadIdx.x + k * kThreads);
       uint32_t cur = S[li], best = cur;
       while (m) {
         int j = __builtin_ctz(m);
@@ -250,45 +192,173 @@ __global__ __launch_bounds__(kThreads) void k_repair(
       }
     }
     if (!__syncthreads_or(changed)) break;
-    if (++iters > NPT + 2) {  // unreachable: the order inside a tile is acyclic
+    if (++iters > G::NPT + 2) {  // unreachable: the order inside a tile is acyclic
       if (threadIdx.x == 0) atomicOr(&counters[0], 1u);
       break;
     }
   }
-  int edge = 0;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    int i = threadIdx.x + k * kThreads;
-    int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
-    uint32_t v = S[((iz + ZO) * HY + iy + 1) * HX + ix + 1];
-    if (v != old[k]) {
-      int z = z0 + iz, y = y0 + iy, x = x0 + ix;
-      sub[((int64_t)z * box.ny + y) * box.nx + x] = v;
-      if ((TZ > 1 && (iz == 0 || iz == TZ - 1)) || iy == 0 || iy == TY - 1 ||
-          ix == 0 || ix == TX - 1)
-        edge = 1;
-    }
-  }
-  edge = __syncthreads_or(edge);
-  // mark the 26 neighbour tiles for the next sweep; one atomic per block
-  // adds the number of newly marked tiles to one of 64 spread counters
+}
+
+// mark the 26 neighbour tiles for sweep `next`; one atomic per block adds
+// the number of newly marked tiles to counters[1 + next % 64]
+__device__ void mark_neighbours(bool edge, const TileCoord& c, const Tiling& tl,
+                                uint32_t* stamp, uint32_t* counters,
+                                uint32_t next) {
   bool newly = false;
   if (edge && threadIdx.x < 27) {
     int dz = (int)threadIdx.x / 9 - 1, dy = ((int)threadIdx.x / 3) % 3 - 1,
         dx = (int)threadIdx.x % 3 - 1;
-    int nz = tz + dz, ny = ty + dy, nx = tx + dx;
+    int nz = c.tz + dz, ny = c.ty + dy, nx = c.tx + dx;
     if ((dz | dy | dx) != 0 && nz >= 0 && nz < tl.ntz && ny >= 0 &&
         ny < tl.nty && nx >= 0 && nx < tl.ntx) {
       uint32_t u = ((uint32_t)nz * tl.nty + ny) * tl.ntx + nx;
-      uint32_t prev = atomicMax(&stamp[u], sweep + 1);
-      newly = prev < sweep + 1;
+      uint32_t prev = atomicMax(&stamp[u], next);
+      newly = prev < next;
     }
   }
   if (threadIdx.x < 64) {
     uint64_t m = __ballot(newly);
     if (threadIdx.x == 0 && m)
-      atomicAdd(&counters[1 + 64 * (sweep & 1) + (t & 63)], (uint32_t)__popcll(m));
+      atomicAdd(&counters[1 + (next & 63)], (uint32_t)__popcll(m));
   }
+}
+
+// First pass, fused: quantize the tile and its halo (a1), build the order
+// flags of the owned points (a2, the flags of Alg. 1), write bins and flags,
+// then relax with halo subbins 0 (the first sweep of a3).
+template <int K, int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_tile0(
+    const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl,
+    Params* prm, typename Traits<K>::Bin* __restrict__ bins,
+    uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
+    uint32_t* counters) {
+  using Tr = Traits<K>;
+  using G = TileGeom<TZ, TY, TX>;
+  using Key = typename Tr::Bin;  // keys fit the signed type of the bins
+  using Bin = typename Tr::Bin;
+  constexpr int kKB = G::H * (int)(sizeof(Key) + sizeof(Bin));
+  constexpr int kBytes = kKB > G::H * 4 ? kKB : G::H * 4;
+  __shared__ __attribute__((aligned(16))) uint8_t buf[kBytes];
+  Key* KY = (Key*)buf;
+  Bin* BN = (Bin*)(buf + G::H * sizeof(Key));
+  uint32_t* S = (uint32_t*)buf;  // reused once the flags are built
+
+  const TileCoord c = tile_coord<TZ, TY, TX>(blockIdx.x, tl);
+  const double inv = prm->inv;
+  bool bad_v = false, bad_r = false;
+  for (int i = threadIdx.x; i < G::H; i += kThreads) {
+    int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+    int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
+    Key k = 0;
+    Bin b = 0;
+    if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx) {
+      typename Tr::Raw u = x[((int64_t)z * box.ny + y) * box.nx + xx];
+      bad_v |= !Tr::finite(u);
+      int64_t q = q_bin(Tr::to_double(u), inv);
+      bad_r |= q > Tr::kBinLimit || q < -Tr::kBinLimit;
+      k = (Key)Tr::key(u);
+      b = (Bin)q;
+    }
+    KY[i] = k;
+    BN[i] = b;
+  }
+  if (bad_v) set_status(prm, ST_NONFINITE);
+  if (bad_r) set_status(prm, ST_RANGE);
+  __syncthreads();
+
+  uint16_t mk[G::PER];
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    const int i = threadIdx.x + k * kThreads;
+    const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
+    const int z = c.z0 + iz, y = c.y0 + iy, xx = c.x0 + ix;
+    uint32_t m = 0;
+    if (z < box.nz && y < box.ny && xx < box.nx) {
+      const int li = G::local(i);
+      const Key kp = KY[li];
+      const Bin bp = BN[li];
+#pragma unroll
+      for (int j = 0; j < 14; ++j) {
+        int zz = z + c_off[j][0], yy = y + c_off[j][1], xq = xx + c_off[j][2];
+        if (zz < 0 || zz >= box.nz || yy < 0 || yy >= box.ny || xq < 0 || xq >= box.nx)
+          continue;
+        const int ln = li + c_off[j][0] * (G::HY * G::HX) + c_off[j][1] * G::HX + c_off[j][2];
+        if (BN[ln] != bp) continue;
+        const Key kq = KY[ln];
+        if (kq < kp || (kq == kp && (j & 1))) m |= 1u << j;  // odd j: lower index
+      }
+      const int64_t g = ((int64_t)z * box.ny + y) * box.nx + xx;
+      bins[g] = bp;
+      mask[g] = (uint16_t)m;
+    }
+    mk[k] = (uint16_t)m;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < G::H; i += kThreads) S[i] = 0;
+  __syncthreads();
+  relax<TZ, TY, TX>(S, mk, counters);
+  int edge = 0;
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    const int i = threadIdx.x + k * kThreads;
+    const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
+    const int z = c.z0 + iz, y = c.y0 + iy, xx = c.x0 + ix;
+    if (z < box.nz && y < box.ny && xx < box.nx) {
+      const uint32_t v = S[G::local(i)];
+      sub[((int64_t)z * box.ny + y) * box.nx + xx] = v;
+      if (v && G::on_edge(i)) edge = 1;
+    }
+  }
+  edge = __syncthreads_or(edge);
+  mark_neighbours(edge, c, tl, stamp, counters, 1);
+}
+
+// Later sweeps: tiles marked for this sweep reload their halo and relax.
+template <int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_repair(
+    Box box, Tiling tl, const uint16_t* __restrict__ mask,
+    uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
+    uint32_t sweep) {
+  using G = TileGeom<TZ, TY, TX>;
+  __shared__ uint32_t S[G::H];
+  const uint32_t t = blockIdx.x;
+  if (stamp[t] < sweep) return;
+  const TileCoord c = tile_coord<TZ, TY, TX>(t, tl);
+  for (int i = threadIdx.x; i < G::H; i += kThreads) {
+    int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+    int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, x = c.x0 + hx - 1;
+    uint32_t v = 0;
+    if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx)
+      v = sub[((int64_t)z * box.ny + y) * box.nx + x];
+    S[i] = v;
+  }
+  uint16_t mk[G::PER];
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    const int i = threadIdx.x + k * kThreads;
+    const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
+    const int z = c.z0 + iz, y = c.y0 + iy, x = c.x0 + ix;
+    mk[k] = (z < box.nz && y < box.ny && x < box.nx)
+                ? mask[((int64_t)z * box.ny + y) * box.nx + x] : (uint16_t)0;
+  }
+  __syncthreads();
+  uint32_t old[G::PER];
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) old[k] = S[G::local(threadIdx.x + k * kThreads)];
+  relax<TZ, TY, TX>(S, mk, counters);
+  int edge = 0;
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    const int i = threadIdx.x + k * kThreads;
+    const uint32_t v = S[G::local(i)];
+    if (v != old[k]) {
+      const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
+      sub[((int64_t)(c.z0 + iz) * box.ny + c.y0 + iy) * box.nx + c.x0 + ix] = v;
+      if (G::on_edge(i)) edge = 1;
+    }
+  }
+  edge = __syncthreads_or(edge);
+  mark_neighbours(edge, c, tl, stamp, counters, sweep + 1);
 }
 
 }  // namespace
@@ -316,17 +386,23 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
   return hipGetLastError();
 }
 
-hipError_t launch_quant_mask(int dtype, const void* x, Box box, Params* prm,
-                             void* bins, uint16_t* mask, hipStream_t s) {
-  int qb = (int)std::min<uint64_t>(8192, ((uint64_t)box.n + kThreads - 1) / kThreads);
-  dim3 mg((box.nx + kThreads - 1) / kThreads,
-          (unsigned)std::min<int64_t>((int64_t)box.nz * box.ny, 65535), 1);
-  if (dtype == 0) {
-    k_quant<4><<<qb, kThreads, 0, s>>>((const uint32_t*)x, box.n, prm, (int32_t*)bins);
-    k_mask<4><<<mg, kThreads, 0, s>>>((const uint32_t*)x, box, (const int32_t*)bins, mask);
+hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm,
+                        void* bins, uint16_t* mask, uint32_t* sub, uint32_t* stamp,
+                        uint32_t* counters, hipStream_t s) {
+  if (t.tz == 1) {
+    if (dtype == 0)
+      k_tile0<4, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
+                                                           (int32_t*)bins, mask, sub, stamp, counters);
+    else
+      k_tile0<8, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
+                                                           (int64_t*)bins, mask, sub, stamp, counters);
   } else {
-    k_quant<8><<<qb, kThreads, 0, s>>>((const uint64_t*)x, box.n, prm, (int64_t*)bins);
-    k_mask<8><<<mg, kThreads, 0, s>>>((const uint64_t*)x, box, (const int64_t*)bins, mask);
+    if (dtype == 0)
+      k_tile0<4, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
+                                                          (int32_t*)bins, mask, sub, stamp, counters);
+    else
+      k_tile0<8, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
+                                                          (int64_t*)bins, mask, sub, stamp, counters);
   }
   return hipGetLastError();
 }
