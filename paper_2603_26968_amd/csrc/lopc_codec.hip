@@ -38,7 +38,6 @@ struct Scratch {
   uint8_t kp0[kMaxUnits];  // kept bytes of the level-1 bitmap
   uint8_t kp1[256];
   uint8_t kp2[32];
-  uint16_t off[kMaxUnits];  // per-unit exclusive offset within its round
   uint32_t rpre[kMaxRounds + 1];  // per-round totals, then exclusive prefix
   uint32_t scan[kCW + 1];
   uint32_t nkept[4];
@@ -186,7 +185,6 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
       if (lane() == 0) *(uint64_t*)(sc.lv0 + r * 8) = m;
     }
     const uint32_t inc = wave_incl_scan(ci);
-    if (u < NU) sc.off[u] = (uint16_t)(inc - ci);
     if (lane() == 63) sc.rpre[r] = inc;
   }
   __syncthreads();
@@ -217,9 +215,13 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
   }
   for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
+    const uint64_t v = u < NU ? U[u] : 0ull;
+    uint32_t ci;
+    if (W == 1) ci = __popc(nonzero_bytes(v));
+    else if (W == 4) ci = ((uint32_t)v != 0u) + ((v >> 32) != 0ull);
+    else ci = v != 0ull;
+    uint32_t d = pos + W * (sc.rpre[r] + wave_incl_scan(ci) - ci);
     if (u >= NU) continue;
-    const uint64_t v = U[u];
-    uint32_t d = pos + W * (sc.rpre[r] + sc.off[u]);
     if (W == 1) {
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
@@ -278,7 +280,6 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
     }
     const uint32_t ci = __popc(mi);
     const uint32_t inc = wave_incl_scan(ci);
-    if (u < NU) sc.off[u] = (uint16_t)(inc - ci);
     if (lane() == 63) sc.rpre[r] = inc;
   }
   __syncthreads();
@@ -286,18 +287,21 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
   if (pos + npay * W != in_len) return false;
   for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
-    if (u >= NU) continue;
-    uint32_t mi;
-    if (W == 1) {
-      mi = sc.lv0[u];
-      uint32_t valid = items - u * 8;
-      if (valid < 8) mi &= (1u << valid) - 1;
-    } else if (W == 4) {
-      mi = (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
-    } else {
-      mi = (sc.lv0[u / 8] >> (u % 8)) & 1u;
+    uint32_t mi = 0;
+    if (u < NU) {
+      if (W == 1) {
+        mi = sc.lv0[u];
+        uint32_t valid = items - u * 8;
+        if (valid < 8) mi &= (1u << valid) - 1;
+      } else if (W == 4) {
+        mi = (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
+      } else {
+        mi = (sc.lv0[u / 8] >> (u % 8)) & 1u;
+      }
     }
-    uint32_t s = pos + W * (sc.rpre[r] + sc.off[u]);
+    const uint32_t ci = __popc(mi);
+    uint32_t s = pos + W * (sc.rpre[r] + wave_incl_scan(ci) - ci);
+    if (u >= NU) continue;
     uint64_t v = 0;
     if (W == 1) {
 #pragma unroll
@@ -391,6 +395,18 @@ constexpr uint64_t kLbAgg = 1ull << 62, kLbInc = 2ull << 62,
                    kLbVal = (1ull << 62) - 1;
 
 // ------------------------------------------------------------------ encoder
+// Record byte r of a chunk: 16-byte header, then the bins part, the subbin
+// part and zero padding to a multiple of 4.
+__device__ __forceinline__ uint8_t record_byte(uint32_t r, const uint8_t* hdr,
+                                               const uint8_t* bp, uint32_t blen,
+                                               const uint8_t* sp, uint32_t slen) {
+  if (r < kRecordHeaderBytes) return hdr[r];
+  r -= kRecordHeaderBytes;
+  if (r < blen) return bp[r];
+  r -= blen;
+  return r < slen ? sp[r] : (uint8_t)0;
+}
+
 template <int K>
 __global__ __launch_bounds__(kCT) void k_encode(
     uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
@@ -400,10 +416,11 @@ __global__ __launch_bounds__(kCT) void k_encode(
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
   constexpr int GPW = (int)(W / 64 / kCW);  // groups per wave
-  __shared__ uint64_t U[kMaxUnits];
-  __shared__ uint64_t mid[kMaxUnits + 2];
-  __shared__ __attribute__((aligned(16))) uint8_t rec[kRecordHeaderBytes + 2 * kChunkBytes + 16];
+  __shared__ uint64_t U[kMaxUnits + 2];  // bit planes; later the subbin part
+  __shared__ uint64_t B[kMaxUnits + 2];  // bins part
+  __shared__ uint64_t X[kMaxUnits + 2];  // subbins after RZE_K
   __shared__ Scratch sc;
+  __shared__ uint8_t hdr[kRecordHeaderBytes];
   __shared__ uint32_t s_chunk;
   __shared__ uint64_t s_excl;
 
@@ -441,7 +458,7 @@ __global__ __launch_bounds__(kCT) void k_encode(
   bit_encode<K, GPW>(wv, G, np, U);
   __syncthreads();
   int pt_b = 0, pt_s1 = 0, pt_s2 = 0;
-  const uint32_t blen = rze_encode<1>(U, L, rec + kRecordHeaderBytes, sc, pt_b);
+  const uint32_t blen = rze_encode<1>(U, L, (uint8_t*)B, sc, pt_b);
 
   // subbins: zero words up to m, BIT_K, RZE_K, RZE_1
   orv = 0;
@@ -457,24 +474,21 @@ __global__ __launch_bounds__(kCT) void k_encode(
   np = orv ? 64 - (uint32_t)__builtin_clzll(orv) : 0;
   bit_encode<K, GPW>(wv, G, np, U);
   __syncthreads();
-  const uint32_t smid = rze_encode<K>(U, L, (uint8_t*)mid, sc, pt_s1);
-  if (threadIdx.x < 16) ((uint8_t*)mid)[smid + threadIdx.x] = 0;  // zero units past smid
+  const uint32_t smid = rze_encode<K>(U, L, (uint8_t*)X, sc, pt_s1);
+  if (threadIdx.x < 16) ((uint8_t*)X)[smid + threadIdx.x] = 0;  // zero units past smid
   __syncthreads();
-  const uint32_t slen = rze_encode<1>(mid, smid, rec + kRecordHeaderBytes + blen, sc, pt_s2);
+  const uint32_t slen = rze_encode<1>(X, smid, (uint8_t*)U, sc, pt_s2);
 
-  uint32_t size = kRecordHeaderBytes + blen + slen;
-  const uint32_t padded = (size + 3) & ~3u;
+  const uint32_t size = (kRecordHeaderBytes + blen + slen + 3) & ~3u;
   if (threadIdx.x == 0) {
-    rec[0] = (uint8_t)pt_b;
-    rec[1] = (uint8_t)(pt_s1 | (pt_s2 << 1));
-    rec[2] = (uint8_t)nc;
-    rec[3] = (uint8_t)(nc >> 8);
-    put_bytes(rec + 4, blen, 4);
-    put_bytes(rec + 8, smid, 4);
-    put_bytes(rec + 12, slen, 4);
-    for (uint32_t i = size; i < padded; ++i) rec[i] = 0;
+    hdr[0] = (uint8_t)pt_b;
+    hdr[1] = (uint8_t)(pt_s1 | (pt_s2 << 1));
+    hdr[2] = (uint8_t)nc;
+    hdr[3] = (uint8_t)(nc >> 8);
+    put_bytes(hdr + 4, blen, 4);
+    put_bytes(hdr + 8, smid, 4);
+    put_bytes(hdr + 12, slen, 4);
   }
-  size = padded;
 
   // decoupled look-back for this chunk's offset in the stream body
   if (threadIdx.x == 0) {
@@ -519,8 +533,15 @@ __global__ __launch_bounds__(kCT) void k_encode(
     if (c == nch - 1) prm->stream_size = dst + size;
   }
   if (dst + size <= cap) {
-    for (uint32_t i = threadIdx.x; i < size / 4; i += kCT)
-      ((uint32_t*)(stream + dst))[i] = ((const uint32_t*)rec)[i];
+    const uint8_t* bp = (const uint8_t*)B;
+    const uint8_t* sp = (const uint8_t*)U;
+    for (uint32_t q = threadIdx.x; q < size / 4; q += kCT) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        w |= (uint32_t)record_byte(4 * q + b, hdr, bp, blen, sp, slen) << (8 * b);
+      ((uint32_t*)(stream + dst))[q] = w;
+    }
   } else if (threadIdx.x == 0) {
     set_status(prm, ST_CAPACITY);
   }
@@ -606,18 +627,18 @@ __device__ __forceinline__ void stage(uint8_t* dst, const uint8_t* src, uint32_t
 }
 
 template <int K>
-__global__ __launch_bounds__(kCT) void k_decode(
+__global__ __launch_bounds__(kCT, 6) void k_decode(
     const uint8_t* __restrict__ stream, uint32_t n,
     const uint64_t* __restrict__ offsets, Params* prm,
     typename Traits<K>::Raw* __restrict__ out) {
   using Tr = Traits<K>;
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
-  __shared__ uint64_t R[kMaxUnits + 2];   // staged record part
-  __shared__ uint64_t U[kMaxUnits];       // bit-plane units
-  __shared__ uint64_t mid[kMaxUnits + 2]; // subbins after RZE_1
-  __shared__ uint64_t Wb[kMaxUnits];      // bin words
+  constexpr int GPW = (int)(W / 64 / kCW);  // groups per wave
+  __shared__ uint64_t U[kMaxUnits + 2];
+  __shared__ uint64_t Mb[kMaxUnits + 2];
   __shared__ Scratch sc;
+  __shared__ uint64_t gsum[64 + 1];  // per-group sums of the bin deltas
   __shared__ int s_bad;
 
   const uint32_t nch = gridDim.x, c = blockIdx.x;
@@ -652,87 +673,114 @@ __global__ __launch_bounds__(kCT) void k_decode(
     return;
   }
 
-  // bins: RZE_1 -> BIT_K -> negabinary -> prefix sum
-  stage((uint8_t*)R, rec + kRecordHeaderBytes, blen);
+  // bins: RZE_1 -> BIT_K -> negabinary -> prefix sum (words kept in registers)
+  stage((uint8_t*)Mb, rec + kRecordHeaderBytes, blen);
   __syncthreads();
-  const uint64_t* bu;
+  const uint64_t* planes;
   if (bfl & 1) {
     ok = blen == L;
-    bu = R;
+    planes = Mb;
   } else {
-    ok = rze_decode<1>((const uint8_t*)R, blen, L, U, sc);
-    bu = U;
+    ok = rze_decode<1>((const uint8_t*)Mb, blen, L, U, sc);
+    planes = U;
   }
   if (!ok) {
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
     return;
   }
-  uint64_t planes = nonzero_planes<K>(bu, G, sc);
-  bit_decode<K>(bu, G, planes, (Word*)Wb);
-  __syncthreads();
+  Word wv[GPW];
   {
-    // each thread owns a run of consecutive words; prefix sums modulo 2^(8K)
-    const Word M = (Word)0xAAAAAAAAAAAAAAAAull;
-    constexpr uint32_t per = W / kCT;
-    const uint32_t b0 = threadIdx.x * per;
-    Word loc = 0;
-    Word d[per];
+    const uint64_t pm0 = nonzero_planes<K>(planes, G, sc);
+    const uint32_t* P32 = (const uint32_t*)planes;
+    const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
+    const Word Mk = (Word)0xAAAAAAAAAAAAAAAAull;
 #pragma unroll
-    for (uint32_t q = 0; q < per; ++q) {
-      const uint32_t i = b0 + q;
-      d[q] = i < nc ? (((Word*)Wb)[i] ^ M) - M : (Word)0;
-      loc += d[q];
+    for (int i = 0; i < GPW; ++i) {
+      const uint32_t g = wave() + kCW * i;
+      Word w = 0;
+      if (g < G) {
+        uint64_t pm = pm0;
+        while (pm) {
+          const uint32_t j = (uint32_t)__builtin_ctzll(pm);
+          pm &= pm - 1;
+          w |= (Word)((P32[2 * (j * G + g) + half] >> sh) & 1u) << j;
+        }
+      }
+      // negabinary -> delta; inclusive prefix within the group of 64 words
+      Word d = (g * 64 + lane() < nc) ? (Word)((w ^ Mk) - Mk) : (Word)0;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        Word y = __shfl_up(d, o, 64);
+        if (lane() >= o) d += y;
+      }
+      wv[i] = d;
+      if (lane() == 63 && g < G) gsum[g] = (uint64_t)d;
     }
-    uint64_t tot;
-    uint64_t run = block_excl_scan<uint64_t, kCW>((uint64_t)loc, sc.scan64, tot);
-    Word acc = (Word)run;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      uint64_t v = threadIdx.x < G ? gsum[threadIdx.x] : 0ull;
+      uint64_t x = v;
 #pragma unroll
-    for (uint32_t q = 0; q < per; ++q) {
-      acc += d[q];
-      ((Word*)Wb)[b0 + q] = acc;
+      for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(x, o, 64);
+        if (lane() >= o) x += y;
+      }
+      if (threadIdx.x < G) gsum[threadIdx.x] = x - v;  // exclusive
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < GPW; ++i) {
+      const uint32_t g = wave() + kCW * i;
+      if (g < G) wv[i] += (Word)gsum[g];
     }
   }
 
   // subbins: RZE_1 -> RZE_K -> BIT_K
   const uint32_t soff = kRecordHeaderBytes + blen;
   const uint32_t shift = soff & 3u;
-  stage((uint8_t*)R, rec + (soff - shift), slen + shift);
+  stage((uint8_t*)U, rec + (soff - shift), slen + shift);
   __syncthreads();
-  const uint8_t* sp = (const uint8_t*)R + shift;
+  const uint8_t* sp = (const uint8_t*)U + shift;
   if (sfl & 2) {
     ok = slen == smid;
     if (ok) {
-      uint8_t* mb = (uint8_t*)mid;
+      uint8_t* mb = (uint8_t*)Mb;
       for (uint32_t i = threadIdx.x; i < smid; i += kCT) mb[i] = sp[i];
     }
     __syncthreads();
   } else {
-    ok = rze_decode<1>(sp, slen, smid, mid, sc);
+    ok = rze_decode<1>(sp, slen, smid, Mb, sc);
   }
+  uint64_t* words = Mb;  // subbin words go to the buffer not holding the planes
   if (ok) {
     if (sfl & 1) {
       ok = smid == L;
-      bu = mid;
+      planes = Mb;
+      words = U;
     } else {
-      ok = rze_decode<K>((const uint8_t*)mid, smid, L, U, sc);
-      bu = U;
+      ok = rze_decode<K>((const uint8_t*)Mb, smid, L, U, sc);
+      planes = U;
     }
   }
   if (!ok) {
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
     return;
   }
-  planes = nonzero_planes<K>(bu, G, sc);
-  bit_decode<K>(bu, G, planes, (Word*)R);
+  const uint64_t spm = nonzero_planes<K>(planes, G, sc);
+  bit_decode<K>(planes, G, spm, (Word*)words);
   __syncthreads();
 
   // reconstruct (Sec. IV-E)
   bool bad = false;
-  for (uint32_t i = threadIdx.x; i < nc; i += kCT) {
+#pragma unroll
+  for (int i = 0; i < GPW; ++i) {
+    const uint32_t g = wave() + kCW * i;
+    const uint32_t j = g * 64 + lane();
+    if (j >= nc) continue;
     int64_t b;
-    if (K == 4) b = (int64_t)(int32_t)((const uint32_t*)Wb)[i];
-    else b = (int64_t)((const uint64_t*)Wb)[i];
-    const uint64_t s = (uint64_t)((const Word*)R)[i];
+    if (K == 4) b = (int64_t)(int32_t)(uint32_t)wv[i];
+    else b = (int64_t)(uint64_t)wv[i];
+    const uint64_t s = (uint64_t)((const Word*)words)[j];
     int64_t klo;
     typename Tr::Raw v = 0;
     if (!bin_floor_key<K>(b, inv, winv, klo) || s > (uint64_t)(Tr::kMaxKey - klo)) {
@@ -741,7 +789,7 @@ __global__ __launch_bounds__(kCT) void k_decode(
       v = Tr::unkey(klo + (int64_t)s);
       if (s && q_bin(Tr::to_double(v), inv) != b) bad = true;
     }
-    out[p0 + i] = v;
+    out[p0 + j] = v;
   }
   if (bad) set_status(prm, ST_FORMAT);
 }
