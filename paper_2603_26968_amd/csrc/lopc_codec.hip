@@ -606,15 +606,15 @@ __device__ __forceinline__ bool bin_floor_key(int64_t b, double inv,
     k = key64(u);
   }
   int steps = 0;
-  while (k > -Tr::kMaxKey && q_bin(Tr::to_double(Tr::unkey(k - 1)), inv) >= b) {
+  while (k > -Tr::kMaxKey && Tr::q(Tr::to_double(Tr::unkey(k - 1)), inv) >= b) {
     --k;
     if (++steps > 8) return false;
   }
-  while (q_bin(Tr::to_double(Tr::unkey(k)), inv) < b) {
+  while (Tr::q(Tr::to_double(Tr::unkey(k)), inv) < b) {
     if (k >= Tr::kMaxKey || ++steps > 8) return false;
     ++k;
   }
-  if (q_bin(Tr::to_double(Tr::unkey(k)), inv) != b) return false;
+  if (Tr::q(Tr::to_double(Tr::unkey(k)), inv) != b) return false;
   out = k;
   return true;
 }
@@ -787,7 +787,7 @@ __global__ __launch_bounds__(kCT, 6) void k_decode(
       bad = true;
     } else {
       v = Tr::unkey(klo + (int64_t)s);
-      if (s && q_bin(Tr::to_double(v), inv) != b) bad = true;
+      if (s && Tr::q(Tr::to_double(v), inv) != b) bad = true;
     }
     out[p0 + j] = v;
   }

@@ -37,6 +37,7 @@ template <> struct Traits<4> {
   __device__ static Raw unkey(int64_t k) { return unkey32(k); }
   __device__ static bool finite(Raw u) { return finite32(u); }
   __device__ static double to_double(Raw u) { return (double)__uint_as_float(u); }
+  __device__ static int64_t q(double y, double inv) { return q_bin32(y, inv); }
 };
 template <> struct Traits<8> {
   using Raw = uint64_t;
@@ -48,12 +49,17 @@ template <> struct Traits<8> {
   __device__ static Raw unkey(int64_t k) { return unkey64(k); }
   __device__ static bool finite(Raw u) { return finite64(u); }
   __device__ static double to_double(Raw u) { return __longlong_as_double((long long)u); }
+  __device__ static int64_t q(double y, double inv) { return q_bin(y, inv); }
 };
 
 // ------------------------------------------------------------------ stencil
 // Edges of the Freudenthal triangulation: +-d for nonzero d in {0,1}^3,
 // listed as (dz, dy, dx); bit j of a point's mask refers to offset j.  Even
 // entries point to a higher linear index (raising weight 1), odd ones lower.
+constexpr int8_t kOff[14][3] = {
+    {0, 0, 1},  {0, 0, -1},  {0, 1, 0},  {0, -1, 0}, {0, 1, 1},
+    {0, -1, -1}, {1, 0, 0},  {-1, 0, 0}, {1, 0, 1},  {-1, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, 1, 1},  {-1, -1, -1}};
 __constant__ int8_t c_off[14][3] = {
     {0, 0, 1},  {0, 0, -1},  {0, 1, 0},  {0, -1, 0}, {0, 1, 1},
     {0, -1, -1}, {1, 0, 0},  {-1, 0, 0}, {1, 0, 1},  {-1, 0, -1},

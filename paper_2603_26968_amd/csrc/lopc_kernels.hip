@@ -118,6 +118,44 @@ __global__ __launch_bounds__(kThreads) void k_params(
   }
 }
 
+// ------------------------------------------------------------------ a1
+// Quantize every point once (Sec. IV-A): 16-byte loads and stores.
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_quant(
+    const typename Traits<K>::Raw* __restrict__ x, uint32_t n, Params* prm,
+    typename Traits<K>::Bin* __restrict__ bins) {
+  using Tr = Traits<K>;
+  using Raw = typename Tr::Raw;
+  using Bin = typename Tr::Bin;
+  constexpr int V = 16 / K;  // values per 16-byte vector
+  const double inv = prm->inv;
+  bool bad_v = false, bad_r = false;
+  const uint32_t nv = n / V;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nv; i += gridDim.x * kThreads) {
+    Raw u[V];
+    Bin b[V];
+    *(uint4*)u = ((const uint4*)x)[i];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      bad_v |= !Tr::finite(u[k]);
+      int64_t q = Tr::q(Tr::to_double(u[k]), inv);
+      bad_r |= q > Tr::kBinLimit || q < -Tr::kBinLimit;
+      b[k] = (Bin)q;
+    }
+    ((uint4*)bins)[i] = *(const uint4*)b;
+  }
+  for (uint32_t i = nv * V + blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += gridDim.x * kThreads) {
+    Raw u = x[i];
+    bad_v |= !Tr::finite(u);
+    int64_t q = Tr::q(Tr::to_double(u), inv);
+    bad_r |= q > Tr::kBinLimit || q < -Tr::kBinLimit;
+    bins[i] = (Bin)q;
+  }
+  if (bad_v) set_status(prm, ST_NONFINITE);
+  if (bad_r) set_status(prm, ST_RANGE);
+}
+
 // ------------------------------------------------------------------ a3
 // Tiles of the subbin repair.  A workgroup owns a TZ x TY x TX tile and keeps
 // the subbins of the tile plus a one-point halo in LDS.  It relaxes them in
@@ -223,49 +261,62 @@ __device__ void mark_neighbours(bool edge, const TileCoord& c, const Tiling& tl,
   }
 }
 
-// First pass, fused: quantize the tile and its halo (a1), build the order
-// flags of the owned points (a2, the flags of Alg. 1), write bins and flags,
-// then relax with halo subbins 0 (the first sweep of a3).
+// First pass, fused: build the order flags of the owned points (a2, the
+// flags of Alg. 1) from the bins and values of the tile and its halo, write
+// them, then relax with halo subbins 0 (the first sweep of a3).
 template <int K, int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_tile0(
     const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl,
-    Params* prm, typename Traits<K>::Bin* __restrict__ bins,
+    const typename Traits<K>::Bin* __restrict__ bins,
     uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
     uint32_t* counters) {
   using Tr = Traits<K>;
   using G = TileGeom<TZ, TY, TX>;
   using Key = typename Tr::Bin;  // keys fit the signed type of the bins
   using Bin = typename Tr::Bin;
+  constexpr int NJ = TZ == 1 ? 6 : 14;  // 2D: only the in-plane offsets
   constexpr int kKB = G::H * (int)(sizeof(Key) + sizeof(Bin));
   constexpr int kBytes = kKB > G::H * 4 ? kKB : G::H * 4;
+  constexpr int HL = (G::H + kThreads - 1) / kThreads;  // halo loads per thread
   __shared__ __attribute__((aligned(16))) uint8_t buf[kBytes];
   Key* KY = (Key*)buf;
   Bin* BN = (Bin*)(buf + G::H * sizeof(Key));
   uint32_t* S = (uint32_t*)buf;  // reused once the flags are built
 
   const TileCoord c = tile_coord<TZ, TY, TX>(blockIdx.x, tl);
-  const double inv = prm->inv;
-  bool bad_v = false, bad_r = false;
-  for (int i = threadIdx.x; i < G::H; i += kThreads) {
-    int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
-    int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
-    Key k = 0;
-    Bin b = 0;
-    if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx) {
-      typename Tr::Raw u = x[((int64_t)z * box.ny + y) * box.nx + xx];
-      bad_v |= !Tr::finite(u);
-      int64_t q = q_bin(Tr::to_double(u), inv);
-      bad_r |= q > Tr::kBinLimit || q < -Tr::kBinLimit;
-      k = (Key)Tr::key(u);
-      b = (Bin)q;
+  {
+    // issue every load of the halo first, then store to LDS
+    typename Tr::Raw u[HL];
+    Bin b[HL];
+#pragma unroll
+    for (int q = 0; q < HL; ++q) {
+      const int i = threadIdx.x + q * kThreads;
+      u[q] = 0;
+      b[q] = 0;
+      if (i < G::H) {
+        int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+        int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
+        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx) {
+          const int64_t g = ((int64_t)z * box.ny + y) * box.nx + xx;
+          u[q] = x[g];
+          b[q] = bins[g];
+        }
+      }
     }
-    KY[i] = k;
-    BN[i] = b;
+#pragma unroll
+    for (int q = 0; q < HL; ++q) {
+      const int i = threadIdx.x + q * kThreads;
+      if (i < G::H) {
+        KY[i] = (Key)Tr::key(u[q]);
+        BN[i] = b[q];
+      }
+    }
   }
-  if (bad_v) set_status(prm, ST_NONFINITE);
-  if (bad_r) set_status(prm, ST_RANGE);
   __syncthreads();
 
+  // the halo lies inside the grid: no neighbour needs a bounds check
+  const bool inner = c.z0 - G::ZO >= 0 && c.z0 + TZ - 1 + G::ZO < box.nz && c.y0 >= 1 &&
+                     c.y0 + TY < box.ny && c.x0 >= 1 && c.x0 + TX < box.nx;
   uint16_t mk[G::PER];
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
@@ -273,23 +324,28 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
     const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
     const int z = c.z0 + iz, y = c.y0 + iy, xx = c.x0 + ix;
     uint32_t m = 0;
-    if (z < box.nz && y < box.ny && xx < box.nx) {
-      const int li = G::local(i);
-      const Key kp = KY[li];
-      const Bin bp = BN[li];
+    const int li = G::local(i);
+    const Key kp = KY[li];
+    const Bin bp = BN[li];
+    if (inner) {
 #pragma unroll
-      for (int j = 0; j < 14; ++j) {
-        int zz = z + c_off[j][0], yy = y + c_off[j][1], xq = xx + c_off[j][2];
+      for (int j = 0; j < NJ; ++j) {
+        const int ln = li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2];
+        const Key kq = KY[ln];
+        if (BN[ln] == bp && (kq < kp || (kq == kp && (j & 1)))) m |= 1u << j;
+      }
+      mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)m;
+    } else if (z < box.nz && y < box.ny && xx < box.nx) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        int zz = z + kOff[j][0], yy = y + kOff[j][1], xq = xx + kOff[j][2];
         if (zz < 0 || zz >= box.nz || yy < 0 || yy >= box.ny || xq < 0 || xq >= box.nx)
           continue;
-        const int ln = li + c_off[j][0] * (G::HY * G::HX) + c_off[j][1] * G::HX + c_off[j][2];
-        if (BN[ln] != bp) continue;
+        const int ln = li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2];
         const Key kq = KY[ln];
-        if (kq < kp || (kq == kp && (j & 1))) m |= 1u << j;  // odd j: lower index
+        if (BN[ln] == bp && (kq < kp || (kq == kp && (j & 1)))) m |= 1u << j;  // odd j: lower index
       }
-      const int64_t g = ((int64_t)z * box.ny + y) * box.nx + xx;
-      bins[g] = bp;
-      mask[g] = (uint16_t)m;
+      mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)m;
     }
     mk[k] = (uint16_t)m;
   }
@@ -324,13 +380,25 @@ __global__ __launch_bounds__(kThreads) void k_repair(
   const uint32_t t = blockIdx.x;
   if (stamp[t] < sweep) return;
   const TileCoord c = tile_coord<TZ, TY, TX>(t, tl);
-  for (int i = threadIdx.x; i < G::H; i += kThreads) {
-    int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
-    int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, x = c.x0 + hx - 1;
-    uint32_t v = 0;
-    if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx)
-      v = sub[((int64_t)z * box.ny + y) * box.nx + x];
-    S[i] = v;
+  constexpr int HL = (G::H + kThreads - 1) / kThreads;
+  {
+    uint32_t hv[HL];
+#pragma unroll
+    for (int q = 0; q < HL; ++q) {
+      const int i = threadIdx.x + q * kThreads;
+      hv[q] = 0;
+      if (i < G::H) {
+        int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+        int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, x = c.x0 + hx - 1;
+        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx)
+          hv[q] = sub[((int64_t)z * box.ny + y) * box.nx + x];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < HL; ++q) {
+      const int i = threadIdx.x + q * kThreads;
+      if (i < G::H) S[i] = hv[q];
+    }
   }
   uint16_t mk[G::PER];
 #pragma unroll
@@ -386,23 +454,32 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
   return hipGetLastError();
 }
 
-hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm,
-                        void* bins, uint16_t* mask, uint32_t* sub, uint32_t* stamp,
+hipError_t launch_quant(int dtype, const void* x, uint32_t n, Params* prm, void* bins,
+                        int nblocks, hipStream_t s) {
+  if (dtype == 0)
+    k_quant<4><<<nblocks, kThreads, 0, s>>>((const uint32_t*)x, n, prm, (int32_t*)bins);
+  else
+    k_quant<8><<<nblocks, kThreads, 0, s>>>((const uint64_t*)x, n, prm, (int64_t*)bins);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, const void* bins,
+                        uint16_t* mask, uint32_t* sub, uint32_t* stamp,
                         uint32_t* counters, hipStream_t s) {
   if (t.tz == 1) {
     if (dtype == 0)
-      k_tile0<4, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
-                                                           (int32_t*)bins, mask, sub, stamp, counters);
+      k_tile0<4, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t,
+                                                           (const int32_t*)bins, mask, sub, stamp, counters);
     else
-      k_tile0<8, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
-                                                           (int64_t*)bins, mask, sub, stamp, counters);
+      k_tile0<8, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t,
+                                                           (const int64_t*)bins, mask, sub, stamp, counters);
   } else {
     if (dtype == 0)
-      k_tile0<4, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
-                                                          (int32_t*)bins, mask, sub, stamp, counters);
+      k_tile0<4, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t,
+                                                          (const int32_t*)bins, mask, sub, stamp, counters);
     else
-      k_tile0<8, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
-                                                          (int64_t*)bins, mask, sub, stamp, counters);
+      k_tile0<8, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t,
+                                                          (const int64_t*)bins, mask, sub, stamp, counters);
   }
   return hipGetLastError();
 }

@@ -68,4 +68,23 @@ LOPC_HD int64_t q_bin(double y, double inv) {
   return neg ? -q : q;
 }
 
+// The same function for float32 fields, whose bins must lie within
+// +-(2^31 - 2): exact for |y*inv| < 2^31 with 32-bit integer conversions;
+// larger products return +-2^31, which is outside the float32 bin range.
+LOPC_HD int64_t q_bin32(double y, double inv) {
+  const double two31 = 2147483648.0;
+  double p = y * inv;
+  const bool neg = p < 0.0;
+  const double a = fabs(p);
+  if (!(a < two31)) return neg ? -(int64_t)two31 : (int64_t)two31;
+  double r = fma(y, inv, -p);
+  const double rr = neg ? -r : r;
+  const double fl = floor(a);
+  const double fr = a - fl;
+  int32_t q = (int32_t)fl;
+  bool up = fr > 0.5 || (fr == 0.5 && (rr > 0.0 || (rr == 0.0 && (q & 1))));
+  int64_t v = (int64_t)q + (up ? 1 : 0);
+  return neg ? -v : v;
+}
+
 }  // namespace lopc

@@ -64,6 +64,16 @@ def cases():
                 for _ in range(9):
                     out.append((y, inv))
                     y = math.nextafter(y, math.inf)
+    # products near the float32 bin limit 2^31 - 2
+    for sgn in (1.0, -1.0):
+        for base in (2.0 ** 31 - 2.5, 2.0 ** 31 - 1.5, 2.0 ** 31 - 0.5, 2.0 ** 31):
+            for inv in (1.0, 0.5, 3.0):
+                y = sgn * base / inv
+                for _ in range(2):
+                    y = math.nextafter(y, -math.inf)
+                for _ in range(5):
+                    out.append((y, inv))
+                    y = math.nextafter(y, math.inf)
     # subnormal inputs, zeros
     for y in (5e-324, -5e-324, 1e-310, -1e-310, 0.0, -0.0, 2.2250738585072014e-308):
         for inv in (1.0, 1e300, 1e308, 3.0):
@@ -75,7 +85,16 @@ def test_quantizer_source_matches_exact_rounding(harness):
     cs = cases()
     inp = "".join(f"{bits(y):x} {bits(i):x}\n" for y, i in cs)
     res = subprocess.run([harness], input=inp, capture_output=True, text=True, check=True)
-    got = [int(v) for v in res.stdout.split()]
+    vals = [int(v) for v in res.stdout.split()]
+    got, got32 = vals[0::2], vals[1::2]
     assert len(got) == len(cs)
     bad = [(y, i, g, exact(y, i)) for (y, i), g in zip(cs, got) if g != exact(y, i)]
     assert not bad, bad[:5]
+    # the float32 variant: exact inside the float32 bin range, out of range outside
+    lim = 2 ** 31 - 2
+    for (y, i), g in zip(cs, got32):
+        e = exact(y, i)
+        if abs(e) <= lim:
+            assert g == e, (y, i, g, e)
+        else:
+            assert abs(g) > lim, (y, i, g, e)
