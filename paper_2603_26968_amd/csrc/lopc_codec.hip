@@ -156,15 +156,24 @@ __device__ bool level_decode(const uint8_t* par, uint32_t n, const uint8_t* in,
 }
 
 // RZE_W over the first `len` bytes of the unit array U (zero beyond len)
-// into out.  Returns the output length; pt = 1 when the input is stored
-// verbatim because the output would not be smaller.
+// into out.  Units from `nua` on are known to be zero (bit planes above the
+// highest set bit) and are skipped.  Returns the output length; pt = 1 when
+// the input is stored verbatim because the output would not be smaller.
 template <int W>
-__device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
-                               Scratch& sc, int& pt) {
+__device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
+                               uint8_t* out, Scratch& sc, int& pt) {
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
   const uint32_t rounds = (NU + 63) / 64;
-  for (uint32_t r = wave(); r < rounds; r += kCW) {
+  const uint32_t ra = (min(nua, NU) + 63) / 64;  // rounds that may hold nonzero units
+  if (ra < rounds) {
+    // bitmap bytes of the zero rounds, and their counts
+    const uint32_t nb0 = (items + 7) / 8;
+    for (uint32_t i = threadIdx.x; i < (nb0 + 3) / 4 + 1; i += kCT) ((uint32_t*)sc.lv0)[i] = 0;
+    if (threadIdx.x >= ra && threadIdx.x < rounds) sc.rpre[threadIdx.x] = 0;
+    __syncthreads();
+  }
+  for (uint32_t r = wave(); r < ra; r += kCW) {
     const uint32_t u = r * 64 + lane();
     const uint64_t v = u < NU ? U[u] : 0ull;
     uint32_t mi, ci;
@@ -213,7 +222,7 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
     for (uint32_t i = threadIdx.x; i < sc.nkept[l]; i += kCT) out[pos + i] = kb[i];
     pos += sc.nkept[l];
   }
-  for (uint32_t r = wave(); r < rounds; r += kCW) {
+  for (uint32_t r = wave(); r < ra; r += kCW) {
     const uint32_t u = r * 64 + lane();
     const uint64_t v = u < NU ? U[u] : 0ull;
     uint32_t ci;
@@ -245,10 +254,28 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint8_t* out,
 
 // Inverse of rze_encode: in[0, in_len) -> the first `len` bytes of U (units
 // rounded up; bytes past len are zero).  Returns false on malformed input;
-// never reads outside [in, in + in_len).
+// never reads outside [in, in + in_len).  If G > 0 the units are bit planes
+// of G groups and sc.planes receives the mask of planes holding a nonzero
+// unit.
+template <int W>
+__device__ __forceinline__ uint32_t unit_bits(const Scratch& sc, uint32_t u, uint32_t NU,
+                                              uint32_t items) {
+  if (u >= NU) return 0u;
+  if (W == 1) {
+    uint32_t mi = sc.lv0[u];
+    uint32_t valid = items - u * 8;
+    if (valid < 8) mi &= (1u << valid) - 1;
+    return mi;
+  } else if (W == 4) {
+    return (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
+  } else {
+    return (sc.lv0[u / 8] >> (u % 8)) & 1u;
+  }
+}
+
 template <int W>
 __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
-                           uint64_t* U, Scratch& sc) {
+                           uint64_t* U, Scratch& sc, uint32_t G) {
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
   const uint32_t rounds = (NU + 63) / 64;
@@ -265,41 +292,22 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
     if (!level_decode(lvl(sc, l + 1), sz[l], in, pos, in_len, lvl(sc, l), sc)) return false;
   // lv0 holds `items` bitmap bits
   for (uint32_t r = wave(); r < rounds; r += kCW) {
-    const uint32_t u = r * 64 + lane();
-    uint32_t mi = 0;
-    if (u < NU) {
-      if (W == 1) {
-        mi = sc.lv0[u];
-        uint32_t valid = items - u * 8;
-        if (valid < 8) mi &= (1u << valid) - 1;
-      } else if (W == 4) {
-        mi = (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
-      } else {
-        mi = (sc.lv0[u / 8] >> (u % 8)) & 1u;
-      }
-    }
-    const uint32_t ci = __popc(mi);
-    const uint32_t inc = wave_incl_scan(ci);
+    const uint32_t ci = __popc(unit_bits<W>(sc, r * 64 + lane(), NU, items));
+    const uint32_t inc = __ballot(ci != 0u) ? wave_incl_scan(ci) : 0u;
     if (lane() == 63) sc.rpre[r] = inc;
   }
   __syncthreads();
   const uint32_t npay = round_prefix(sc, rounds);
   if (pos + npay * W != in_len) return false;
+  uint64_t pm = 0;
   for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
-    uint32_t mi = 0;
-    if (u < NU) {
-      if (W == 1) {
-        mi = sc.lv0[u];
-        uint32_t valid = items - u * 8;
-        if (valid < 8) mi &= (1u << valid) - 1;
-      } else if (W == 4) {
-        mi = (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
-      } else {
-        mi = (sc.lv0[u / 8] >> (u % 8)) & 1u;
-      }
-    }
+    const uint32_t mi = unit_bits<W>(sc, u, NU, items);
     const uint32_t ci = __popc(mi);
+    if (!__ballot(ci != 0u)) {
+      if (u < NU) U[u] = 0;
+      continue;
+    }
     uint32_t s = pos + W * (sc.rpre[r] + wave_incl_scan(ci) - ci);
     if (u >= NU) continue;
     uint64_t v = 0;
@@ -321,8 +329,19 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
       for (int b = 0; b < 8; ++b) v |= (uint64_t)in[s + b] << (8 * b);
     }
     U[u] = v;
+    if (G && v) pm |= 1ull << (u / G);
+  }
+  if (G) {
+    for (int d = 32; d > 0; d >>= 1) pm |= __shfl_xor(pm, d, 64);
+    if (lane() == 0) sc.orv[wave()] = pm;
   }
   __syncthreads();
+  if (G) {
+    uint64_t m = 0;
+    for (int w = 0; w < kCW; ++w) m |= sc.orv[w];
+    if (threadIdx.x == 0) sc.planes = m;
+    __syncthreads();
+  }
   return true;
 }
 
@@ -458,7 +477,7 @@ __global__ __launch_bounds__(kCT) void k_encode(
   bit_encode<K, GPW>(wv, G, np, U);
   __syncthreads();
   int pt_b = 0, pt_s1 = 0, pt_s2 = 0;
-  const uint32_t blen = rze_encode<1>(U, L, (uint8_t*)B, sc, pt_b);
+  const uint32_t blen = rze_encode<1>(U, L, np * G, (uint8_t*)B, sc, pt_b);
 
   // subbins: zero words up to m, BIT_K, RZE_K, RZE_1
   orv = 0;
@@ -474,10 +493,10 @@ __global__ __launch_bounds__(kCT) void k_encode(
   np = orv ? 64 - (uint32_t)__builtin_clzll(orv) : 0;
   bit_encode<K, GPW>(wv, G, np, U);
   __syncthreads();
-  const uint32_t smid = rze_encode<K>(U, L, (uint8_t*)X, sc, pt_s1);
+  const uint32_t smid = rze_encode<K>(U, L, np * G, (uint8_t*)X, sc, pt_s1);
   if (threadIdx.x < 16) ((uint8_t*)X)[smid + threadIdx.x] = 0;  // zero units past smid
   __syncthreads();
-  const uint32_t slen = rze_encode<1>(X, smid, (uint8_t*)U, sc, pt_s2);
+  const uint32_t slen = rze_encode<1>(X, smid, (smid + 7) / 8, (uint8_t*)U, sc, pt_s2);
 
   const uint32_t size = (kRecordHeaderBytes + blen + slen + 3) & ~3u;
   if (threadIdx.x == 0) {
@@ -677,12 +696,15 @@ __global__ __launch_bounds__(kCT, 6) void k_decode(
   stage((uint8_t*)Mb, rec + kRecordHeaderBytes, blen);
   __syncthreads();
   const uint64_t* planes;
+  uint64_t pm0 = 0;
   if (bfl & 1) {
     ok = blen == L;
     planes = Mb;
+    if (ok) pm0 = nonzero_planes<K>(planes, G, sc);
   } else {
-    ok = rze_decode<1>((const uint8_t*)Mb, blen, L, U, sc);
+    ok = rze_decode<1>((const uint8_t*)Mb, blen, L, U, sc, G);
     planes = U;
+    pm0 = sc.planes;
   }
   if (!ok) {
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
@@ -690,7 +712,6 @@ __global__ __launch_bounds__(kCT, 6) void k_decode(
   }
   Word wv[GPW];
   {
-    const uint64_t pm0 = nonzero_planes<K>(planes, G, sc);
     const uint32_t* P32 = (const uint32_t*)planes;
     const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
     const Word Mk = (Word)0xAAAAAAAAAAAAAAAAull;
@@ -749,41 +770,86 @@ __global__ __launch_bounds__(kCT, 6) void k_decode(
     }
     __syncthreads();
   } else {
-    ok = rze_decode<1>(sp, slen, smid, Mb, sc);
+    ok = rze_decode<1>(sp, slen, smid, Mb, sc, 0);
   }
   uint64_t* words = Mb;  // subbin words go to the buffer not holding the planes
+  uint64_t spm = 0;
   if (ok) {
     if (sfl & 1) {
       ok = smid == L;
       planes = Mb;
       words = U;
+      if (ok) spm = nonzero_planes<K>(planes, G, sc);
     } else {
-      ok = rze_decode<K>((const uint8_t*)Mb, smid, L, U, sc);
+      ok = rze_decode<K>((const uint8_t*)Mb, smid, L, U, sc, G);
       planes = U;
+      spm = sc.planes;
     }
   }
   if (!ok) {
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
     return;
   }
-  const uint64_t spm = nonzero_planes<K>(planes, G, sc);
   bit_decode<K>(planes, G, spm, (Word*)words);
-  __syncthreads();
 
-  // reconstruct (Sec. IV-E)
+  // reconstruct (Sec. IV-E).  The bin floors of the chunk's bin range go to
+  // a table in the (now free) planes buffer when the range is small enough,
+  // so that each distinct bin is walked once.
+  using Key = typename Tr::Bin;  // order keys fit the signed bin type
+  constexpr uint32_t kTab = kChunkBytes / sizeof(Key);
+  constexpr Key kNoKey = (Key)((uint64_t)1 << (8 * sizeof(Key) - 1));  // most negative
+  int64_t bmin = INT64_MAX, bmax = INT64_MIN;
+#pragma unroll
+  for (int i = 0; i < GPW; ++i) {
+    const uint32_t j = (wave() + kCW * i) * 64 + lane();
+    const int64_t b = K == 4 ? (int64_t)(int32_t)(uint32_t)wv[i] : (int64_t)(uint64_t)wv[i];
+    if (j < nc) {
+      bmin = b < bmin ? b : bmin;
+      bmax = b > bmax ? b : bmax;
+    }
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    int64_t a = __shfl_xor(bmin, d, 64), c2 = __shfl_xor(bmax, d, 64);
+    bmin = a < bmin ? a : bmin;
+    bmax = c2 > bmax ? c2 : bmax;
+  }
+  if (lane() == 0) {
+    sc.orv[wave()] = (uint64_t)bmin;
+    sc.scan64[wave()] = (uint64_t)bmax;
+  }
+  __syncthreads();
+  for (int w = 0; w < kCW; ++w) {
+    bmin = min(bmin, (int64_t)sc.orv[w]);
+    bmax = max(bmax, (int64_t)sc.scan64[w]);
+  }
+  const bool table = (uint64_t)bmax - (uint64_t)bmin < kTab;
+  Key* T = (Key*)planes;
+  if (table) {
+    const uint32_t R = (uint32_t)((uint64_t)bmax - (uint64_t)bmin) + 1;
+    for (uint32_t e = threadIdx.x; e < R; e += kCT) {
+      int64_t klo;
+      T[e] = bin_floor_key<K>(bmin + (int64_t)e, inv, winv, klo) ? (Key)klo : kNoKey;
+    }
+  }
+  __syncthreads();
   bool bad = false;
 #pragma unroll
   for (int i = 0; i < GPW; ++i) {
-    const uint32_t g = wave() + kCW * i;
-    const uint32_t j = g * 64 + lane();
+    const uint32_t j = (wave() + kCW * i) * 64 + lane();
     if (j >= nc) continue;
-    int64_t b;
-    if (K == 4) b = (int64_t)(int32_t)(uint32_t)wv[i];
-    else b = (int64_t)(uint64_t)wv[i];
+    const int64_t b = K == 4 ? (int64_t)(int32_t)(uint32_t)wv[i] : (int64_t)(uint64_t)wv[i];
     const uint64_t s = (uint64_t)((const Word*)words)[j];
     int64_t klo;
+    bool have;
+    if (table) {
+      const Key t = T[(uint32_t)((uint64_t)b - (uint64_t)bmin)];
+      have = t != kNoKey;
+      klo = (int64_t)t;
+    } else {
+      have = bin_floor_key<K>(b, inv, winv, klo);
+    }
     typename Tr::Raw v = 0;
-    if (!bin_floor_key<K>(b, inv, winv, klo) || s > (uint64_t)(Tr::kMaxKey - klo)) {
+    if (!have || s > (uint64_t)(Tr::kMaxKey - klo)) {
       bad = true;
     } else {
       v = Tr::unkey(klo + (int64_t)s);
