@@ -53,10 +53,11 @@ def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        s, stats = P.compress(x, eb, "noa", stats=True, out=stream_buf, workspace=ws_c)
+        s, stats, hdr = P.compress(x, eb, "noa", stats=True, header=True, out=stream_buf,
+                                   workspace=ws_c)
         if timing:
             ph = lopc.lopc_ctx_last_timings(ctx)
-        P.decompress(s, out=y, workspace=ws_d)
+        P.decompress(s, out=y, workspace=ws_d, header=hdr)
         if timing:
             ph2 = lopc.lopc_ctx_last_timings(ctx)
             for k in ("range", "quant", "repair", "encode"):

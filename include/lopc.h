@@ -113,6 +113,20 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
                     void* d_field, size_t field_cap, void* d_ws,
                     size_t ws_bytes, void* stream);
 
+/* lopc_decompress with the stream's 64-byte header also given in host memory
+ * (for a caller that already holds it, e.g. from lopc_ctx_last_header); this
+ * saves a device-to-host read.  h_header must equal the first 64 bytes of
+ * d_stream: shapes come from h_header, the error-bound parameters from the
+ * device copy, so a mismatch gives wrong values (or LOPC_E_FORMAT) but never
+ * an access outside the given buffers. */
+int lopc_decompress_h(lopc_ctx* ctx, const void* h_header, const void* d_stream,
+                      size_t stream_size, void* d_field, size_t field_cap,
+                      void* d_ws, size_t ws_bytes, void* stream);
+
+/* Copy the 64-byte header of the most recent successful lopc_compress on this
+ * context into h_header.  LOPC_E_ARG if there is none. */
+int lopc_ctx_last_header(lopc_ctx* ctx, void* h_header);
+
 /* Static text for a status code. */
 const char* lopc_strerror(int status);
 

@@ -22,6 +22,9 @@ struct lopc_ctx {
   // pinned host slots for small device-to-host reads
   Params* h_prm;
   uint32_t* h_cnt;
+  // header of the most recent successful compression
+  uint8_t last_header[64];
+  int have_header;
   // last HIP failure (for diagnostics)
   int hip_error;
   char hip_where[64];
@@ -218,6 +221,7 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->h_prm = (Params*)p;
   c->h_cnt = (uint32_t*)((uint8_t*)p + 2048);
   c->timing = 0;
+  c->have_header = 0;
   c->hip_error = 0;
   c->hip_where[0] = 0;
   {
@@ -398,6 +402,8 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   }
   const Params& hp = *ctx->h_prm;
   *h_stream_size = (size_t)hp.stream_size;
+  std::memcpy(ctx->last_header, hp.header, kHeaderBytes);
+  ctx->have_header = status_code(hp.status) == LOPC_OK;
   if (h_stats) {
     h_stats->eps = hp.eps;
     h_stats->repair_sweeps = sweeps;
@@ -442,18 +448,9 @@ int lopc_stream_info(const void* h_header, size_t n, int* dtype, int* ndim,
   return LOPC_OK;
 }
 
-int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
-                    void* d_field, size_t field_cap, void* d_ws,
-                    size_t ws_bytes, void* stream) {
-  if (!ctx || !d_stream || !d_field || !d_ws) return LOPC_E_ARG;
-  if (stream_size < kHeaderBytes) return LOPC_E_FORMAT;
-  hipStream_t hs = (hipStream_t)stream;
-  HIP_CTX(ctx, hipSetDevice(ctx->device));
-  uint8_t* hh = (uint8_t*)ctx->h_prm;  // pinned staging for the header
-  HIP_CTX(ctx, hipMemcpyAsync(hh, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, hs));
-  HIP_CTX(ctx, hipStreamSynchronize(hs));
-  uint8_t hdr[kHeaderBytes];
-  std::memcpy(hdr, hh, kHeaderBytes);
+static int decompress_core(lopc_ctx* ctx, const uint8_t* hdr, const void* d_stream,
+                           size_t stream_size, void* d_field, size_t field_cap,
+                           void* d_ws, size_t ws_bytes, hipStream_t hs) {
   int dtype, ndim;
   int64_t dims[3];
   size_t fbytes;
@@ -472,10 +469,10 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
   HIP_CTX(ctx, hipMemsetAsync(prm, 0, sizeof(Params), hs));
   HIP_CTX(ctx, mark(ctx, 5, hs));
   HIP_CTX(ctx, launch_offsets((const uint8_t*)d_stream, (uint32_t)nch,
-                         stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs));
+                              stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs));
   HIP_CTX(ctx, mark(ctx, 6, hs));
   HIP_CTX(ctx, launch_decode(dtype, (const uint8_t*)d_stream, (uint32_t)s.n, offsets,
-                        prm, d_field, hs));
+                             prm, d_field, hs));
   HIP_CTX(ctx, mark(ctx, 7, hs));
   HIP_CTX(ctx, hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4, hipMemcpyDeviceToHost, hs));
   HIP_CTX(ctx, hipStreamSynchronize(hs));
@@ -484,6 +481,38 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
     ctx->ms[LOPC_PHASE_DECODE] = span(ctx, 6, 7);
   }
   return status_code(ctx->h_prm->status);
+}
+
+int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
+                    void* d_field, size_t field_cap, void* d_ws,
+                    size_t ws_bytes, void* stream) {
+  if (!ctx || !d_stream || !d_field || !d_ws) return LOPC_E_ARG;
+  if (stream_size < kHeaderBytes) return LOPC_E_FORMAT;
+  hipStream_t hs = (hipStream_t)stream;
+  HIP_CTX(ctx, hipSetDevice(ctx->device));
+  uint8_t* hh = (uint8_t*)ctx->h_prm;  // pinned staging for the header
+  HIP_CTX(ctx, hipMemcpyAsync(hh, d_stream, kHeaderBytes, hipMemcpyDeviceToHost, hs));
+  HIP_CTX(ctx, hipStreamSynchronize(hs));
+  uint8_t hdr[kHeaderBytes];
+  std::memcpy(hdr, hh, kHeaderBytes);
+  return decompress_core(ctx, hdr, d_stream, stream_size, d_field, field_cap, d_ws, ws_bytes, hs);
+}
+
+int lopc_decompress_h(lopc_ctx* ctx, const void* h_header, const void* d_stream,
+                      size_t stream_size, void* d_field, size_t field_cap, void* d_ws,
+                      size_t ws_bytes, void* stream) {
+  if (!ctx || !h_header || !d_stream || !d_field || !d_ws) return LOPC_E_ARG;
+  if (stream_size < kHeaderBytes) return LOPC_E_FORMAT;
+  HIP_CTX(ctx, hipSetDevice(ctx->device));
+  return decompress_core(ctx, (const uint8_t*)h_header, d_stream, stream_size, d_field,
+                         field_cap, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int lopc_ctx_last_header(lopc_ctx* ctx, void* h_header) {
+  if (!ctx || !h_header) return LOPC_E_ARG;
+  if (!ctx->have_header) return LOPC_E_ARG;
+  std::memcpy(h_header, ctx->last_header, kHeaderBytes);
+  return LOPC_OK;
 }
 
 }  // extern "C"

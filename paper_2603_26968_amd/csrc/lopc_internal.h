@@ -39,6 +39,7 @@ struct alignas(256) Params {
   int64_t kmin, kmax;  // order keys of the smallest / largest value
   uint32_t mode;
   uint32_t dtype;
+  uint8_t header[64];  // copy of the stream header (read back with Params)
 };
 
 // A field as a 3D box (a 2D field d0 x d1 is the box 1 x d0 x d1: the same

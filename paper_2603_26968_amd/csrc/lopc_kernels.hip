@@ -100,8 +100,8 @@ __global__ __launch_bounds__(kThreads) void k_params(
   prm->eps = e;
   prm->inv = v;
   prm->winv = 1.0 / v;
-  if (cap >= kHeaderBytes) {
-    uint8_t* h = stream;
+  {
+    uint8_t* h = prm->header;
     put_bytes(h + 0, kMagic, 4);
     put_bytes(h + 4, kVersion, 2);
     h[6] = (uint8_t)(K == 4 ? 0 : 1);
@@ -115,6 +115,8 @@ __global__ __launch_bounds__(kThreads) void k_params(
     put_bytes(h + 40, (uint64_t)__double_as_longlong(eb), 8);
     put_bytes(h + 48, (uint64_t)__double_as_longlong(e), 8);
     put_bytes(h + 56, (uint64_t)__double_as_longlong(v), 8);
+    if (cap >= kHeaderBytes)
+      for (int i = 0; i < (int)kHeaderBytes; ++i) stream[i] = h[i];
   }
 }
 

@@ -29,7 +29,8 @@ HEADER_BYTES = 64
 EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_workspace_size", "lopc_compress", "lopc_stream_info",
            "lopc_decompress", "lopc_strerror", "lopc_ctx_set_timing",
-           "lopc_ctx_last_timings", "lopc_ctx_last_hip_error")
+           "lopc_ctx_last_timings", "lopc_ctx_last_hip_error", "lopc_decompress_h",
+           "lopc_ctx_last_header")
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
 
@@ -89,6 +90,10 @@ def load() -> ctypes.CDLL:
     L.lopc_ctx_set_timing.restype = ci
     L.lopc_ctx_last_timings.argtypes = [vp, ctypes.POINTER(cd), ci]
     L.lopc_ctx_last_timings.restype = ci
+    L.lopc_decompress_h.argtypes = [vp, vp, vp, sz, vp, sz, vp, sz, vp]
+    L.lopc_decompress_h.restype = ci
+    L.lopc_ctx_last_header.argtypes = [vp, vp]
+    L.lopc_ctx_last_header.restype = ci
     L.lopc_ctx_last_hip_error.argtypes = [vp, ctypes.POINTER(ci)]
     L.lopc_ctx_last_hip_error.restype = ctypes.c_char_p
     _lib = L
@@ -186,6 +191,21 @@ def lopc_decompress(ctx, d_stream, size, d_field, cap, d_ws, ws_bytes, stream) -
     return load().lopc_decompress(ctx, d_stream, size, d_field, cap, d_ws, ws_bytes, stream)
 
 
+def lopc_decompress_h(ctx, header: bytes, d_stream, size, d_field, cap, d_ws, ws_bytes,
+                      stream) -> int:
+    buf = ctypes.create_string_buffer(bytes(header)[:HEADER_BYTES], HEADER_BYTES)
+    return load().lopc_decompress_h(ctx, buf, d_stream, size, d_field, cap, d_ws, ws_bytes,
+                                    stream)
+
+
+def lopc_ctx_last_header(ctx) -> bytes:
+    buf = ctypes.create_string_buffer(HEADER_BYTES)
+    st = load().lopc_ctx_last_header(ctx, buf)
+    if st:
+        raise LopcError(st, "lopc_ctx_last_header")
+    return buf.raw
+
+
 # ------------------------------------------------------------------ torch API
 _ctx = {}
 
@@ -217,18 +237,33 @@ def _check_field(x: torch.Tensor):
     return _dtype_code(x.dtype)
 
 
+_sizes = {}
+
+
+def _sizes_for(ctx, shape, dtype):
+    """(compress bound, compress workspace, decompress workspace), cached."""
+    key = (tuple(shape), dtype)
+    v = _sizes.get(key)
+    if v is None:
+        v = (lopc_compress_bound(shape, dtype), lopc_workspace_size(ctx, shape, dtype, 0),
+             lopc_workspace_size(ctx, shape, dtype, 1))
+        _sizes[key] = v
+    return v
+
+
 def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = False,
-             out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+             out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+             header: bool = False):
     """Compress a 2D/3D float32/float64 device tensor.  Returns a uint8 device
-    tensor holding the stream (a view of ``out`` if given), plus a stats dict
-    when ``stats`` is true."""
+    tensor holding the stream (a view of ``out`` if given), then a stats dict
+    when ``stats`` is true, then the 64-byte header (host bytes) when
+    ``header`` is true."""
     code = _check_field(x)
     dev = x.device
     ctx = context(dev.index)
-    cap = lopc_compress_bound(x.shape, x.dtype)
+    cap, wsz, _ = _sizes_for(ctx, x.shape, x.dtype)
     if out is None or out.numel() < cap:
         out = torch.empty(cap, dtype=torch.uint8, device=dev)
-    wsz = lopc_workspace_size(ctx, x.shape, x.dtype, 0)
     if workspace is None or workspace.numel() < wsz:
         workspace = torch.empty(wsz, dtype=torch.uint8, device=dev)
     s = torch.cuda.current_stream(dev).cuda_stream
@@ -237,29 +272,38 @@ def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = Fals
                                   workspace.data_ptr(), workspace.numel(), s)
     if st:
         raise LopcError(st, "lopc_compress", ctx)
-    res = out[:size]
-    return (res, stt.as_dict()) if stats else res
+    res = [out[:size]]
+    if stats:
+        res.append(stt.as_dict())
+    if header:
+        res.append(lopc_ctx_last_header(ctx))
+    return res[0] if len(res) == 1 else tuple(res)
 
 
 def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
-               workspace: torch.Tensor | None = None) -> torch.Tensor:
-    """Decompress a uint8 device tensor holding exactly one stream."""
+               workspace: torch.Tensor | None = None,
+               header: bytes | None = None) -> torch.Tensor:
+    """Decompress a uint8 device tensor holding exactly one stream.  If the
+    caller holds the stream's 64-byte header on the host (``header``, e.g.
+    from ``compress(..., header=True)``) no device-to-host read is needed."""
     if not stream.is_cuda or stream.dtype != torch.uint8 or not stream.is_contiguous():
         raise ValueError("stream must be a contiguous uint8 device tensor")
     if stream.numel() < HEADER_BYTES:
         raise LopcError(LOPC_E_FORMAT, "lopc_decompress")
-    info = lopc_stream_info(stream[:HEADER_BYTES].cpu().numpy().tobytes())
+    hdr = bytes(header) if header is not None else \
+        stream[:HEADER_BYTES].cpu().numpy().tobytes()
+    info = lopc_stream_info(hdr)
     dev = stream.device
     ctx = context(dev.index)
     if out is None:
         out = torch.empty(info["shape"], dtype=info["dtype"], device=dev)
-    wsz = lopc_workspace_size(ctx, info["shape"], info["dtype"], 1)
+    wsz = _sizes_for(ctx, info["shape"], info["dtype"])[2]
     if workspace is None or workspace.numel() < wsz:
         workspace = torch.empty(wsz, dtype=torch.uint8, device=dev)
     s = torch.cuda.current_stream(dev).cuda_stream
-    st = lopc_decompress(ctx, stream.data_ptr(), stream.numel(), out.data_ptr(),
-                         out.numel() * out.element_size(), workspace.data_ptr(),
-                         workspace.numel(), s)
+    st = lopc_decompress_h(ctx, hdr, stream.data_ptr(), stream.numel(), out.data_ptr(),
+                           out.numel() * out.element_size(), workspace.data_ptr(),
+                           workspace.numel(), s)
     if st:
         raise LopcError(st, "lopc_decompress", ctx)
     return out

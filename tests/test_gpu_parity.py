@@ -238,3 +238,28 @@ def test_adversarial_bin_edges(P, ref):
         x = np.array(vals, dt)
         x = np.resize(x, (len(x) // 7, 7))
         check(P, ref, x, eps, "abs", f"edges {dt.__name__} eps={eps}")
+
+
+def test_header_passthrough(P, ref):
+    """lopc_ctx_last_header returns the stream's header; lopc_decompress_h
+    with it equals lopc_decompress; a mismatched header is rejected or gives
+    wrong values but stays inside the buffers."""
+    from paper_2603_26968_amd import lopc
+    _say("header passthrough")
+    x = synth.gaussian_bumps((70, 61), seed=9)
+    t = torch.from_numpy(x).cuda()
+    s, hdr = P.compress(t, 1e-3, "noa", header=True)
+    assert hdr == s[:64].cpu().numpy().tobytes()
+    y1 = P.decompress(s).cpu().numpy()
+    y2 = P.decompress(s, header=hdr).cpu().numpy()
+    assert same_bits(y1, y2) and same_bits(y1, ref.decompress(s.cpu().numpy().tobytes()))
+    # a header of another shape with the same number of chunks
+    other = bytearray(hdr)
+    other[8:16] = (61).to_bytes(8, "little")
+    other[16:24] = (70).to_bytes(8, "little")
+    out = torch.zeros((61, 70), dtype=torch.float32, device="cuda")
+    try:
+        P.decompress(s, header=bytes(other), out=out)
+    except P.LopcError as e:
+        assert e.code == lopc.LOPC_E_FORMAT
+    torch.cuda.synchronize()
