@@ -32,6 +32,9 @@
  *   - return value: LOPC_OK (0) or a negative lopc_status; arguments are
  *     validated before any launch; on error the output buffers hold
  *     unspecified bytes but nothing outside them is written;
+ *   - alignment: a field to compress must start on a 16-byte boundary, a
+ *     stream on a 4-byte boundary, a field to decode into on its element
+ *     size, a workspace on a 256-byte boundary (torch allocations are);
  *   - a context may be used by one host thread at a time.
  */
 #ifndef LOPC_H
@@ -126,6 +129,77 @@ int lopc_decompress_h(lopc_ctx* ctx, const void* h_header, const void* d_stream,
 /* Copy the 64-byte header of the most recent successful lopc_compress on this
  * context into h_header.  LOPC_E_ARG if there is none. */
 int lopc_ctx_last_header(lopc_ctx* ctx, void* h_header);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent fields in one call.  Each phase (range, quantize, order
+ * flags + first relaxation, each repair sweep, chunk encoder; header check,
+ * chunk decoder) is one persistent launch per group of fields with the same
+ * dtype and dimensionality, draining a work-queue of (field, block),
+ * (field, tile) or (field, chunk) items; repair sweeps run over a device
+ * work list of the tiles marked by the previous sweep.  The launch sequence
+ * reads everything from the workspace, so it is captured once per context,
+ * workspace and composition (dtypes x dimensionalities present) as a HIP
+ * graph and replayed; a batch whose repair needs more sweeps than the graph
+ * holds continues with direct launches (and the next capture holds more).
+ * Fields never interact: every field's stream equals its lopc_compress
+ * stream byte for byte, and every decoded field its lopc_decompress output.
+ */
+typedef struct {
+  const void* d_in;      /* compress: field; decompress: stream              */
+  size_t in_bytes;       /* decompress: stream size (compress: ignored)      */
+  void* d_out;           /* compress: stream; decompress: field              */
+  size_t out_cap;        /* bytes available at d_out                         */
+  int dtype;             /* lopc_dtype (decompress: must match the header)   */
+  int ndim;              /* 2 or 3 (decompress: must match the header)       */
+  int64_t dims[3];       /* unused trailing dims ignored                     */
+  double error_bound;    /* compress only                                    */
+  int mode;              /* compress only: lopc_eb_mode                      */
+  uint64_t* d_out_size;  /* optional device word: stream / field bytes       */
+  int32_t* d_status;     /* optional device word: this field's lopc_status   */
+} lopc_job;
+
+/* Optional figures of a batch compression. */
+typedef struct {
+  uint64_t repair_sweeps;      /* sweeps over all fields, first pass included */
+  uint64_t active_tiles_total; /* tiles processed over all sweeps             */
+  int graph;                   /* 1: the launch sequence was a graph replay   */
+  int continued;               /* 1: sweeps beyond the captured ones ran      */
+} lopc_batch_stats;
+
+/* Workspace bytes a batch of n jobs needs (op 0 = compress, 1 = decompress). */
+int lopc_batch_workspace_size(lopc_ctx* ctx, int op, int n, const lopc_job* jobs,
+                              size_t* bytes);
+
+/* Compress / decompress n jobs (n >= 1) with workspace d_ws (ws_bytes >=
+ * lopc_batch_workspace_size).  Every job is validated before any launch: a
+ * bad pointer, shape, dtype, mode or alignment returns LOPC_E_ARG, a bad
+ * bound LOPC_E_BOUND, a decompress stream shorter than its table
+ * LOPC_E_FORMAT, a decompress field capacity below the field size
+ * LOPC_E_CAPACITY, and nothing runs.  Otherwise every field is processed
+ * and its size and status are written to d_out_size / d_status (when given)
+ * and kept for lopc_ctx_last_batch; the call returns LOPC_OK if every field
+ * succeeded, else the status of the first failing job.  Buffers of different
+ * jobs must not overlap.  The first batch of a composition on a workspace
+ * allocates its graph (owned by the context until it is destroyed). */
+int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
+                        size_t ws_bytes, void* stream, lopc_batch_stats* h_stats);
+int lopc_decompress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
+                          size_t ws_bytes, void* stream);
+
+/* Per-job results of the most recent batch call, in job order (n must equal
+ * that batch's n; either array may be NULL).  After a call rejected before
+ * launch, *h_status of the offending job holds the error and the rest 0. */
+int lopc_ctx_last_batch(lopc_ctx* ctx, int n, uint64_t* h_sizes, int32_t* h_status);
+
+/* Context options.
+ *   LOPC_OPT_BATCH_GRAPH   1 (default): capture and replay batch launch
+ *                          sequences as HIP graphs; 0: direct launches.
+ *   LOPC_OPT_GRAPH_SWEEPS  repair sweeps captured in a batch graph (1..62);
+ *                          0 (default): adaptive, starting at 16.
+ *   LOPC_OPT_PERSIST_PCT   size of the persistent grids in percent of the
+ *                          resident capacity (1..400, default 100). */
+enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT = 3 };
+int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value);
 
 /* Static text for a status code. */
 const char* lopc_strerror(int status);

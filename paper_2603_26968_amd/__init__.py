@@ -14,6 +14,10 @@ _BINDING = (
     "lopc_stream_info", "lopc_workspace_size", "lopc_compress", "lopc_decompress",
     "lopc_ctx_create", "lopc_ctx_destroy", "LOPC_EB_ABS", "LOPC_EB_NOA", "LOPC_F32",
     "LOPC_F64", "Stats", "lopc_ctx_set_timing", "lopc_ctx_last_timings",
+    "compress_batch", "decompress_batch", "Job", "BatchStats", "lopc_batch_workspace_size",
+    "lopc_compress_batch", "lopc_decompress_batch", "lopc_ctx_last_batch",
+    "lopc_ctx_set_option", "LOPC_OPT_BATCH_GRAPH", "LOPC_OPT_GRAPH_SWEEPS",
+    "LOPC_OPT_PERSIST_PCT",
 )
 
 

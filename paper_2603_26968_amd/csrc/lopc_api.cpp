@@ -1,185 +1,13 @@
 // lopc_api.cpp -- host runtime of liblopc.so: argument validation, workspace
 // layout, launch sequence, status reporting.  The public contract is in
 // include/lopc.h.
-#include <hip/hip_runtime.h>
-
-#include <cmath>
-#include <cstdint>
-#include <cstdio>
-#include <cstdlib>
-#include <algorithm>
-#include <cstring>
 #include <new>
 
-#include "../../include/lopc.h"
-#include "lopc_internal.h"
+#include "lopc_host.h"
 
 using namespace lopc;
 
-struct lopc_ctx {
-  int device;
-  int num_cu;
-  // pinned host slots for small device-to-host reads
-  Params* h_prm;
-  uint32_t* h_cnt;
-  // header of the most recent successful compression
-  uint8_t last_header[64];
-  int have_header;
-  // last HIP failure (for diagnostics)
-  int hip_error;
-  char hip_where[64];
-  int sync_check;  // LOPC_SYNC_CHECK=1: synchronise after every launch
-  // phase timing
-  int timing;
-  hipEvent_t ev[8];
-  double ms[LOPC_PHASES];
-};
-
-namespace {
-
-constexpr uint32_t kMaxSweeps = 1u << 16;
-constexpr int kMinmaxBlocks = 1024;
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-struct Shape {
-  int ndim;
-  int64_t d[3];  // as given (2D: d[2] = 1)
-  uint64_t n;
-  Box box;
-};
-
-int make_shape(int ndim, const int64_t* dims, Shape* s) {
-  if ((ndim != 2 && ndim != 3) || !dims) return LOPC_E_ARG;
-  s->ndim = ndim;
-  uint64_t n = 1;
-  for (int i = 0; i < 3; ++i) {
-    int64_t v = i < ndim ? dims[i] : 1;
-    if (v < 1 || v > (int64_t)kMaxPoints) return LOPC_E_ARG;
-    s->d[i] = v;
-    n *= (uint64_t)v;
-    if (n > kMaxPoints) return LOPC_E_ARG;
-  }
-  s->n = n;
-  if (ndim == 2) {
-    s->box.nz = 1;
-    s->box.ny = (int32_t)s->d[0];
-    s->box.nx = (int32_t)s->d[1];
-  } else {
-    s->box.nz = (int32_t)s->d[0];
-    s->box.ny = (int32_t)s->d[1];
-    s->box.nx = (int32_t)s->d[2];
-  }
-  s->box.n = (uint32_t)n;
-  return LOPC_OK;
-}
-
-Tiling make_tiling(const Box& b) {
-  Tiling t;
-  if (b.nz == 1) {
-    t.tz = 1; t.ty = 32; t.tx = 64;
-  } else {
-    t.tz = 8; t.ty = 8; t.tx = 32;
-  }
-  t.ntz = (b.nz + t.tz - 1) / t.tz;
-  t.nty = (b.ny + t.ty - 1) / t.ty;
-  t.ntx = (b.nx + t.tx - 1) / t.tx;
-  t.ntiles = (uint32_t)t.ntz * t.nty * t.ntx;
-  return t;
-}
-
-struct CompressLayout {
-  size_t prm, counters, stamp, lookback, parts, zero_end;  // zeroed prefix
-  size_t part, bins, mask, sub, total;
-};
-
-// repair counters: [0] internal error flag, [1 + s % 64] tiles marked for
-// sweep s (a ring the host clears after reading)
-constexpr size_t kCounterWords = 1 + 64;
-
-CompressLayout compress_layout(const Shape& s, int dtype) {
-  const size_t k = dtype == 0 ? 4 : 8;
-  const uint64_t W = kChunkBytes / k;
-  const uint64_t nch = (s.n + W - 1) / W;
-  Tiling t = make_tiling(s.box);
-  CompressLayout L;
-  size_t o = 0;
-  L.prm = o; o += align256(sizeof(Params));
-  L.counters = o; o += align256(kCounterWords * 4);
-  L.stamp = o; o += align256((size_t)t.ntiles * 4);
-  L.lookback = o; o += align256(nch * 8);
-  L.parts = o; o += align256(nch * 8);
-  L.zero_end = o;
-  L.part = o; o += align256(16 * kMinmaxBlocks);
-  L.bins = o; o += align256(s.n * k);
-  L.mask = o; o += align256(s.n * 2);
-  L.sub = o; o += align256(s.n * 4);
-  L.total = o;
-  return L;
-}
-
-size_t decompress_ws(const Shape& s, int dtype) {
-  const size_t k = dtype == 0 ? 4 : 8;
-  const uint64_t W = kChunkBytes / k;
-  const uint64_t nch = (s.n + W - 1) / W;
-  return align256(sizeof(Params)) + align256(nch * 8);
-}
-
-int status_code(uint32_t st) {
-  if (st & ST_NONFINITE) return LOPC_E_NONFINITE;
-  if (st & ST_BOUND) return LOPC_E_BOUND;
-  if (st & ST_RANGE) return LOPC_E_RANGE;
-  if (st & ST_FORMAT) return LOPC_E_FORMAT;
-  if (st & ST_INTERNAL) return LOPC_E_INTERNAL;
-  if (st & ST_CAPACITY) return LOPC_E_CAPACITY;
-  return LOPC_OK;
-}
-
-#define HIP_TRY(expr)                         \
-  do {                                        \
-    if ((expr) != hipSuccess) return LOPC_E_HIP; \
-  } while (0)
-
-// like HIP_TRY, but records the error and the call site in the context
-#define HIP_CTX(c, expr)                                              \
-  do {                                                                \
-    hipError_t e_ = (expr);                                           \
-    if (e_ == hipSuccess && (c)->sync_check) e_ = hipDeviceSynchronize(); \
-    if (e_ != hipSuccess) {                                           \
-      (c)->hip_error = (int)e_;                                       \
-      std::strncpy((c)->hip_where, #expr, sizeof((c)->hip_where) - 1); \
-      return LOPC_E_HIP;                                              \
-    }                                                                 \
-  } while (0)
-
-// event i of the current call (no-op unless timing is on)
-hipError_t mark(lopc_ctx* c, int i, hipStream_t s) {
-  return c->timing ? hipEventRecord(c->ev[i], s) : hipSuccess;
-}
-// elapsed ms between events a and b (after the stream has synchronised)
-double span(lopc_ctx* c, int a, int b) {
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
-  return (double)ms;
-}
-
-uint64_t rd_u64(const uint8_t* p) {
-  uint64_t v = 0;
-  for (int i = 0; i < 8; ++i) v |= (uint64_t)p[i] << (8 * i);
-  return v;
-}
-uint32_t rd_u32(const uint8_t* p) {
-  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) |
-         ((uint32_t)p[3] << 24);
-}
-double rd_f64(const uint8_t* p) {
-  uint64_t u = rd_u64(p);
-  double d;
-  std::memcpy(&d, &u, 8);
-  return d;
-}
-
-}  // namespace
+using namespace lopc_host;
 
 extern "C" {
 
@@ -230,12 +58,21 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   }
   for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
   for (int i = 0; i < LOPC_PHASES; ++i) c->ms[i] = 0.0;
+  c->use_graph = 1;
+  c->graph_sweeps = 0;
+  c->sweeps_hint = 16;
+  c->persist_pct = 100;
   *out = c;
   return LOPC_OK;
 }
 
 void lopc_ctx_destroy(lopc_ctx* ctx) {
   if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (BatchGraph& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->h_plan) (void)hipHostFree(ctx->h_plan);
+  if (ctx->h_back) (void)hipHostFree(ctx->h_back);
   if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
   for (int i = 0; i < 8; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
@@ -308,6 +145,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   int st = make_shape(ndim, dims, &s);
   if (st) return st;
   if (!std::isfinite(error_bound) || !(error_bound > 0)) return LOPC_E_BOUND;
+  if (((uintptr_t)d_field & 15) || ((uintptr_t)d_stream & 3)) return LOPC_E_ARG;
   CompressLayout L = compress_layout(s, dtype);
   if (ws_bytes < L.total || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
   hipStream_t hs = (hipStream_t)stream;
@@ -462,6 +300,7 @@ static int decompress_core(lopc_ctx* ctx, const uint8_t* hdr, const void* d_stre
   const uint64_t nch = (s.n + W - 1) / W;
   if (stream_size < kHeaderBytes + 4 * nch) return LOPC_E_FORMAT;
   if (field_cap < fbytes) return LOPC_E_CAPACITY;
+  if (((uintptr_t)d_stream & 3) || ((uintptr_t)d_field & (k - 1))) return LOPC_E_ARG;
   if (ws_bytes < decompress_ws(s, dtype) || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
   uint8_t* ws = (uint8_t*)d_ws;
   Params* prm = (Params*)ws;

@@ -426,11 +426,12 @@ __device__ __forceinline__ uint8_t record_byte(uint32_t r, const uint8_t* hdr,
   return r < slen ? sp[r] : (uint8_t)0;
 }
 
+// Encodes chunk c of a field and writes its record (Sec. III-B, IV-C).
 template <int K>
-__global__ __launch_bounds__(kCT) void k_encode(
-    uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
-    const uint32_t* __restrict__ sub, uint64_t* lookback, uint32_t* parts,
-    Params* prm, uint8_t* stream, uint64_t cap, uint32_t nch) {
+__device__ void encode_body(uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
+                            const uint32_t* __restrict__ sub, uint64_t* lookback,
+                            uint32_t* parts, Params* prm, uint8_t* stream, uint64_t cap,
+                            uint32_t nch, uint32_t c) {
   using Tr = Traits<K>;
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
@@ -440,13 +441,8 @@ __global__ __launch_bounds__(kCT) void k_encode(
   __shared__ uint64_t X[kMaxUnits + 2];  // subbins after RZE_K
   __shared__ Scratch sc;
   __shared__ uint8_t hdr[kRecordHeaderBytes];
-  __shared__ uint32_t s_chunk;
   __shared__ uint64_t s_excl;
 
-  if (threadIdx.x == 0) s_chunk = atomicAdd(&prm->ticket, 1u);
-  __syncthreads();
-  const uint32_t c = s_chunk;
-  if (c >= nch) return;
   const uint32_t p0 = c * W;
   const uint32_t nc = min(W, n - p0);
   const uint32_t m = (nc + 63) / 64 * 64;
@@ -566,12 +562,26 @@ __global__ __launch_bounds__(kCT) void k_encode(
   }
 }
 
+// Single field: chunks are taken in ticket order (the look-back of a chunk
+// only waits for chunks whose workgroups already run).
+template <int K>
+__global__ __launch_bounds__(kCT) void k_encode(
+    uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
+    const uint32_t* __restrict__ sub, uint64_t* lookback, uint32_t* parts,
+    Params* prm, uint8_t* stream, uint64_t cap, uint32_t nch) {
+  __shared__ uint32_t s_chunk;
+  if (threadIdx.x == 0) s_chunk = atomicAdd(&prm->ticket, 1u);
+  __syncthreads();
+  const uint32_t c = s_chunk;
+  if (c >= nch) return;
+  encode_body<K>(n, bins, sub, lookback, parts, prm, stream, cap, nch, c);
+}
+
 // ------------------------------------------------------------------ decoder
 // Exclusive offsets of the records from the size table; the sizes must add
 // up to the stream body exactly.
-__global__ __launch_bounds__(kThreads) void k_offsets(
-    const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
-    uint64_t* offsets, Params* prm) {
+__device__ void offsets_body(const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
+                             uint64_t* offsets, Params* prm) {
   __shared__ uint64_t sh[kWaves + 1];
   const uint32_t per = (nch + kThreads - 1) / kThreads;
   const uint32_t b = threadIdx.x * per, e = min(nch, b + per);
@@ -585,6 +595,12 @@ __global__ __launch_bounds__(kThreads) void k_offsets(
     off += tab[i];
   }
   if (threadIdx.x == 0 && total != body_bytes) set_status(prm, ST_FORMAT);
+}
+
+__global__ __launch_bounds__(kThreads) void k_offsets(
+    const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
+    uint64_t* offsets, Params* prm) {
+  offsets_body(stream, nch, body_bytes, offsets, prm);
 }
 
 // Totals of the bins and subbin parts over all chunks (statistics only).
@@ -645,11 +661,12 @@ __device__ __forceinline__ void stage(uint8_t* dst, const uint8_t* src, uint32_t
     ((uint32_t*)dst)[i] = ((const uint32_t*)src)[i];
 }
 
+// Decodes chunk c of a field (Sec. IV-E); a malformed record sets FORMAT.
 template <int K>
-__global__ __launch_bounds__(kCT, 6) void k_decode(
-    const uint8_t* __restrict__ stream, uint32_t n,
-    const uint64_t* __restrict__ offsets, Params* prm,
-    typename Traits<K>::Raw* __restrict__ out) {
+__device__ void decode_body(const uint8_t* __restrict__ stream, uint32_t n,
+                            const uint64_t* __restrict__ offsets, Params* prm,
+                            typename Traits<K>::Raw* __restrict__ out, uint32_t nch,
+                            uint32_t c) {
   using Tr = Traits<K>;
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
@@ -660,11 +677,12 @@ __global__ __launch_bounds__(kCT, 6) void k_decode(
   __shared__ uint64_t gsum[64 + 1];  // per-group sums of the bin deltas
   __shared__ int s_bad;
 
-  const uint32_t nch = gridDim.x, c = blockIdx.x;
   const uint32_t p0 = c * W, nc = min(W, n - p0);
   const uint32_t m = (nc + 63) / 64 * 64, G = m / 64, L = m * K;
   const uint64_t body = kHeaderBytes + 4ull * nch;
-  if (prm->status & ST_FORMAT) return;  // offsets inconsistent
+  // offsets inconsistent (one read decides for the block: other chunks may
+  // set the flag concurrently)
+  if (__syncthreads_or(threadIdx.x == 0 && (prm->status & ST_FORMAT))) return;
   const uint32_t rsize = ((const uint32_t*)(stream + kHeaderBytes))[c];
   const uint8_t* rec = stream + body + offsets[c];
   if (threadIdx.x == 0) s_bad = 0;
@@ -860,6 +878,137 @@ __global__ __launch_bounds__(kCT, 6) void k_decode(
   if (bad) set_status(prm, ST_FORMAT);
 }
 
+template <int K>
+__global__ __launch_bounds__(kCT, 6) void k_decode(
+    const uint8_t* __restrict__ stream, uint32_t n,
+    const uint64_t* __restrict__ offsets, Params* prm,
+    typename Traits<K>::Raw* __restrict__ out) {
+  decode_body<K>(stream, n, offsets, prm, out, gridDim.x, blockIdx.x);
+}
+
+// ------------------------------------------------------------------ batches
+// Encoder over the chunks of every field of one dtype, in ticket order: a
+// chunk's look-back only waits for chunks of its field with earlier tickets,
+// which workgroups already hold.  Skipped when *gate != 0 (the repair sweeps
+// before it have not reached the fixed point: tiles are listed for sweep
+// gate_sweep).
+template <int K>
+__global__ __launch_bounds__(kCT) void k_encode_p(const BatchDesc* bd, const Job* jobs,
+                                                  int gate_sweep) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  __shared__ uint32_t s_t;
+  BatchCounters* bc = bd->bc;
+  if (gate_sweep > 0 && bc->lens[gate_sweep % kRing]) return;
+  const uint32_t i0 = bd->item0[PH_C][g0], i1 = bd->item0[PH_C][g0 + 2];
+  const int j0 = (int)bd->job0[g0], j1 = (int)bd->job0[g0 + 2];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_t = i0 + atomicAdd(&bc->enc_cursor[K == 4 ? 0 : 1], 1u);
+    __syncthreads();
+    const uint32_t t = s_t;
+    if (t >= i1) break;
+    const Job& J = jobs[find_job<&Job::c0>(jobs, j0, j1, t)];
+    encode_body<K>(J.box.n, (const typename Traits<K>::Bin*)J.bins, J.sub, J.lookback,
+                   J.parts, J.prm, J.stream, J.cap, J.nch, t - J.c0);
+  }
+}
+
+__device__ int status_of(uint32_t st) {
+  if (st & ST_NONFINITE) return -2;
+  if (st & ST_BOUND) return -3;
+  if (st & ST_RANGE) return -4;
+  if (st & ST_FORMAT) return -6;
+  if (st & ST_INTERNAL) return -9;
+  if (st & ST_CAPACITY) return -5;
+  return 0;
+}
+
+// Per-field results of a compress batch: stream size and status.
+__global__ __launch_bounds__(kThreads) void k_finalize_c(const BatchDesc* bd, const Job* jobs,
+                                                         int gate_sweep) {
+  if (gate_sweep > 0 && bd->bc->lens[gate_sweep % kRing]) return;
+  BatchResult* res = bd->res;
+  const uint32_t nj = bd->job0[kGroups];
+  for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < nj; j += gridDim.x * kThreads) {
+    const Job& J = jobs[j];
+    const int st = status_of(J.prm->status);
+    const uint64_t size = J.prm->stream_size;
+    res[j].size = size;
+    res[j].status = st;
+    if (J.out_size) *J.out_size = size;
+    if (J.out_status) *J.out_status = st;
+  }
+}
+
+// Header check of a field to decode (the same rules as the host parser),
+// then the record offsets from its size table.
+__global__ __launch_bounds__(kThreads) void k_dhead_p(const BatchDesc* bd, const Job* jobs) {
+  __shared__ int s_ok;
+  const int nj = (int)bd->job0[kGroups];
+  for (int j = blockIdx.x; j < nj; j += gridDim.x) {
+    const Job& J = jobs[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint8_t* h = J.stream;
+      auto u64 = [&](int o) {
+        uint64_t v = 0;
+        for (int b = 0; b < 8; ++b) v |= (uint64_t)h[o + b] << (8 * b);
+        return v;
+      };
+      bool ok = (u64(0) & 0xFFFFFFFFFFFFull) == ((uint64_t)kMagic | ((uint64_t)kVersion << 32));
+      ok = ok && h[6] == J.dtype && h[7] == J.ndim && h[32] <= 1 &&
+           (uint32_t)u64(36) == kChunkBytes;
+      for (int i = 0; i < 3; ++i)
+        ok = ok && u64(8 + 8 * i) == (uint64_t)(i < J.ndim ? J.dims[i] : 1);
+      const double e = __longlong_as_double((long long)u64(48));
+      const double v = __longlong_as_double((long long)u64(56));
+      ok = ok && finite64(u64(48)) && e > 0.0 && finite64(u64(56)) && v > 0.0;
+      ok = ok && fma(v, e, -1.0) >= 0.0 &&
+           fma(__longlong_as_double((long long)u64(56) - 1), e, -1.0) < 0.0;
+      if (!ok) set_status(J.prm, ST_FORMAT);
+      s_ok = ok;
+    }
+    __syncthreads();
+    if (s_ok)
+      offsets_body(J.stream, J.nch, J.stream_size - kHeaderBytes - 4ull * J.nch, J.offsets,
+                   J.prm);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kCT, 6) void k_decode_p(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  __shared__ uint32_t s_t;
+  BatchCounters* bc = bd->bc;
+  const uint32_t i0 = bd->item0[PH_C][g0], i1 = bd->item0[PH_C][g0 + 2];
+  const int j0 = (int)bd->job0[g0], j1 = (int)bd->job0[g0 + 2];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_t = i0 + atomicAdd(&bc->dec_cursor[K == 4 ? 0 : 1], 1u);
+    __syncthreads();
+    const uint32_t t = s_t;
+    if (t >= i1) break;
+    const Job& J = jobs[find_job<&Job::c0>(jobs, j0, j1, t)];
+    decode_body<K>(J.stream, J.box.n, J.offsets, J.prm,
+                   (typename Traits<K>::Raw*)J.y, J.nch, t - J.c0);
+  }
+}
+
+// Per-field results of a decompress batch: field bytes and status.
+__global__ __launch_bounds__(kThreads) void k_finalize_d(const BatchDesc* bd, const Job* jobs) {
+  BatchResult* res = bd->res;
+  const uint32_t nj = bd->job0[kGroups];
+  for (uint32_t j = blockIdx.x * kThreads + threadIdx.x; j < nj; j += gridDim.x * kThreads) {
+    const Job& J = jobs[j];
+    const int st = status_of(J.prm->status);
+    const uint64_t size = st ? 0 : (uint64_t)J.box.n * (J.dtype == 0 ? 4u : 8u);
+    res[j].size = size;
+    res[j].status = st;
+    if (J.out_size) *J.out_size = size;
+    if (J.out_status) *J.out_status = st;
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -900,6 +1049,48 @@ hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
   else
     k_decode<8><<<nch, kCT, 0, s>>>(stream, n, offsets, prm, (uint64_t*)field);
   return hipGetLastError();
+}
+
+hipError_t launch_encode_p(int dtype, const BatchDesc* bd, const Job* jobs, int gate_sweep,
+                           int grid, hipStream_t s) {
+  if (dtype == 0) k_encode_p<4><<<grid, kCT, 0, s>>>(bd, jobs, gate_sweep);
+  else k_encode_p<8><<<grid, kCT, 0, s>>>(bd, jobs, gate_sweep);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_c(const BatchDesc* bd, const Job* jobs, int gate_sweep,
+                             hipStream_t s) {
+  k_finalize_c<<<4, kThreads, 0, s>>>(bd, jobs, gate_sweep);
+  return hipGetLastError();
+}
+
+hipError_t launch_dhead_p(const BatchDesc* bd, const Job* jobs, int grid, hipStream_t s) {
+  k_dhead_p<<<grid, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                           hipStream_t s) {
+  if (dtype == 0) k_decode_p<4><<<grid, kCT, 0, s>>>(bd, jobs);
+  else k_decode_p<8><<<grid, kCT, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_d(const BatchDesc* bd, const Job* jobs, hipStream_t s) {
+  k_finalize_d<<<4, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+int codec_blocks_per_cu(int kernel) {
+  int b = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (kernel) {
+    case PK_ENCODE: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_encode_p<8>, kCT, 0); break;
+    case PK_DHEAD: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_dhead_p, kThreads, 0); break;
+    case PK_DECODE: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_decode_p<8>, kCT, 0); break;
+    default: break;
+  }
+  return e == hipSuccess && b > 0 ? b : 1;
 }
 
 }  // namespace lopc

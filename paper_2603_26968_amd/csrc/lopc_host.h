@@ -1,0 +1,208 @@
+// lopc_host.h -- host-side internals of liblopc.so shared by the single-field
+// calls (lopc_api.cpp) and the batch calls (lopc_batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lopc.h"
+#include "lopc_internal.h"
+
+// A captured batch launch sequence.
+struct BatchGraph {
+  int op;              // 0 compress, 1 decompress
+  const void* ws;      // workspace it was captured on
+  uint32_t gmask;      // groups present
+  int sweeps;          // repair sweeps captured (compress)
+  int grid_pct;        // persistent grid size it was captured with
+  uint64_t used;       // last use (for eviction)
+  hipGraphExec_t exec;
+};
+
+struct lopc_ctx {
+  int device;
+  int num_cu;
+  // pinned host slots for small device-to-host reads
+  lopc::Params* h_prm;
+  uint32_t* h_cnt;
+  // header of the most recent successful compression
+  uint8_t last_header[64];
+  int have_header;
+  // last HIP failure (for diagnostics)
+  int hip_error;
+  char hip_where[64];
+  int sync_check;  // LOPC_SYNC_CHECK=1: synchronise after every launch
+  // phase timing
+  int timing;
+  hipEvent_t ev[8];
+  double ms[LOPC_PHASES];
+  // batches
+  int use_graph;       // capture batch sequences as graphs
+  int graph_sweeps;    // sweeps per graph (0 = adaptive)
+  int sweeps_hint;     // adaptive capture size
+  int persist_pct;     // persistent grid size, percent of resident capacity
+  int per_cu[lopc::PK_COUNT];  // resident blocks per CU (0 = not queried)
+  hipStream_t cap_stream;      // stream used for captures
+  void* h_plan;        // pinned staging of the plan + job table
+  size_t h_plan_cap;
+  void* h_back;        // pinned read-back of counters + results
+  size_t h_back_cap;
+  uint64_t use_clock;
+  std::vector<BatchGraph> graphs;
+  std::vector<uint64_t> last_sizes;
+  std::vector<int32_t> last_status;
+};
+
+namespace lopc_host {
+using namespace lopc;
+
+constexpr uint32_t kMaxSweeps = 1u << 16;
+constexpr int kMinmaxBlocks = 1024;
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Shape {
+  int ndim;
+  int64_t d[3];  // as given (2D: d[2] = 1)
+  uint64_t n;
+  Box box;
+};
+
+inline int make_shape(int ndim, const int64_t* dims, Shape* s) {
+  if ((ndim != 2 && ndim != 3) || !dims) return LOPC_E_ARG;
+  s->ndim = ndim;
+  uint64_t n = 1;
+  for (int i = 0; i < 3; ++i) {
+    int64_t v = i < ndim ? dims[i] : 1;
+    if (v < 1 || v > (int64_t)kMaxPoints) return LOPC_E_ARG;
+    s->d[i] = v;
+    n *= (uint64_t)v;
+    if (n > kMaxPoints) return LOPC_E_ARG;
+  }
+  s->n = n;
+  if (ndim == 2) {
+    s->box.nz = 1;
+    s->box.ny = (int32_t)s->d[0];
+    s->box.nx = (int32_t)s->d[1];
+  } else {
+    s->box.nz = (int32_t)s->d[0];
+    s->box.ny = (int32_t)s->d[1];
+    s->box.nx = (int32_t)s->d[2];
+  }
+  s->box.n = (uint32_t)n;
+  return LOPC_OK;
+}
+
+inline Tiling make_tiling(const Box& b) {
+  Tiling t;
+  if (b.nz == 1) {
+    t.tz = 1; t.ty = 32; t.tx = 64;
+  } else {
+    t.tz = 8; t.ty = 8; t.tx = 32;
+  }
+  t.ntz = (b.nz + t.tz - 1) / t.tz;
+  t.nty = (b.ny + t.ty - 1) / t.ty;
+  t.ntx = (b.nx + t.tx - 1) / t.tx;
+  t.ntiles = (uint32_t)t.ntz * t.nty * t.ntx;
+  return t;
+}
+
+struct CompressLayout {
+  size_t prm, counters, stamp, lookback, parts, zero_end;  // zeroed prefix
+  size_t part, bins, mask, sub, total;
+};
+
+// repair counters: [0] internal error flag, [1 + s % 64] tiles marked for
+// sweep s (a ring the host clears after reading)
+constexpr size_t kCounterWords = 1 + 64;
+
+inline CompressLayout compress_layout(const Shape& s, int dtype) {
+  const size_t k = dtype == 0 ? 4 : 8;
+  const uint64_t W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  Tiling t = make_tiling(s.box);
+  CompressLayout L;
+  size_t o = 0;
+  L.prm = o; o += align256(sizeof(Params));
+  L.counters = o; o += align256(kCounterWords * 4);
+  L.stamp = o; o += align256((size_t)t.ntiles * 4);
+  L.lookback = o; o += align256(nch * 8);
+  L.parts = o; o += align256(nch * 8);
+  L.zero_end = o;
+  L.part = o; o += align256(16 * kMinmaxBlocks);
+  L.bins = o; o += align256(s.n * k);
+  L.mask = o; o += align256(s.n * 2);
+  L.sub = o; o += align256(s.n * 4);
+  L.total = o;
+  return L;
+}
+
+inline size_t decompress_ws(const Shape& s, int dtype) {
+  const size_t k = dtype == 0 ? 4 : 8;
+  const uint64_t W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  return align256(sizeof(Params)) + align256(nch * 8);
+}
+
+inline int status_code(uint32_t st) {
+  if (st & ST_NONFINITE) return LOPC_E_NONFINITE;
+  if (st & ST_BOUND) return LOPC_E_BOUND;
+  if (st & ST_RANGE) return LOPC_E_RANGE;
+  if (st & ST_FORMAT) return LOPC_E_FORMAT;
+  if (st & ST_INTERNAL) return LOPC_E_INTERNAL;
+  if (st & ST_CAPACITY) return LOPC_E_CAPACITY;
+  return LOPC_OK;
+}
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    if ((expr) != hipSuccess) return LOPC_E_HIP; \
+  } while (0)
+
+// like HIP_TRY, but records the error and the call site in the context
+#define HIP_CTX(c, expr)                                              \
+  do {                                                                \
+    hipError_t e_ = (expr);                                           \
+    if (e_ == hipSuccess && (c)->sync_check) e_ = hipDeviceSynchronize(); \
+    if (e_ != hipSuccess) {                                           \
+      (c)->hip_error = (int)e_;                                       \
+      std::strncpy((c)->hip_where, #expr, sizeof((c)->hip_where) - 1); \
+      return LOPC_E_HIP;                                              \
+    }                                                                 \
+  } while (0)
+
+// event i of the current call (no-op unless timing is on)
+inline hipError_t mark(lopc_ctx* c, int i, hipStream_t s) {
+  return c->timing ? hipEventRecord(c->ev[i], s) : hipSuccess;
+}
+// elapsed ms between events a and b (after the stream has synchronised)
+inline double span(lopc_ctx* c, int a, int b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
+  return (double)ms;
+}
+
+inline uint64_t rd_u64(const uint8_t* p) {
+  uint64_t v = 0;
+  for (int i = 0; i < 8; ++i) v |= (uint64_t)p[i] << (8 * i);
+  return v;
+}
+inline uint32_t rd_u32(const uint8_t* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) |
+         ((uint32_t)p[3] << 24);
+}
+inline double rd_f64(const uint8_t* p) {
+  uint64_t u = rd_u64(p);
+  double d;
+  std::memcpy(&d, &u, 8);
+  return d;
+}
+
+}  // namespace lopc_host

@@ -56,6 +56,99 @@ struct Tiling {
   uint32_t ntiles;
 };
 
+// ------------------------------------------------------------------ batches
+// A batch runs every phase as one persistent launch per (dtype, tile shape)
+// group over a batch-wide work-queue of (field, block), (field, tile) or
+// (field, chunk) items.  Everything a launch needs is read from device
+// memory (the plan below and the job table), so one captured launch sequence
+// serves every batch of the same composition and workspace.
+
+// Points per item of the batched min/max and quantize passes.
+constexpr uint32_t kMinmaxSpan = 65536;
+constexpr uint32_t kQuantSpan = 16384;
+// Work-list ring: slot s % 64 holds sweep s.
+constexpr uint32_t kRing = 64;
+
+// group of a field: 2 * dtype + (3D)
+constexpr int kGroups = 4;
+enum { PH_MM = 0, PH_Q = 1, PH_T = 2, PH_C = 3, PH_N = 4 };
+
+// Counters at the start of a batch workspace (cleared with the rest of the
+// zeroed prefix at the start of every batch).
+struct alignas(256) BatchCounters {
+  uint32_t err;           // relaxation limit hit (never expected)
+  uint32_t zero;          // stays 0: the gate of launches that must run
+  uint32_t enc_cursor[2];  // encoder tickets per dtype
+  uint32_t dec_cursor[2];  // decoder tickets per dtype
+  uint32_t pad[2];
+  uint32_t lens[kRing];     // tiles listed for sweep s (slot s % 64)
+  uint32_t cursors[kRing];  // work-queue cursor of sweep s
+};
+
+// Per-field descriptor.  Items of every phase are numbered batch-wide (jobs
+// sorted by group); a field owns [mm0, mm0 + mm_blocks) etc.
+struct Job {
+  const void* x;         // field to compress
+  void* y;               // field to decode into
+  uint8_t* stream;       // stream (compress output / decompress input)
+  uint64_t cap;          // stream capacity (compress)
+  uint64_t stream_size;  // stream size (decompress input)
+  uint64_t* out_size;    // caller's result words (may be null)
+  int32_t* out_status;
+  Box box;
+  Tiling tl;
+  uint32_t nch;
+  int32_t dtype, mode, ndim, mm_blocks;
+  int64_t dims[3];
+  double eb;
+  Params* prm;
+  void* bins;
+  uint16_t* mask;
+  uint32_t* sub;
+  uint32_t* stamp;
+  uint64_t* lookback;
+  uint32_t* parts;
+  int64_t* part;      // min/max partials
+  uint64_t* offsets;  // record offsets (decompress)
+  uint32_t mm0, q0, t0, c0;
+};
+
+// Result of one field, read back by the host after the batch.
+struct BatchResult {
+  uint64_t size;   // stream bytes (compress) / field bytes (decompress)
+  int32_t status;  // lopc_status
+  uint32_t pad;
+};
+
+// Batch plan: jobs of group g are [job0[g], job0[g + 1]); items of group g in
+// phase ph are [item0[ph][g], item0[ph][g + 1]).
+// The job table follows the plan in memory.
+struct alignas(256) BatchDesc {
+  uint32_t job0[kGroups + 1];
+  uint32_t item0[PH_N][kGroups + 1];
+  uint32_t tiles;        // capacity of each work list
+  uint32_t pad;
+  uint64_t zero_words;   // 32-bit words cleared at the start of a batch
+  uint32_t* zero_base;   // start of the cleared region (bc is its head)
+  BatchCounters* bc;
+  uint32_t* lists;       // two work lists of `tiles` items (sweep parity)
+  BatchResult* res;      // one result per job
+};
+
+// index of the job owning batch-wide item `item` of the phase whose
+// prefixes start at member `first`, among jobs [lo, hi) (sorted by it; the
+// largest index whose prefix is <= item, which skips fields with no items)
+template <uint32_t Job::*first>
+__device__ __forceinline__ int find_job(const Job* jobs, int lo, int hi, uint32_t item) {
+  hi -= 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].*first <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Launchers (lopc_kernels.hip).  All enqueue on `s` and return the HIP
 // status of the last launch.
 hipError_t launch_minmax(int dtype, const void* x, uint32_t n, double* part,
@@ -84,5 +177,35 @@ hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
 hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
                          const uint64_t* offsets, Params* prm, void* field,
                          hipStream_t s);
+
+// Batch launchers (persistent grids; `grid` blocks drain the queue).  Every
+// launch reads the plan `bd` and the job table `jobs` that follows it.
+// `gate_sweep` > 0: skip unless no tile was listed for that sweep.
+hipError_t launch_zero_p(const BatchDesc* bd, int grid, hipStream_t s);
+hipError_t launch_zero_n(uint32_t* words, uint64_t nwords, hipStream_t s);
+hipError_t launch_minmax_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                           hipStream_t s);
+hipError_t launch_params_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                           hipStream_t s);
+hipError_t launch_quant_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                          hipStream_t s);
+hipError_t launch_tile0_p(int group, const BatchDesc* bd, const Job* jobs, int grid,
+                          hipStream_t s);
+hipError_t launch_repair_p(const BatchDesc* bd, const Job* jobs, uint32_t sweep, int grid,
+                           hipStream_t s);
+hipError_t launch_encode_p(int dtype, const BatchDesc* bd, const Job* jobs, int gate_sweep,
+                           int grid, hipStream_t s);
+hipError_t launch_finalize_c(const BatchDesc* bd, const Job* jobs, int gate_sweep,
+                             hipStream_t s);
+hipError_t launch_dhead_p(const BatchDesc* bd, const Job* jobs, int grid, hipStream_t s);
+hipError_t launch_decode_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                           hipStream_t s);
+hipError_t launch_finalize_d(const BatchDesc* bd, const Job* jobs, hipStream_t s);
+
+// Resident blocks per CU of each persistent batch kernel (occupancy query).
+enum { PK_ZERO, PK_MINMAX, PK_PARAMS, PK_QUANT, PK_TILE0, PK_REPAIR, PK_ENCODE, PK_DHEAD,
+       PK_DECODE, PK_COUNT };
+int batch_blocks_per_cu(int kernel);
+int codec_blocks_per_cu(int kernel);
 
 }  // namespace lopc

@@ -20,13 +20,12 @@ namespace {
 
 // ------------------------------------------------------------------ a0
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_minmax(
-    const typename Traits<K>::Raw* x, uint32_t n, int64_t* part, Params* prm) {
+__device__ void minmax_body(const typename Traits<K>::Raw* x, uint32_t n, int64_t* part,
+                            Params* prm, uint32_t blk, uint32_t nblk) {
   using Tr = Traits<K>;
   int64_t lo = INT64_MAX, hi = INT64_MIN;
   bool bad = false;
-  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += gridDim.x * kThreads) {
+  for (uint32_t i = blk * kThreads + threadIdx.x; i < n; i += nblk * kThreads) {
     typename Tr::Raw u = x[i];
     bad |= !Tr::finite(u);
     int64_t k = Tr::key(u);
@@ -46,16 +45,22 @@ __global__ __launch_bounds__(kThreads) void k_minmax(
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = slo[0];
-    part[2 * blockIdx.x + 1] = shi[0];
+    part[2 * blk] = slo[0];
+    part[2 * blk + 1] = shi[0];
   }
 }
 
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_params(
-    int mode, double eb, const int64_t* part, int nblocks, Params* prm,
-    uint8_t* stream, uint64_t cap, int ndim, int64_t d0, int64_t d1,
-    int64_t d2) {
+__global__ __launch_bounds__(kThreads) void k_minmax(
+    const typename Traits<K>::Raw* x, uint32_t n, int64_t* part, Params* prm) {
+  minmax_body<K>(x, n, part, prm, blockIdx.x, gridDim.x);
+}
+
+
+template <int K>
+__device__ void params_body(int mode, double eb, const int64_t* part, int nblocks,
+                            Params* prm, uint8_t* stream, uint64_t cap, int ndim,
+                            int64_t d0, int64_t d1, int64_t d2) {
   using Tr = Traits<K>;
   __shared__ int64_t slo[kThreads], shi[kThreads];
   int64_t lo = INT64_MAX, hi = INT64_MIN;
@@ -120,12 +125,21 @@ __global__ __launch_bounds__(kThreads) void k_params(
   }
 }
 
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_params(
+    int mode, double eb, const int64_t* part, int nblocks, Params* prm,
+    uint8_t* stream, uint64_t cap, int ndim, int64_t d0, int64_t d1,
+    int64_t d2) {
+  params_body<K>(mode, eb, part, nblocks, prm, stream, cap, ndim, d0, d1, d2);
+}
+
+
 // ------------------------------------------------------------------ a1
 // Quantize every point once (Sec. IV-A): 16-byte loads and stores.
 template <int K>
-__global__ __launch_bounds__(kThreads) void k_quant(
-    const typename Traits<K>::Raw* __restrict__ x, uint32_t n, Params* prm,
-    typename Traits<K>::Bin* __restrict__ bins) {
+__device__ void quant_body(const typename Traits<K>::Raw* __restrict__ x, uint32_t n,
+                           Params* prm, typename Traits<K>::Bin* __restrict__ bins,
+                           uint32_t blk, uint32_t nblk) {
   using Tr = Traits<K>;
   using Raw = typename Tr::Raw;
   using Bin = typename Tr::Bin;
@@ -133,7 +147,7 @@ __global__ __launch_bounds__(kThreads) void k_quant(
   const double inv = prm->inv;
   bool bad_v = false, bad_r = false;
   const uint32_t nv = n / V;
-  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nv; i += gridDim.x * kThreads) {
+  for (uint32_t i = blk * kThreads + threadIdx.x; i < nv; i += nblk * kThreads) {
     Raw u[V];
     Bin b[V];
     *(uint4*)u = ((const uint4*)x)[i];
@@ -146,8 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_quant(
     }
     ((uint4*)bins)[i] = *(const uint4*)b;
   }
-  for (uint32_t i = nv * V + blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += gridDim.x * kThreads) {
+  for (uint32_t i = nv * V + blk * kThreads + threadIdx.x; i < n; i += nblk * kThreads) {
     Raw u = x[i];
     bad_v |= !Tr::finite(u);
     int64_t q = Tr::q(Tr::to_double(u), inv);
@@ -157,6 +170,14 @@ __global__ __launch_bounds__(kThreads) void k_quant(
   if (bad_v) set_status(prm, ST_NONFINITE);
   if (bad_r) set_status(prm, ST_RANGE);
 }
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_quant(
+    const typename Traits<K>::Raw* __restrict__ x, uint32_t n, Params* prm,
+    typename Traits<K>::Bin* __restrict__ bins) {
+  quant_body<K>(x, n, prm, bins, blockIdx.x, gridDim.x);
+}
+
 
 // ------------------------------------------------------------------ a3
 // Tiles of the subbin repair.  A workgroup owns a TZ x TY x TX tile and keeps
@@ -266,12 +287,12 @@ __device__ void mark_neighbours(bool edge, const TileCoord& c, const Tiling& tl,
 // First pass, fused: build the order flags of the owned points (a2, the
 // flags of Alg. 1) from the bins and values of the tile and its halo, write
 // them, then relax with halo subbins 0 (the first sweep of a3).
+// Returns (block-uniform) whether a boundary subbin of the tile is nonzero.
 template <int K, int TZ, int TY, int TX>
-__global__ __launch_bounds__(kThreads) void k_tile0(
-    const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl,
-    const typename Traits<K>::Bin* __restrict__ bins,
-    uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
-    uint32_t* counters) {
+__device__ bool tile0_body(const typename Traits<K>::Raw* __restrict__ x, Box box,
+                           Tiling tl, const typename Traits<K>::Bin* __restrict__ bins,
+                           uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
+                           uint32_t* counters, uint32_t t, TileCoord& c) {
   using Tr = Traits<K>;
   using G = TileGeom<TZ, TY, TX>;
   using Key = typename Tr::Bin;  // keys fit the signed type of the bins
@@ -285,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
   Bin* BN = (Bin*)(buf + G::H * sizeof(Key));
   uint32_t* S = (uint32_t*)buf;  // reused once the flags are built
 
-  const TileCoord c = tile_coord<TZ, TY, TX>(blockIdx.x, tl);
+  c = tile_coord<TZ, TY, TX>(t, tl);
   {
     // issue every load of the halo first, then store to LDS
     typename Tr::Raw u[HL];
@@ -367,21 +388,35 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
       if (v && G::on_edge(i)) edge = 1;
     }
   }
-  edge = __syncthreads_or(edge);
+  return __syncthreads_or(edge) != 0;
+}
+
+template <int K, int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_tile0(
+    const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl,
+    const typename Traits<K>::Bin* __restrict__ bins,
+    uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
+    uint32_t* counters) {
+  TileCoord c;
+  const bool edge = tile0_body<K, TZ, TY, TX>(x, box, tl, bins, mask, sub, counters,
+                                              blockIdx.x, c);
   mark_neighbours(edge, c, tl, stamp, counters, 1);
 }
 
+
 // Later sweeps: tiles marked for this sweep reload their halo and relax.
+// One sweep of tile t if it is marked for it.  Returns (block-uniform) whether
+// a boundary subbin changed; false if the tile did not run.
 template <int TZ, int TY, int TX>
-__global__ __launch_bounds__(kThreads) void k_repair(
-    Box box, Tiling tl, const uint16_t* __restrict__ mask,
-    uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
-    uint32_t sweep) {
+__device__ bool repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
+                            uint32_t* __restrict__ sub, const uint32_t* stamp,
+                            uint32_t* counters, uint32_t sweep, uint32_t t, TileCoord& c) {
   using G = TileGeom<TZ, TY, TX>;
   __shared__ uint32_t S[G::H];
-  const uint32_t t = blockIdx.x;
-  if (stamp[t] < sweep) return;
-  const TileCoord c = tile_coord<TZ, TY, TX>(t, tl);
+  // one read decides for the whole block (a neighbour may raise the stamp
+  // concurrently)
+  if (!__syncthreads_or(threadIdx.x == 0 && stamp[t] >= sweep)) return false;
+  c = tile_coord<TZ, TY, TX>(t, tl);
   constexpr int HL = (G::H + kThreads - 1) / kThreads;
   {
     uint32_t hv[HL];
@@ -427,8 +462,148 @@ __global__ __launch_bounds__(kThreads) void k_repair(
       if (G::on_edge(i)) edge = 1;
     }
   }
-  edge = __syncthreads_or(edge);
-  mark_neighbours(edge, c, tl, stamp, counters, sweep + 1);
+  return __syncthreads_or(edge) != 0;
+}
+
+template <int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_repair(
+    Box box, Tiling tl, const uint16_t* __restrict__ mask,
+    uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
+    uint32_t sweep) {
+  TileCoord c;
+  if (repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, sweep, blockIdx.x, c))
+    mark_neighbours(true, c, tl, stamp, counters, sweep + 1);
+}
+
+
+
+// ------------------------------------------------------------------ batches
+// Persistent kernels: a fixed grid drains the batch-wide items of one phase.
+
+// mark the 26 neighbour tiles of a tile of a batch field for sweep `next`
+// and append the newly marked ones (as batch-wide tile items) to that
+// sweep's work list; each tile is listed at most once per sweep
+__device__ void mark_list(bool edge, const TileCoord& c, const Tiling& tl, uint32_t* stamp,
+                          uint32_t t0, uint32_t* lens, uint32_t* list, uint32_t next) {
+  if (threadIdx.x >= 64) return;
+  bool newly = false;
+  uint32_t item = 0;
+  if (edge && threadIdx.x < 27) {
+    int dz = (int)threadIdx.x / 9 - 1, dy = ((int)threadIdx.x / 3) % 3 - 1,
+        dx = (int)threadIdx.x % 3 - 1;
+    int nz = c.tz + dz, ny = c.ty + dy, nx = c.tx + dx;
+    if ((dz | dy | dx) != 0 && nz >= 0 && nz < tl.ntz && ny >= 0 && ny < tl.nty &&
+        nx >= 0 && nx < tl.ntx) {
+      uint32_t u = ((uint32_t)nz * tl.nty + ny) * tl.ntx + nx;
+      newly = atomicMax(&stamp[u], next) < next;
+      item = t0 + u;
+    }
+  }
+  const uint64_t m = __ballot(newly);
+  if (!m) return;
+  uint32_t pos = 0;
+  if (threadIdx.x == 0) pos = atomicAdd(&lens[next % kRing], (uint32_t)__popcll(m));
+  pos = __shfl(pos, 0, 64);
+  if (newly) list[pos + lane_prefix(m)] = item;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_p(const BatchDesc* bd) {
+  const uint64_t n = bd->zero_words;
+  uint32_t* base = bd->zero_base;
+  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kThreads)
+    base[i] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_n(uint32_t* w, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * kThreads)
+    w[i] = 0;
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_minmax_p(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  const uint32_t i1 = bd->item0[PH_MM][g0 + 2];
+  const int j0 = (int)bd->job0[g0], j1 = (int)bd->job0[g0 + 2];
+  for (uint32_t it = bd->item0[PH_MM][g0] + blockIdx.x; it < i1; it += gridDim.x) {
+    const Job& J = jobs[find_job<&Job::mm0>(jobs, j0, j1, it)];
+    __syncthreads();
+    minmax_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.part, J.prm, it - J.mm0,
+                   (uint32_t)J.mm_blocks);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_params_p(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  const int j1 = (int)bd->job0[g0 + 2];
+  for (int j = (int)bd->job0[g0] + (int)blockIdx.x; j < j1; j += (int)gridDim.x) {
+    const Job& J = jobs[j];
+    __syncthreads();
+    params_body<K>(J.mode, J.eb, J.part, J.mm_blocks, J.prm, J.stream, J.cap, J.ndim,
+                   J.dims[0], J.dims[1], J.ndim == 3 ? J.dims[2] : 1);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_quant_p(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  const uint32_t i1 = bd->item0[PH_Q][g0 + 2];
+  const int j0 = (int)bd->job0[g0], j1 = (int)bd->job0[g0 + 2];
+  for (uint32_t it = bd->item0[PH_Q][g0] + blockIdx.x; it < i1; it += gridDim.x) {
+    const Job& J = jobs[find_job<&Job::q0>(jobs, j0, j1, it)];
+    quant_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.prm,
+                  (typename Traits<K>::Bin*)J.bins, it - J.q0,
+                  (J.box.n + kQuantSpan - 1) / kQuantSpan);
+  }
+}
+
+template <int K, int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_tile0_p(const BatchDesc* bd, const Job* jobs,
+                                                      int g) {
+  BatchCounters* bc = bd->bc;
+  uint32_t* list1 = bd->lists + bd->tiles;  // sweep 1: odd list
+  const uint32_t i1 = bd->item0[PH_T][g + 1];
+  const int j0 = (int)bd->job0[g], j1 = (int)bd->job0[g + 1];
+  for (uint32_t it = bd->item0[PH_T][g] + blockIdx.x; it < i1; it += gridDim.x) {
+    const Job& J = jobs[find_job<&Job::t0>(jobs, j0, j1, it)];
+    __syncthreads();
+    TileCoord c;
+    const bool edge = tile0_body<K, TZ, TY, TX>(
+        (const typename Traits<K>::Raw*)J.x, J.box, J.tl,
+        (const typename Traits<K>::Bin*)J.bins, J.mask, J.sub, &bc->err, it - J.t0, c);
+    mark_list(edge, c, J.tl, J.stamp, J.t0, bc->lens, list1, 1);
+  }
+}
+
+// One sweep over the tiles listed for it, of fields of both tile shapes.
+__global__ __launch_bounds__(kThreads) void k_repair_p(const BatchDesc* bd, const Job* jobs,
+                                                       uint32_t sweep) {
+  __shared__ uint32_t s_it;
+  BatchCounters* bc = bd->bc;
+  const uint32_t* list_in = bd->lists + (sweep & 1) * bd->tiles;
+  uint32_t* list_out = bd->lists + ((sweep + 1) & 1) * bd->tiles;
+  const uint32_t n = bc->lens[sweep % kRing];
+  const int nj = (int)bd->job0[kGroups];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_it = atomicAdd(&bc->cursors[sweep % kRing], 1u);
+    __syncthreads();
+    const uint32_t it = s_it;
+    if (it >= n) break;
+    const uint32_t item = list_in[it];
+    const Job& J = jobs[find_job<&Job::t0>(jobs, 0, nj, item)];
+    TileCoord c;
+    bool edge;
+    if (J.tl.tz == 1)
+      edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+                                    item - J.t0, c);
+    else
+      edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+                                   item - J.t0, c);
+    if (edge) mark_list(true, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
+  }
 }
 
 }  // namespace
@@ -494,6 +669,72 @@ hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
   else
     k_repair<8, 8, 32><<<t.ntiles, kThreads, 0, s>>>(box, t, mask, sub, stamp, counters, sweep);
   return hipGetLastError();
+}
+
+hipError_t launch_zero_p(const BatchDesc* bd, int grid, hipStream_t s) {
+  k_zero_p<<<grid, kThreads, 0, s>>>(bd);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_n(uint32_t* words, uint64_t nwords, hipStream_t s) {
+  if (!nwords) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(1024, (nwords + kThreads - 1) / kThreads);
+  k_zero_n<<<grid, kThreads, 0, s>>>(words, nwords);
+  return hipGetLastError();
+}
+
+hipError_t launch_minmax_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                           hipStream_t s) {
+  if (dtype == 0) k_minmax_p<4><<<grid, kThreads, 0, s>>>(bd, jobs);
+  else k_minmax_p<8><<<grid, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_params_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                           hipStream_t s) {
+  if (dtype == 0) k_params_p<4><<<grid, kThreads, 0, s>>>(bd, jobs);
+  else k_params_p<8><<<grid, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
+                          hipStream_t s) {
+  if (dtype == 0) k_quant_p<4><<<grid, kThreads, 0, s>>>(bd, jobs);
+  else k_quant_p<8><<<grid, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile0_p(int group, const BatchDesc* bd, const Job* jobs, int grid,
+                          hipStream_t s) {
+  switch (group) {
+    case 0: k_tile0_p<4, 1, 32, 64><<<grid, kThreads, 0, s>>>(bd, jobs, 0); break;
+    case 1: k_tile0_p<4, 8, 8, 32><<<grid, kThreads, 0, s>>>(bd, jobs, 1); break;
+    case 2: k_tile0_p<8, 1, 32, 64><<<grid, kThreads, 0, s>>>(bd, jobs, 2); break;
+    default: k_tile0_p<8, 8, 8, 32><<<grid, kThreads, 0, s>>>(bd, jobs, 3); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_repair_p(const BatchDesc* bd, const Job* jobs, uint32_t sweep, int grid,
+                           hipStream_t s) {
+  k_repair_p<<<grid, kThreads, 0, s>>>(bd, jobs, sweep);
+  return hipGetLastError();
+}
+
+// resident blocks per CU of the persistent kernels of this file
+int batch_blocks_per_cu(int kernel) {
+  int b = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (kernel) {
+    case PK_ZERO: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_zero_p, kThreads, 0); break;
+    case PK_MINMAX: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_minmax_p<8>, kThreads, 0); break;
+    case PK_PARAMS: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_params_p<8>, kThreads, 0); break;
+    case PK_QUANT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_quant_p<8>, kThreads, 0); break;
+    case PK_TILE0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_tile0_p<8, 8, 8, 32>, kThreads, 0); break;
+    case PK_REPAIR: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_p, kThreads, 0); break;
+    default: break;
+  }
+  return e == hipSuccess && b > 0 ? b : 1;
 }
 
 }  // namespace lopc

@@ -30,7 +30,9 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_workspace_size", "lopc_compress", "lopc_stream_info",
            "lopc_decompress", "lopc_strerror", "lopc_ctx_set_timing",
            "lopc_ctx_last_timings", "lopc_ctx_last_hip_error", "lopc_decompress_h",
-           "lopc_ctx_last_header")
+           "lopc_ctx_last_header", "lopc_batch_workspace_size", "lopc_compress_batch",
+           "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option")
+LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT = 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
 
@@ -47,6 +49,24 @@ class Stats(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("repair_sweeps", ctypes.c_uint64),
                 ("active_tiles_total", ctypes.c_uint64), ("bins_bytes", ctypes.c_uint64),
                 ("subbins_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Job(ctypes.Structure):
+    """lopc_job: one field of a batch."""
+    _fields_ = [("d_in", ctypes.c_void_p), ("in_bytes", ctypes.c_size_t),
+                ("d_out", ctypes.c_void_p), ("out_cap", ctypes.c_size_t),
+                ("dtype", ctypes.c_int), ("ndim", ctypes.c_int),
+                ("dims", ctypes.c_int64 * 3), ("error_bound", ctypes.c_double),
+                ("mode", ctypes.c_int), ("d_out_size", ctypes.c_void_p),
+                ("d_status", ctypes.c_void_p)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("repair_sweeps", ctypes.c_uint64), ("active_tiles_total", ctypes.c_uint64),
+                ("graph", ctypes.c_int), ("continued", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -96,6 +116,18 @@ def load() -> ctypes.CDLL:
     L.lopc_ctx_last_header.restype = ci
     L.lopc_ctx_last_hip_error.argtypes = [vp, ctypes.POINTER(ci)]
     L.lopc_ctx_last_hip_error.restype = ctypes.c_char_p
+    jp = ctypes.POINTER(Job)
+    L.lopc_batch_workspace_size.argtypes = [vp, ci, ci, jp, szp]
+    L.lopc_batch_workspace_size.restype = ci
+    L.lopc_compress_batch.argtypes = [vp, ci, jp, vp, sz, vp, ctypes.POINTER(BatchStats)]
+    L.lopc_compress_batch.restype = ci
+    L.lopc_decompress_batch.argtypes = [vp, ci, jp, vp, sz, vp]
+    L.lopc_decompress_batch.restype = ci
+    L.lopc_ctx_last_batch.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(ctypes.c_int32)]
+    L.lopc_ctx_last_batch.restype = ci
+    L.lopc_ctx_set_option.argtypes = [vp, ci, ctypes.c_int64]
+    L.lopc_ctx_set_option.restype = ci
     _lib = L
     return L
 
@@ -206,6 +238,42 @@ def lopc_ctx_last_header(ctx) -> bytes:
     return buf.raw
 
 
+def lopc_ctx_set_option(ctx: int, option: int, value: int) -> None:
+    st = load().lopc_ctx_set_option(ctx, option, int(value))
+    if st:
+        raise LopcError(st, "lopc_ctx_set_option")
+
+
+def lopc_batch_workspace_size(ctx: int, op: int, jobs) -> int:
+    n = ctypes.c_size_t()
+    st = load().lopc_batch_workspace_size(ctx, op, len(jobs), jobs, ctypes.byref(n))
+    if st:
+        raise LopcError(st, "lopc_batch_workspace_size")
+    return n.value
+
+
+def lopc_compress_batch(ctx, jobs, d_ws, ws_bytes, stream):
+    """Raw call: returns (status, BatchStats)."""
+    stats = BatchStats()
+    st = load().lopc_compress_batch(ctx, len(jobs), jobs, d_ws, ws_bytes, stream,
+                                    ctypes.byref(stats))
+    return st, stats
+
+
+def lopc_decompress_batch(ctx, jobs, d_ws, ws_bytes, stream) -> int:
+    return load().lopc_decompress_batch(ctx, len(jobs), jobs, d_ws, ws_bytes, stream)
+
+
+def lopc_ctx_last_batch(ctx, n: int):
+    """(sizes, statuses) of the most recent batch call, in job order."""
+    sizes = (ctypes.c_uint64 * n)()
+    sts = (ctypes.c_int32 * n)()
+    st = load().lopc_ctx_last_batch(ctx, n, sizes, sts)
+    if st:
+        raise LopcError(st, "lopc_ctx_last_batch")
+    return list(sizes), list(sts)
+
+
 # ------------------------------------------------------------------ torch API
 _ctx = {}
 
@@ -307,6 +375,125 @@ def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
     if st:
         raise LopcError(st, "lopc_decompress", ctx)
     return out
+
+
+# ------------------------------------------------------------------ batches
+_ws_cache = {}
+
+
+def _workspace(ctx, nbytes, dev, workspace=None):
+    """Caller's workspace, else a per-context one grown as needed (a stable
+    address lets the library replay its captured launch sequence)."""
+    if workspace is not None:
+        if workspace.numel() < nbytes:
+            raise ValueError(f"workspace holds {workspace.numel()} bytes, {nbytes} needed")
+        return workspace
+    w = _ws_cache.get(ctx)
+    if w is None or w.numel() < nbytes:
+        w = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        _ws_cache[ctx] = w
+    return w
+
+
+def _align(v, a=256):
+    return (v + a - 1) // a * a
+
+
+def compress_batch(fields, error_bounds, modes="noa", out: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None, stats: bool = False, ctx=None,
+                   raise_on_error: bool = True):
+    """Compress many independent 2D/3D float32/float64 device tensors in one
+    batch call.  ``error_bounds`` and ``modes`` are scalars or one per field.
+    Streams are packed into ``out`` (allocated if None) at 256-byte aligned
+    offsets; returns the list of stream views (None for a failed field when
+    ``raise_on_error`` is false), then the batch stats dict if ``stats``."""
+    n = len(fields)
+    if n == 0:
+        return ([], {}) if stats else []
+    ebs = list(error_bounds) if hasattr(error_bounds, "__len__") else [error_bounds] * n
+    mds = list(modes) if isinstance(modes, (list, tuple)) else [modes] * n
+    if len(ebs) != n or len(mds) != n:
+        raise ValueError("one error bound and one mode per field")
+    dev = fields[0].device
+    ctx = context(dev.index) if ctx is None else ctx
+    caps = []
+    for x in fields:
+        _check_field(x)
+        if x.device != dev:
+            raise ValueError("all fields of a batch live on one device")
+        caps.append(_sizes_for(ctx, x.shape, x.dtype)[0])
+    offs, total = [], 0
+    for c in caps:
+        offs.append(total)
+        total += _align(c)
+    if out is None or out.numel() < total:
+        out = torch.empty(total, dtype=torch.uint8, device=dev)
+    jobs = (Job * n)()
+    base = out.data_ptr()
+    for i, x in enumerate(fields):
+        j = jobs[i]
+        j.d_in = x.data_ptr()
+        j.d_out = base + offs[i]
+        j.out_cap = caps[i]
+        j.dtype = _dtype_code(x.dtype)
+        j.ndim = x.dim()
+        for d in range(x.dim()):
+            j.dims[d] = int(x.shape[d])
+        j.error_bound = float(ebs[i])
+        j.mode = _mode(mds[i])
+    wsz = lopc_batch_workspace_size(ctx, 0, jobs)
+    ws = _workspace(ctx, wsz, dev, workspace)
+    s = torch.cuda.current_stream(dev).cuda_stream
+    st, bst = lopc_compress_batch(ctx, jobs, ws.data_ptr(), ws.numel(), s)
+    if st and (raise_on_error or st in (LOPC_E_ARG, LOPC_E_HIP, LOPC_E_INTERNAL)):
+        raise LopcError(st, "lopc_compress_batch", ctx)
+    sizes, sts = lopc_ctx_last_batch(ctx, n)
+    res = [out[offs[i]:offs[i] + sizes[i]] if sts[i] == 0 else None for i in range(n)]
+    if stats:
+        d = bst.as_dict()
+        d["status"] = sts
+        return res, d
+    return res
+
+
+def decompress_batch(streams, outs=None, workspace: torch.Tensor | None = None,
+                     headers=None, ctx=None, raise_on_error: bool = True):
+    """Decompress many streams (contiguous uint8 device tensors) in one batch
+    call.  Shapes and dtypes come from ``headers`` (host bytes, one per
+    stream) or from each stream's first 64 bytes.  Returns the list of
+    fields (None for a failed stream when ``raise_on_error`` is false)."""
+    n = len(streams)
+    if n == 0:
+        return []
+    dev = streams[0].device
+    ctx = context(dev.index) if ctx is None else ctx
+    if headers is None:
+        heads = torch.stack([s[:HEADER_BYTES] for s in streams]).cpu().numpy()
+        headers = [heads[i].tobytes() for i in range(n)]
+    infos = [lopc_stream_info(h) for h in headers]
+    if outs is None:
+        outs = [torch.empty(inf["shape"], dtype=inf["dtype"], device=dev) for inf in infos]
+    jobs = (Job * n)()
+    for i, (s, inf, y) in enumerate(zip(streams, infos, outs)):
+        if not s.is_cuda or s.dtype != torch.uint8 or not s.is_contiguous():
+            raise ValueError("streams must be contiguous uint8 device tensors")
+        j = jobs[i]
+        j.d_in = s.data_ptr()
+        j.in_bytes = s.numel()
+        j.d_out = y.data_ptr()
+        j.out_cap = y.numel() * y.element_size()
+        j.dtype = _dtype_code(inf["dtype"])
+        j.ndim = len(inf["shape"])
+        for d, v in enumerate(inf["shape"]):
+            j.dims[d] = v
+    wsz = lopc_batch_workspace_size(ctx, 1, jobs)
+    ws = _workspace(ctx, wsz, dev, workspace)
+    st = lopc_decompress_batch(ctx, jobs, ws.data_ptr(), ws.numel(),
+                               torch.cuda.current_stream(dev).cuda_stream)
+    if st and (raise_on_error or st in (LOPC_E_ARG, LOPC_E_HIP, LOPC_E_INTERNAL)):
+        raise LopcError(st, "lopc_decompress_batch", ctx)
+    _, sts = lopc_ctx_last_batch(ctx, n)
+    return [outs[i] if sts[i] == 0 else None for i in range(n)]
 
 
 # load eagerly: a missing library is an import error, never a silent fallback

@@ -13,6 +13,8 @@ This module holds no compression arithmetic: it only makes inputs.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -39,9 +41,7 @@ def gaussian_bumps(shape, seed: int = 0, n_bumps: int = 32, noise: float = 1e-3,
     rng = _rng(seed)
     shape = tuple(int(s) for s in shape)
     nd = len(shape)
-    axes = [np.arange(s, dtype=np.float64) for s in shape]
-    out = np.zeros(shape, np.float64)
-    grids = np.meshgrid(*axes, indexing="ij", sparse=True)
+    bumps = []
     for _ in range(n_bumps):
         amp = rng.uniform(-1.0, 1.0)
         sig = rng.uniform(sigma_range[0], sigma_range[1], size=nd)
@@ -52,14 +52,44 @@ def gaussian_bumps(shape, seed: int = 0, n_bumps: int = 32, noise: float = 1e-3,
         else:
             q, r = np.linalg.qr(rng.standard_normal((3, 3)))
             rot = q * np.sign(np.diag(r))
-        prec = rot @ np.diag(1.0 / sig ** 2) @ rot.T
-        d = [g - c for g, c in zip(grids, centre)]
-        quad = np.zeros(shape, np.float64)
-        for a in range(nd):
-            for b in range(nd):
-                if prec[a, b] != 0.0:
-                    quad += prec[a, b] * (d[a] * d[b])
-        out += amp * np.exp(-0.5 * quad)
+        bumps.append((amp, centre, rot @ np.diag(1.0 / sig ** 2) @ rot.T))
+    out = np.zeros(shape, np.float64)
+
+    def slab(lo, hi):
+        # the quadratic form split into terms over pairs of axes, so that only
+        # their sum runs over the full grid
+        sub = out[lo:hi]
+        axes = [np.arange(lo, hi, dtype=np.float64)] + \
+            [np.arange(s, dtype=np.float64) for s in shape[1:]]
+        grids = np.meshgrid(*axes, indexing="ij", sparse=True)
+        for amp, centre, P in bumps:
+            d = [g - c for g, c in zip(grids, centre)]
+            if nd == 2:
+                quad = P[0, 0] * (d[0] * d[0]) + (P[0, 1] + P[1, 0]) * (d[0] * d[1]) + \
+                    P[1, 1] * (d[1] * d[1])
+            else:
+                a = P[0, 0] * (d[0] * d[0]) + (P[0, 1] + P[1, 0]) * (d[0] * d[1]) + \
+                    P[1, 1] * (d[1] * d[1])
+                b = (P[0, 2] + P[2, 0]) * (d[0] * d[2])
+                c = (P[1, 2] + P[2, 1]) * (d[1] * d[2]) + P[2, 2] * (d[2] * d[2])
+                quad = a + b
+                quad += c
+            np.multiply(quad, -0.5, out=quad)
+            np.exp(quad, out=quad)
+            quad *= amp
+            sub += quad
+
+    # slabs of about 256K points keep the temporaries small; numpy's
+    # element-wise loops release the GIL, so slabs run on threads
+    n0 = shape[0]
+    plane = max(1, out.size // n0)
+    step = max(1, (1 << 18) // plane)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    if workers == 1 or n0 <= step:
+        slab(0, n0)
+    else:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(lambda lo: slab(lo, min(n0, lo + step)), range(0, n0, step)))
     if noise:
         out += rng.normal(0.0, noise, size=shape)
     return out.astype(dtype)
