@@ -1,18 +1,30 @@
 #!/usr/bin/env python
 """Benchmark of the LOPC hot path on one MI355X.
 
-One step = compress + decompress (every step of the path: NOA range,
-quantize, order mask, repair sweeps to the fixed point, chunk encoders and
-stream assembly, decoders and reconstruction) of the 3D float32 256^3
-turbulence field (power-law GRF, P(k) ~ k^-3, + 1% noise, normalised to
-[0, 1]) at a NOA bound of 1e-3 (bit-exact).  The field is resident in HBM
-before the timed region starts.
+Default workload (the headline line): one step = compress + decompress
+(every step of the path: NOA range, quantize, order flags, repair sweeps to
+the fixed point, chunk encoders and stream assembly, record offsets, chunk
+decoders and reconstruction) of the 3D float32 256^3 turbulence field
+(power-law GRF, P(k) ~ k^-3, + 1% noise, normalised to [0, 1]) at a NOA
+bound of 1e-3, bit-exact.  The field is resident in HBM before the timed
+region starts.  value = uncompressed bytes / (compress + decompress time),
+GB/s (1e9 B/s).
 
-value = uncompressed bytes / (compress + decompress time), GB/s (1e9 B/s).
+Other workloads (--workload), one JSON line each:
+  smooth2d     2D float32 512^2 Gaussian bumps, NOA 1e-3
+  fronts2d     2D float32 1800 x 3600 periodic fronts, NOA 1e-3
+  lognormal3d  3D float64 512^3 exp(2 g) floored at its 10th percentile, NOA 1e-3
+  batch        256 uneven float32 fields (2D side 64..1024, 3D side 32..192,
+               NOA bounds 1e-4..1e-2): one batch compress + one batch
+               decompress per step
+  serve        Poisson request streams (compress or decompress, 1 MiB to
+               512 MiB, float32/float64, 2D/3D) at 0.25 .. 1.1 times the
+               single-slot service rate, served on 4 slots under a 64 GiB
+               HBM budget: p50 / p99 latency and GB/s per rate
 
-Prints one JSON line.  Usage:
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--eb 1e-3]
-                  [--no-cpu-baseline] [--all-eb]
+Prints one JSON line per workload.  Usage:
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload turb3d]
+                  [--eb 1e-3] [--no-cpu-baseline] [--all-eb]
 """
 from __future__ import annotations
 
@@ -28,6 +40,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, public spec
+METRIC = "LOPC compress+decompress GB/s (uncompressed bytes / round-trip time), bit-exact"
+
+SINGLE = {
+    # name: (generator, shape, description)
+    "turb3d": ("turbulence_field", (256, 256, 256),
+               "3D float32 256^3 GRF P(k)~k^-3 + 1% noise, [0,1]"),
+    "smooth2d": ("smooth_field", (512, 512), "2D float32 512^2 32 Gaussian bumps + N(0,1e-3)"),
+    "fronts2d": ("fronts_field", (1800, 3600), "2D float32 1800x3600 periodic sinusoids + fronts"),
+    "lognormal3d": ("lognormal_field", (512, 512, 512),
+                    "3D float64 512^3 exp(2g), g GRF P(k)~k^-2.5, floored at 10th pct"),
+}
 
 
 def parse():
@@ -35,14 +58,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="turb3d",
+                    choices=list(SINGLE) + ["batch", "serve"])
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--all-eb", action="store_true",
                     help="also time the 1e-2 and 1e-4 bounds of the same field")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
     return ap.parse_args()
 
 
+# ------------------------------------------------------------------ single field
 def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing):
     import torch
     stream_buf, ws_c, ws_d, y = bufs
@@ -70,19 +97,25 @@ def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing):
     return (t1 - t0), {k: v / max(steps, 1) for k, v in phase.items()}, stats, s
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                          "described in DESIGN.md and not built", "n_gpus": args.gpus}))
-        sys.exit(2)
+def oracle_roundtrip(xh, eb):
+    import oracle
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liblopc_ref.so")):
+        oracle.build()
+    t0 = time.perf_counter()
+    s = oracle.compress(xh, eb, oracle.NOA)
+    y = oracle.decompress(s)
+    return s, y, time.perf_counter() - t0
+
+
+def bench_single(args, name):
     import torch
 
     import paper_2603_26968_amd as P
     from paper_2603_26968_amd import lopc, synth
 
+    gen, shape, desc = SINGLE[name]
     dev = torch.device("cuda:0")
-    xh = synth.turbulence_field(seed=args.seed)
+    xh = getattr(synth, gen)(shape, seed=args.seed)
     n, k = xh.size, xh.itemsize
     x = torch.from_numpy(xh).to(dev)
     ctx = lopc.context(0)
@@ -101,12 +134,12 @@ def main():
     t_d = phase["offsets"] + phase["decode"]
     value = n * k / (dt / args.steps) / 1e9
 
-    # the decoder kernel: algorithmic bytes = stream bytes read + field written
+    # algorithmic bytes of the two codec kernels: the decoder reads the
+    # stream and writes the field; the encoder reads bins and subbins and
+    # writes the stream
     dec_bytes = S + n * k
     dec_gbps = dec_bytes / (phase["decode"] * 1e-3) / 1e9 if phase["decode"] else 0.0
-    # the encoder kernel: bins + subbins read, stream written
-    kb = 4 if k == 4 else 8
-    enc_bytes = n * kb + n * 4 + S
+    enc_bytes = n * k + n * 4 + S
     enc_gbps = enc_bytes / (phase["encode"] * 1e-3) / 1e9 if phase["encode"] else 0.0
     kernels = {
         "decode": {"ms": phase["decode"], "bytes": dec_bytes, "GBps": dec_gbps},
@@ -131,14 +164,14 @@ def main():
                 "decompress_GBps": round(n * k / ((ph["offsets"] + ph["decode"]) * 1e-3) / 1e9, 2),
                 "CR": round(n * k / se.numel(), 3), "repair_sweeps": int(st["repair_sweeps"])}
 
+    dtname = "f32" if k == 4 else "f64"
     out = {
-        "metric": "LOPC compress+decompress GB/s (uncompressed bytes / round-trip time), bit-exact",
+        "metric": METRIC,
         "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "turb3d: 3D float32 256^3 GRF P(k)~k^-3 + 1% noise, [0,1]; "
-                               f"NOA eb {args.eb:g}; compress + decompress",
-                   "shape": list(xh.shape), "eb": args.eb, "mode": "NOA",
+        "config": {"workload": f"{name}: {desc}; NOA eb {args.eb:g}; compress + decompress",
+                   "shape": list(xh.shape), "field_dtype": dtname, "eb": args.eb, "mode": "NOA",
                    "arithmetic": "binary64 quantizer/decoder, 32-bit integer repair and codecs"},
         "compress_GBps": round(n * k / (t_c * 1e-3) / 1e9, 2) if t_c else None,
         "decompress_GBps": round(n * k / (t_d * 1e-3) / 1e9, 2) if t_d else None,
@@ -154,20 +187,218 @@ def main():
         out["other_eb"] = extra
 
     if not args.no_cpu_baseline:
+        # the oracle on a bounded sample: the whole field when it is small,
+        # else the leading slab of the same field (about 16M points)
+        sl = xh
+        if xh.size > (1 << 24):
+            rows = max(1, (1 << 24) // (xh.size // xh.shape[0]))
+            sl = np.ascontiguousarray(xh[:rows])
+        ref_stream, ref_y, t_cpu = oracle_roundtrip(sl, args.eb)
+        what = "the whole field" if sl is xh else f"its leading slab {list(sl.shape)}"
+        out["cpu_baseline"] = {"value": round(sl.nbytes / t_cpu / 1e9, 5), "unit": "GB/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"one compress + decompress of {what} "
+                                         f"({sl.nbytes / 1e6:.0f} MB), single-threaded C oracle, "
+                                         f"{t_cpu:.1f} s"}
+        if sl is xh:
+            out["parity"] = {"stream_identical": gpu_stream == ref_stream,
+                             "reconstruction_identical": bool(np.array_equal(
+                                 gpu_y.view(np.uint8), ref_y.view(np.uint8)))}
+        else:
+            # the slab through the GPU path as well
+            xs = torch.from_numpy(sl).to(dev)
+            s2 = P.compress(xs, args.eb, "noa")
+            y2 = P.decompress(s2)
+            out["parity"] = {"sample": "leading slab",
+                             "stream_identical": s2.cpu().numpy().tobytes() == ref_stream,
+                             "reconstruction_identical": bool(np.array_equal(
+                                 y2.cpu().numpy().view(np.uint8), ref_y.view(np.uint8)))}
+    return out
+
+
+# ------------------------------------------------------------------ batch
+def _oracle_field(args_tuple):
+    x, eb = args_tuple
+    import oracle
+    t0 = time.perf_counter()
+    s = oracle.compress(x, eb, oracle.NOA)
+    oracle.decompress(s)
+    return time.perf_counter() - t0, len(s)
+
+
+def bench_batch(args):
+    import torch
+
+    import paper_2603_26968_amd as P
+    from paper_2603_26968_amd import lopc, synth
+
+    fields = synth.batch_fields(256, seed=args.seed)
+    xs = [torch.from_numpy(x).cuda() for x, _ in fields]
+    ebs = [eb for _, eb in fields]
+    nbytes = sum(x.nbytes for x, _ in fields)
+    ctx = lopc.context(0)
+    caps = [lopc.lopc_compress_bound(x.shape, x.dtype) for x in xs]
+    out = torch.empty(sum((c + 255) // 256 * 256 for c in caps), dtype=torch.uint8, device="cuda")
+    ys = [torch.empty_like(x) for x in xs]
+
+    def step():
+        streams, st, hdrs = P.compress_batch(xs, ebs, "noa", out=out, stats=True, headers=True)
+        P.decompress_batch(streams, outs=ys, headers=hdrs)
+        return streams, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tc = td = 0.0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        streams, st, hdrs = P.compress_batch(xs, ebs, "noa", out=out, stats=True, headers=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P.decompress_batch(streams, outs=ys, headers=hdrs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tc += t1 - t0
+        td += t2 - t1
+    tc /= args.steps
+    td /= args.steps
+    S = sum(int(s.numel()) for s in streams)
+    # identity: every batch stream equals its single-field stream, every
+    # decoded field the single-field decode
+    ident = True
+    for x, eb, s, y in zip(xs, ebs, streams, ys):
+        s1 = P.compress(x, eb, "noa")
+        if not torch.equal(s1, s):
+            ident = False
+            break
+        if not torch.equal(P.decompress(s1).view(torch.uint8), y.view(torch.uint8)):
+            ident = False
+            break
+    res = {
+        "metric": METRIC, "value": round(nbytes / (tc + td) / 1e9, 3), "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round((tc + td) * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch: 256 float32 fields, 2D side log-U[64,1024] or 3D side "
+                               "log-U[32,192], NOA eb log-U[1e-4,1e-2]; one batch compress + "
+                               "one batch decompress",
+                   "fields": len(xs), "total_bytes": nbytes},
+        "compress_GBps": round(nbytes / tc / 1e9, 2), "decompress_GBps": round(nbytes / td / 1e9, 2),
+        "CR": round(nbytes / S, 3), "repair_sweeps": int(st["repair_sweeps"]),
+        "graph": int(st["graph"]), "sweeps_continued": int(st["continued"]),
+        "hbm_frac_algorithmic": round(2 * (nbytes + S) / (tc + td) / 1e9 / HBM_PEAK_GBPS, 4),
+        "identity_batch_vs_single": ident,
+    }
+    if not args.no_cpu_baseline:
+        from concurrent.futures import ProcessPoolExecutor
         import oracle
         if not os.path.exists(os.path.join(ROOT, "oracle", "liblopc_ref.so")):
             oracle.build()
+        sample = fields[::16]
+        sb = sum(x.nbytes for x, _ in sample)
+        workers = min(16, os.cpu_count() or 1, len(sample))
         t0 = time.perf_counter()
-        ref_stream = oracle.compress(xh, args.eb, oracle.NOA)
-        ref_y = oracle.decompress(ref_stream)
-        t_cpu = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(n * k / t_cpu / 1e9, 5), "unit": "GB/s", "cores": 1,
+        with ProcessPoolExecutor(workers) as ex:
+            list(ex.map(_oracle_field, sample))
+        tw = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(sb / tw / 1e9, 5), "unit": "GB/s", "cores": workers,
                                "kind": "oracle",
-                               "sample": "one compress + decompress of the same 256^3 field "
-                                         f"({n * k / 1e6:.0f} MB), single-threaded C oracle, "
-                                         f"{t_cpu:.1f} s"}
-        out["parity"] = {"stream_identical": gpu_stream == ref_stream,
-                         "reconstruction_identical": bool(np.array_equal(gpu_y.view(np.uint32), ref_y.view(np.uint32)))}
+                               "sample": f"every 16th field ({len(sample)} fields, {sb / 1e6:.0f} MB), "
+                                         f"one process per field, {tw:.1f} s"}
+    return res
+
+
+# ------------------------------------------------------------------ serving
+def bench_serve(args):
+    import torch
+
+    import paper_2603_26968_amd as P
+    from paper_2603_26968_amd import serve, synth
+
+    n_templates = 64
+    base2 = torch.from_numpy(synth.smooth_field()).cuda()
+    base3 = torch.from_numpy(synth.turbulence_field((256, 256, 256))).cuda()
+    T = []
+    for spec in synth.serving_requests(n_templates, seed=7):
+        base = base2 if len(spec["shape"]) == 2 else base3
+        x = synth.reflect_tile(base, spec["shape"])
+        x = x.to(torch.float32 if spec["dtype"] == np.float32 else torch.float64).contiguous()
+        s, hdr = P.compress(x, spec["eb"], "noa", header=True)
+        s = s.clone()
+        if spec["op"] == "compress":
+            T.append(dict(op="compress", data=x, eb=spec["eb"], want=s, bytes=x.nbytes))
+        else:
+            y = P.decompress(s, header=hdr)
+            T.append(dict(op="decompress", data=s, header=hdr, want=y, bytes=y.nbytes))
+            del x
+    torch.cuda.synchronize()
+    budget = 64 << 30
+    slots = 4
+
+    def make(i, keep):
+        t = T[i % n_templates]
+        return serve.Request(t["op"], t["data"], eb=t.get("eb", 0.0), header=t.get("header"),
+                             tag=i % n_templates, keep=keep)
+
+    def same(r):
+        got, want = r.result, T[r.tag]["want"]
+        return got.shape == want.shape and torch.equal(
+            got.view(torch.uint8) if got.dtype != torch.uint8 else got,
+            want.view(torch.uint8) if want.dtype != torch.uint8 else want)
+
+    # service rate of one slot, requests back to back
+    with serve.Server(budget, slots=1) as one:
+        reqs = [one.submit(make(i, False)) for i in range(n_templates)]
+        for r in reqs:
+            r.done.wait()
+        t0 = time.perf_counter()
+        reqs = [one.submit(make(i, False)) for i in range(n_templates)]
+        for r in reqs:
+            r.done.wait()
+        mu = n_templates / (time.perf_counter() - t0)
+    rates = {}
+    ident = True
+    with serve.Server(budget, slots=slots) as srv:
+        for f in (0.25, 0.5, 0.75, 0.9, 1.1):
+            offs = serve.poisson_arrivals(args.requests, rate=f * mu, seed=7)
+            reqs = serve.run_arrivals(srv, lambda i: make(i, i % 50 == 0), offs)
+            st = serve.latency_stats(reqs, lambda r: T[r.tag]["bytes"])
+            kept = [r for r in reqs if r.keep and r.error is None]
+            st["identity_checked"] = len(kept)
+            st["identity_alone_vs_mix"] = all(same(r) for r in kept)
+            ident = ident and st["identity_alone_vs_mix"] and st["failed"] == 0
+            st["rate_per_s"] = round(f * mu, 2)
+            rates[str(f)] = {q: (round(v, 3) if isinstance(v, float) else v) for q, v in st.items()}
+            del reqs, kept
+            print(json.dumps({"serve_rate_done": f, **rates[str(f)]}), file=sys.stderr, flush=True)
+        peak = srv.admission.peak
+    top = rates["0.9"]
+    return {
+        "metric": METRIC, "value": top["GBps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": n_templates, "ms_per_step": top["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serve: Poisson requests (compress or decompress, 1-512 MiB, "
+                               "f32/f64, 2D/3D, NOA eb log-U[1e-4,1e-2]) on 4 slots, 64 GiB budget; "
+                               "value = GB/s served at 0.9 x the single-slot service rate",
+                   "templates": n_templates, "requests_per_rate": args.requests, "slots": slots},
+        "service_rate_one_slot_per_s": round(mu, 2),
+        "rates": rates, "identity_alone_vs_mix": ident, "admission_peak_bytes": peak,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
+                          "described in DESIGN.md and not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.workload == "batch":
+        out = bench_batch(args)
+    elif args.workload == "serve":
+        out = bench_serve(args)
+    else:
+        out = bench_single(args, args.workload)
     print(json.dumps(out), flush=True)
 
 

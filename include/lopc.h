@@ -191,6 +191,21 @@ int lopc_decompress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws
  * launch, *h_status of the offending job holds the error and the rest 0. */
 int lopc_ctx_last_batch(lopc_ctx* ctx, int n, uint64_t* h_sizes, int32_t* h_status);
 
+/* The 64-byte stream headers of the most recent lopc_compress_batch, in job
+ * order (n * 64 bytes into h_headers; zeros for a failed job), e.g. to pass
+ * to lopc_decompress_h without reading them back from the streams. */
+int lopc_ctx_last_batch_headers(lopc_ctx* ctx, int n, void* h_headers);
+
+/* Autotuner of the batch path: runs the batch (op 0 = compress, 1 =
+ * decompress) with each candidate size of the persistent grids (25, 50,
+ * 100, 200, 400 % of the resident capacity), once untimed and `reps` times
+ * timed (host clock around the synchronous call), keeps the fastest in the
+ * context (as LOPC_OPT_PERSIST_PCT) and returns it in *h_pct (may be NULL).
+ * The outputs are those of an ordinary call.  Errors as lopc_compress_batch;
+ * a per-field failure does not stop the tuning. */
+int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void* d_ws,
+                        size_t ws_bytes, void* stream, int reps, int* h_pct);
+
 /* Context options.
  *   LOPC_OPT_BATCH_GRAPH   1 (default): capture and replay batch launch
  *                          sequences as HIP graphs; 0: direct launches.

@@ -17,7 +17,8 @@ _BINDING = (
     "compress_batch", "decompress_batch", "Job", "BatchStats", "lopc_batch_workspace_size",
     "lopc_compress_batch", "lopc_decompress_batch", "lopc_ctx_last_batch",
     "lopc_ctx_set_option", "LOPC_OPT_BATCH_GRAPH", "LOPC_OPT_GRAPH_SWEEPS",
-    "LOPC_OPT_PERSIST_PCT",
+    "LOPC_OPT_PERSIST_PCT", "lopc_ctx_last_batch_headers", "lopc_batch_autotune",
+    "autotune_compress_batch",
 )
 
 

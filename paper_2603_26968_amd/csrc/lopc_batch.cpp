@@ -11,6 +11,7 @@
 //   compress: min/max partials, two tile work lists, then per field its
 //             bins, order flags and subbins
 //   decompress: record offsets of every field
+#include <chrono>
 #include <new>
 
 #include "lopc_host.h"
@@ -308,9 +309,12 @@ int collect(lopc_ctx* c, const Plan& P, int n) {
   const BatchResult* r = host_results(c);
   c->last_sizes.assign(n, 0);
   c->last_status.assign(n, 0);
+  c->last_headers.assign((size_t)n * kHeaderBytes, 0);
   for (int q = 0; q < n; ++q) {
-    c->last_sizes[P.order[q]] = r[q].size;
-    c->last_status[P.order[q]] = r[q].status;
+    const int i = P.order[q];
+    c->last_sizes[i] = r[q].size;
+    c->last_status[i] = r[q].status;
+    std::memcpy(&c->last_headers[(size_t)i * kHeaderBytes], r[q].header, kHeaderBytes);
   }
   for (int i = 0; i < n; ++i)
     if (c->last_status[i]) return c->last_status[i];
@@ -320,6 +324,7 @@ int collect(lopc_ctx* c, const Plan& P, int n) {
 void reject(lopc_ctx* c, int n, int bad, int st) {
   c->last_sizes.assign(n > 0 ? n : 0, 0);
   c->last_status.assign(n > 0 ? n : 0, 0);
+  c->last_headers.assign((size_t)(n > 0 ? n : 0) * kHeaderBytes, 0);
   if (bad >= 0 && bad < n) c->last_status[bad] = st;
 }
 
@@ -465,6 +470,44 @@ int lopc_ctx_last_batch(lopc_ctx* ctx, int n, uint64_t* h_sizes, int32_t* h_stat
     if (h_sizes) h_sizes[i] = ctx->last_sizes[i];
     if (h_status) h_status[i] = ctx->last_status[i];
   }
+  return LOPC_OK;
+}
+
+int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void* d_ws,
+                        size_t ws_bytes, void* stream, int reps, int* h_pct) {
+  if (!ctx || (op != 0 && op != 1) || reps < 1) return LOPC_E_ARG;
+  static const int kCand[] = {25, 50, 100, 200, 400};
+  const int keep = ctx->persist_pct;
+  int best = keep;
+  double best_t = 1e300;
+  for (int pct : kCand) {
+    ctx->persist_pct = pct;
+    // one call to capture (or warm) this configuration, then the timed ones
+    double t = 0.0;
+    for (int r = 0; r <= reps; ++r) {
+      auto t0 = std::chrono::steady_clock::now();
+      int st = op == 0 ? lopc_compress_batch(ctx, n, jobs, d_ws, ws_bytes, stream, nullptr)
+                       : lopc_decompress_batch(ctx, n, jobs, d_ws, ws_bytes, stream);
+      auto t1 = std::chrono::steady_clock::now();
+      if (st == LOPC_E_ARG || st == LOPC_E_HIP || st == LOPC_E_INTERNAL) {
+        ctx->persist_pct = keep;
+        return st;
+      }
+      if (r) t += std::chrono::duration<double>(t1 - t0).count();
+    }
+    if (t < best_t) {
+      best_t = t;
+      best = pct;
+    }
+  }
+  ctx->persist_pct = best;
+  if (h_pct) *h_pct = best;
+  return LOPC_OK;
+}
+
+int lopc_ctx_last_batch_headers(lopc_ctx* ctx, int n, void* h_headers) {
+  if (!ctx || !h_headers || n < 0 || (size_t)n != ctx->last_sizes.size()) return LOPC_E_ARG;
+  std::memcpy(h_headers, ctx->last_headers.data(), (size_t)n * kHeaderBytes);
   return LOPC_OK;
 }
 

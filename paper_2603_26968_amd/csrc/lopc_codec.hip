@@ -935,6 +935,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize_c(const BatchDesc* bd, co
     const uint64_t size = J.prm->stream_size;
     res[j].size = size;
     res[j].status = st;
+    for (int b = 0; b < (int)kHeaderBytes; ++b) res[j].header[b] = J.prm->header[b];
     if (J.out_size) *J.out_size = size;
     if (J.out_status) *J.out_status = st;
   }

@@ -58,6 +58,7 @@ struct lopc_ctx {
   std::vector<BatchGraph> graphs;
   std::vector<uint64_t> last_sizes;
   std::vector<int32_t> last_status;
+  std::vector<uint8_t> last_headers;  // 64 bytes per job (compress batches)
 };
 
 namespace lopc_host {

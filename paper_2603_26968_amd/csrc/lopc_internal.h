@@ -118,6 +118,7 @@ struct BatchResult {
   uint64_t size;   // stream bytes (compress) / field bytes (decompress)
   int32_t status;  // lopc_status
   uint32_t pad;
+  uint8_t header[64];  // compress: the stream header
 };
 
 // Batch plan: jobs of group g are [job0[g], job0[g + 1]); items of group g in

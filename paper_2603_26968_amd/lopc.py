@@ -31,7 +31,8 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_decompress", "lopc_strerror", "lopc_ctx_set_timing",
            "lopc_ctx_last_timings", "lopc_ctx_last_hip_error", "lopc_decompress_h",
            "lopc_ctx_last_header", "lopc_batch_workspace_size", "lopc_compress_batch",
-           "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option")
+           "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option",
+           "lopc_ctx_last_batch_headers", "lopc_batch_autotune")
 LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT = 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
@@ -126,6 +127,10 @@ def load() -> ctypes.CDLL:
     L.lopc_ctx_last_batch.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_uint64),
                                       ctypes.POINTER(ctypes.c_int32)]
     L.lopc_ctx_last_batch.restype = ci
+    L.lopc_batch_autotune.argtypes = [vp, ci, ci, jp, vp, sz, vp, ci, ctypes.POINTER(ci)]
+    L.lopc_batch_autotune.restype = ci
+    L.lopc_ctx_last_batch_headers.argtypes = [vp, ci, vp]
+    L.lopc_ctx_last_batch_headers.restype = ci
     L.lopc_ctx_set_option.argtypes = [vp, ci, ctypes.c_int64]
     L.lopc_ctx_set_option.restype = ci
     _lib = L
@@ -274,6 +279,26 @@ def lopc_ctx_last_batch(ctx, n: int):
     return list(sizes), list(sts)
 
 
+def lopc_batch_autotune(ctx, op, jobs, d_ws, ws_bytes, stream, reps: int = 2) -> int:
+    """Pick the persistent grid size for this batch; returns it (percent)."""
+    pct = ctypes.c_int()
+    st = load().lopc_batch_autotune(ctx, op, len(jobs), jobs, d_ws, ws_bytes, stream, reps,
+                                    ctypes.byref(pct))
+    if st:
+        raise LopcError(st, "lopc_batch_autotune", ctx)
+    return pct.value
+
+
+def lopc_ctx_last_batch_headers(ctx, n: int):
+    """64-byte stream headers of the most recent compress batch, in job order."""
+    buf = ctypes.create_string_buffer(n * HEADER_BYTES)
+    st = load().lopc_ctx_last_batch_headers(ctx, n, buf)
+    if st:
+        raise LopcError(st, "lopc_ctx_last_batch_headers")
+    raw = buf.raw
+    return [raw[i * HEADER_BYTES:(i + 1) * HEADER_BYTES] for i in range(n)]
+
+
 # ------------------------------------------------------------------ torch API
 _ctx = {}
 
@@ -321,14 +346,15 @@ def _sizes_for(ctx, shape, dtype):
 
 def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = False,
              out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
-             header: bool = False):
+             header: bool = False, ctx: int | None = None):
     """Compress a 2D/3D float32/float64 device tensor.  Returns a uint8 device
     tensor holding the stream (a view of ``out`` if given), then a stats dict
     when ``stats`` is true, then the 64-byte header (host bytes) when
-    ``header`` is true."""
+    ``header`` is true.  ``ctx``: a library context of the caller's thread
+    (default: the shared one of the device)."""
     code = _check_field(x)
     dev = x.device
-    ctx = context(dev.index)
+    ctx = context(dev.index) if ctx is None else ctx
     cap, wsz, _ = _sizes_for(ctx, x.shape, x.dtype)
     if out is None or out.numel() < cap:
         out = torch.empty(cap, dtype=torch.uint8, device=dev)
@@ -350,7 +376,7 @@ def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = Fals
 
 def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
                workspace: torch.Tensor | None = None,
-               header: bytes | None = None) -> torch.Tensor:
+               header: bytes | None = None, ctx: int | None = None) -> torch.Tensor:
     """Decompress a uint8 device tensor holding exactly one stream.  If the
     caller holds the stream's 64-byte header on the host (``header``, e.g.
     from ``compress(..., header=True)``) no device-to-host read is needed."""
@@ -362,7 +388,7 @@ def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
         stream[:HEADER_BYTES].cpu().numpy().tobytes()
     info = lopc_stream_info(hdr)
     dev = stream.device
-    ctx = context(dev.index)
+    ctx = context(dev.index) if ctx is None else ctx
     if out is None:
         out = torch.empty(info["shape"], dtype=info["dtype"], device=dev)
     wsz = _sizes_for(ctx, info["shape"], info["dtype"])[2]
@@ -399,17 +425,8 @@ def _align(v, a=256):
     return (v + a - 1) // a * a
 
 
-def compress_batch(fields, error_bounds, modes="noa", out: torch.Tensor | None = None,
-                   workspace: torch.Tensor | None = None, stats: bool = False, ctx=None,
-                   raise_on_error: bool = True):
-    """Compress many independent 2D/3D float32/float64 device tensors in one
-    batch call.  ``error_bounds`` and ``modes`` are scalars or one per field.
-    Streams are packed into ``out`` (allocated if None) at 256-byte aligned
-    offsets; returns the list of stream views (None for a failed field when
-    ``raise_on_error`` is false), then the batch stats dict if ``stats``."""
+def _compress_jobs(fields, error_bounds, modes, out, ctx):
     n = len(fields)
-    if n == 0:
-        return ([], {}) if stats else []
     ebs = list(error_bounds) if hasattr(error_bounds, "__len__") else [error_bounds] * n
     mds = list(modes) if isinstance(modes, (list, tuple)) else [modes] * n
     if len(ebs) != n or len(mds) != n:
@@ -441,6 +458,22 @@ def compress_batch(fields, error_bounds, modes="noa", out: torch.Tensor | None =
             j.dims[d] = int(x.shape[d])
         j.error_bound = float(ebs[i])
         j.mode = _mode(mds[i])
+    return jobs, out, offs, ctx, dev
+
+
+def compress_batch(fields, error_bounds, modes="noa", out: torch.Tensor | None = None,
+                   workspace: torch.Tensor | None = None, stats: bool = False, ctx=None,
+                   raise_on_error: bool = True, headers: bool = False):
+    """Compress many independent 2D/3D float32/float64 device tensors in one
+    batch call.  ``error_bounds`` and ``modes`` are scalars or one per field.
+    Streams are packed into ``out`` (allocated if None) at 256-byte aligned
+    offsets; returns the list of stream views (None for a failed field when
+    ``raise_on_error`` is false), then the batch stats dict if ``stats``,
+    then the list of 64-byte headers (host bytes) if ``headers``."""
+    n = len(fields)
+    if n == 0:
+        return ([], {}) if stats else []
+    jobs, out, offs, ctx, dev = _compress_jobs(fields, error_bounds, modes, out, ctx)
     wsz = lopc_batch_workspace_size(ctx, 0, jobs)
     ws = _workspace(ctx, wsz, dev, workspace)
     s = torch.cuda.current_stream(dev).cuda_stream
@@ -449,11 +482,25 @@ def compress_batch(fields, error_bounds, modes="noa", out: torch.Tensor | None =
         raise LopcError(st, "lopc_compress_batch", ctx)
     sizes, sts = lopc_ctx_last_batch(ctx, n)
     res = [out[offs[i]:offs[i] + sizes[i]] if sts[i] == 0 else None for i in range(n)]
+    ret = [res]
     if stats:
         d = bst.as_dict()
         d["status"] = sts
-        return res, d
-    return res
+        ret.append(d)
+    if headers:
+        ret.append(lopc_ctx_last_batch_headers(ctx, n))
+    return ret[0] if len(ret) == 1 else tuple(ret)
+
+
+def autotune_compress_batch(fields, error_bounds, modes="noa", out=None, workspace=None,
+                            ctx=None, reps: int = 2) -> int:
+    """Tune the persistent grid size of the batch path on this batch (kept in
+    the context); returns the chosen percentage."""
+    jobs, out, offs, ctx, dev = _compress_jobs(fields, error_bounds, modes, out, ctx)
+    wsz = lopc_batch_workspace_size(ctx, 0, jobs)
+    ws = _workspace(ctx, wsz, dev, workspace)
+    return lopc_batch_autotune(ctx, 0, jobs, ws.data_ptr(), ws.numel(),
+                               torch.cuda.current_stream(dev).cuda_stream, reps)
 
 
 def decompress_batch(streams, outs=None, workspace: torch.Tensor | None = None,

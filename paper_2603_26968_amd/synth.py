@@ -21,7 +21,7 @@ import numpy as np
 __all__ = [
     "gaussian_bumps", "power_law_grf", "smooth_field", "turbulence_field",
     "lognormal_field", "fronts_field", "batch_fields", "serving_requests",
-    "CONFIGS",
+    "reflect_tile", "CONFIGS",
 ]
 
 
@@ -217,6 +217,26 @@ def serving_requests(n: int, seed: int = 7, min_bytes: int = 1 << 20,
         eb = float(math.exp(rng.uniform(math.log(1e-4), math.log(1e-2))))
         reqs.append({"op": op, "dtype": dt, "shape": shape, "eb": eb})
     return reqs
+
+
+def reflect_tile(base, shape):
+    """A field of ``shape`` made from ``base`` (same number of axes) by
+    mirror tiling: index i of an axis of length n reads base index
+    r(i mod 2n) with r(j) = j for j < n, 2n - 1 - j otherwise.  Works on
+    numpy arrays and on torch tensors (on their device), so serving payloads
+    of any size come from a few generated fields."""
+    idx = []
+    for n, m in zip(base.shape, shape):
+        j = np.arange(int(m)) % (2 * n)
+        j = np.where(j < n, j, 2 * n - 1 - j)
+        idx.append(j)
+    if isinstance(base, np.ndarray):
+        return np.ascontiguousarray(base[np.ix_(*idx)])
+    import torch
+    out = base
+    for ax, j in enumerate(idx):
+        out = torch.index_select(out, ax, torch.from_numpy(j).to(base.device))
+    return out.contiguous()
 
 
 #: The workloads by name: generator, full shape, NOA bounds.

@@ -95,6 +95,8 @@ def test_batch_streams_equal_single_and_oracle(P, ref):
     assert_same_streams(got, want, "batch")
     assert st["status"] == [0] * len(batch)
     assert st["repair_sweeps"] >= 1
+    hdrs = P.lopc_ctx_last_batch_headers(P.context(0), len(batch))
+    assert [h for h in hdrs] == [w[:64] for w in want]
 
 
 def test_batch_decompress_equals_single(P, ref):
