@@ -133,14 +133,16 @@ int lopc_ctx_last_header(lopc_ctx* ctx, void* h_header);
 /* ------------------------------------------------------------------ batches
  * Many independent fields in one call.  Each phase (range, quantize, order
  * flags + first relaxation, each repair sweep, chunk encoder; header check,
- * chunk decoder) is one persistent launch per group of fields with the same
- * dtype and dimensionality, draining a work-queue of (field, block),
- * (field, tile) or (field, chunk) items; repair sweeps run over a device
- * work list of the tiles marked by the previous sweep.  The launch sequence
- * reads everything from the workspace, so it is captured once per context,
- * workspace and composition (dtypes x dimensionalities present) as a HIP
- * graph and replayed; a batch whose repair needs more sweeps than the graph
- * holds continues with direct launches (and the next capture holds more).
+ * chunk decoder) is one launch per group of fields with the same dtype and
+ * tile shape over a batch-wide work-queue of (field, block), (field, tile)
+ * or (field, chunk) items; repair sweeps run over a device work list of the
+ * tiles marked by the previous sweep.  Launches are either direct grids (one
+ * workgroup per item; the default) or persistent grids that drain the queue
+ * (LOPC_OPT_PERSIST_PCT).  The launch sequence reads everything from the
+ * workspace; it is captured as a HIP graph once per context, workspace,
+ * composition (groups present) and -- for direct grids -- batch shape, and
+ * replayed; a batch whose repair needs more sweeps than the graph holds
+ * continues with direct launches (and the next capture holds more).
  * Fields never interact: every field's stream equals its lopc_compress
  * stream byte for byte, and every decoded field its lopc_decompress output.
  */
@@ -197,10 +199,10 @@ int lopc_ctx_last_batch(lopc_ctx* ctx, int n, uint64_t* h_sizes, int32_t* h_stat
 int lopc_ctx_last_batch_headers(lopc_ctx* ctx, int n, void* h_headers);
 
 /* Autotuner of the batch path: runs the batch (op 0 = compress, 1 =
- * decompress) with each candidate size of the persistent grids (25, 50,
- * 100, 200, 400 % of the resident capacity), once untimed and `reps` times
- * timed (host clock around the synchronous call), keeps the fastest in the
- * context (as LOPC_OPT_PERSIST_PCT) and returns it in *h_pct (may be NULL).
+ * decompress) with direct grids and with persistent grids of 50, 100 and
+ * 200 % of the resident capacity, once untimed and `reps` times timed (host
+ * clock around the synchronous call), keeps the fastest in the context (as
+ * LOPC_OPT_PERSIST_PCT, 0 = direct) and returns it in *h_pct (may be NULL).
  * The outputs are those of an ordinary call.  Errors as lopc_compress_batch;
  * a per-field failure does not stop the tuning. */
 int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void* d_ws,
@@ -211,8 +213,10 @@ int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void
  *                          sequences as HIP graphs; 0: direct launches.
  *   LOPC_OPT_GRAPH_SWEEPS  repair sweeps captured in a batch graph (1..62);
  *                          0 (default): adaptive, starting at 16.
- *   LOPC_OPT_PERSIST_PCT   size of the persistent grids in percent of the
- *                          resident capacity (1..400, default 100). */
+ *   LOPC_OPT_PERSIST_PCT   0 (default): direct grids, one workgroup per
+ *                          item; 1..400: persistent grids of that percentage
+ *                          of the resident capacity, draining the queues (one
+ *                          captured graph then serves every batch shape). */
 enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT = 3 };
 int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value);
 

@@ -61,7 +61,7 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->use_graph = 1;
   c->graph_sweeps = 0;
   c->sweeps_hint = 16;
-  c->persist_pct = 100;
+  c->persist_pct = 0;
   *out = c;
   return LOPC_OK;
 }

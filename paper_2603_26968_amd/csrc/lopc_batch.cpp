@@ -211,60 +211,98 @@ int grow_pinned(void** p, size_t* cap, size_t need) {
   return LOPC_OK;
 }
 
+// Item counts of the groups [g0, g1) in phase ph.
+uint32_t items(const BatchDesc& D, int ph, int g0, int g1) {
+  return D.item0[ph][g1] - D.item0[ph][g0];
+}
+
 // The launch sequence of a batch, everything addressed from the workspace.
-hipError_t enqueue(lopc_ctx* c, int op, uint8_t* ws, uint32_t gmask, int sweeps,
-                   hipStream_t s) {
+// Persistent mode (persist_pct > 0): fixed grids drain the queues, so the
+// sequence does not depend on the batch's sizes.  Direct mode: one
+// workgroup per item, grids from the plan D.
+hipError_t enqueue(lopc_ctx* c, int op, uint8_t* ws, const BatchDesc& D, uint32_t gmask,
+                   int sweeps, hipStream_t s) {
   const BatchDesc* bd = (const BatchDesc*)ws;
   const Job* jobs = (const Job*)(ws + sizeof(BatchDesc));
+  const bool pers = c->persist_pct > 0;
   hipError_t e;
 #define Q(x)                            \
   do {                                  \
     if ((e = (x)) != hipSuccess) return e; \
   } while (0)
   Q(launch_zero_p(bd, grid_of(c, PK_ZERO), s));
-  const bool d32 = gmask & 3u, d64 = gmask & 12u;
+  const bool has[2] = {(gmask & 3u) != 0, (gmask & 12u) != 0};
   if (op == 0) {
     for (int d = 0; d < 2; ++d) {
-      if (!(d ? d64 : d32)) continue;
-      Q(launch_minmax_p(d, bd, jobs, grid_of(c, PK_MINMAX), s));
-      Q(launch_params_p(d, bd, jobs, grid_of(c, PK_PARAMS), s));
-      Q(launch_quant_p(d, bd, jobs, grid_of(c, PK_QUANT), s));
+      if (!has[d]) continue;
+      const int g0 = 2 * d, g1 = 2 * d + 2;
+      if (pers) {
+        Q(launch_minmax_p(d, bd, jobs, grid_of(c, PK_MINMAX), s));
+        Q(launch_params_p(d, bd, jobs, grid_of(c, PK_PARAMS), s));
+        Q(launch_quant_p(d, bd, jobs, grid_of(c, PK_QUANT), s));
+      } else {
+        Q(launch_minmax_d(d, bd, jobs, items(D, PH_MM, g0, g1), s));
+        Q(launch_params_d(d, bd, jobs, D.job0[g1] - D.job0[g0], s));
+        Q(launch_quant_d(d, bd, jobs, items(D, PH_Q, g0, g1), s));
+      }
     }
-    for (int g = 0; g < kGroups; ++g)
-      if (gmask & (1u << g)) Q(launch_tile0_p(g, bd, jobs, grid_of(c, PK_TILE0), s));
-    for (int t = 1; t <= sweeps; ++t) Q(launch_repair_p(bd, jobs, (uint32_t)t, grid_of(c, PK_REPAIR), s));
-    for (int d = 0; d < 2; ++d)
-      if (d ? d64 : d32) Q(launch_encode_p(d, bd, jobs, sweeps + 1, grid_of(c, PK_ENCODE), s));
+    for (int g = 0; g < kGroups; ++g) {
+      if (!(gmask & (1u << g))) continue;
+      if (pers) Q(launch_tile0_p(g, bd, jobs, grid_of(c, PK_TILE0), s));
+      else Q(launch_tile0_d(g, bd, jobs, items(D, PH_T, g, g + 1), s));
+    }
+    for (int t = 1; t <= sweeps; ++t) {
+      if (pers) Q(launch_repair_p(bd, jobs, (uint32_t)t, grid_of(c, PK_REPAIR), s));
+      else Q(launch_repair_d(bd, jobs, (uint32_t)t, D.tiles, s));
+    }
+    for (int d = 0; d < 2; ++d) {
+      if (!has[d]) continue;
+      if (pers) Q(launch_encode_p(d, bd, jobs, sweeps + 1, grid_of(c, PK_ENCODE), s));
+      else Q(launch_encode_d(d, bd, jobs, sweeps + 1, items(D, PH_C, 2 * d, 2 * d + 2), s));
+    }
     Q(launch_finalize_c(bd, jobs, sweeps + 1, s));
   } else {
-    Q(launch_dhead_p(bd, jobs, grid_of(c, PK_DHEAD), s));
-    for (int d = 0; d < 2; ++d)
-      if (d ? d64 : d32) Q(launch_decode_p(d, bd, jobs, grid_of(c, PK_DECODE), s));
+    Q(launch_dhead_p(bd, jobs, pers ? grid_of(c, PK_DHEAD) : (int)D.job0[kGroups], s));
+    for (int d = 0; d < 2; ++d) {
+      if (!has[d]) continue;
+      if (pers) Q(launch_decode_p(d, bd, jobs, grid_of(c, PK_DECODE), s));
+      else Q(launch_decode_d(d, bd, jobs, items(D, PH_C, 2 * d, 2 * d + 2), s));
+    }
     Q(launch_finalize_d(bd, jobs, s));
   }
 #undef Q
   return hipSuccess;
 }
 
+// a captured sequence fits this batch
+bool graph_fits(const BatchGraph& g, lopc_ctx* c, int op, const void* ws, uint32_t gmask,
+                int sweeps, const BatchDesc& D) {
+  if (g.op != op || g.ws != ws || g.gmask != gmask || g.sweeps != sweeps ||
+      g.grid_pct != c->persist_pct)
+    return false;
+  if (c->persist_pct > 0) return true;
+  // direct grids: the batch's shape must match
+  return std::memcmp(g.job0, D.job0, sizeof(D.job0)) == 0 &&
+         std::memcmp(g.item0, D.item0, sizeof(D.item0)) == 0 && g.tiles == D.tiles;
+}
+
 // Run the sequence: replay a cached graph (capturing it first if needed) or
 // launch directly.  *graph = 1 when a graph ran.
-int run_sequence(lopc_ctx* c, int op, uint8_t* ws, uint32_t gmask, int sweeps,
-                 hipStream_t s, int* graph) {
+int run_sequence(lopc_ctx* c, int op, uint8_t* ws, const BatchDesc& D, uint32_t gmask,
+                 int sweeps, hipStream_t s, int* graph) {
   *graph = 0;
   if (!c->use_graph) {
-    HIP_CTX(c, enqueue(c, op, ws, gmask, sweeps, s));
+    HIP_CTX(c, enqueue(c, op, ws, D, gmask, sweeps, s));
     return LOPC_OK;
   }
   BatchGraph* hit = nullptr;
   for (BatchGraph& g : c->graphs)
-    if (g.op == op && g.ws == ws && g.gmask == gmask && g.sweeps == sweeps &&
-        g.grid_pct == c->persist_pct)
-      hit = &g;
+    if (graph_fits(g, c, op, ws, gmask, sweeps, D)) hit = &g;
   if (!hit) {
     if (!c->cap_stream) HIP_CTX(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIP_CTX(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-    hipError_t e = enqueue(c, op, ws, gmask, sweeps, c->cap_stream);
+    hipError_t e = enqueue(c, op, ws, D, gmask, sweeps, c->cap_stream);
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
     if (e == hipSuccess) e = e2;
     hipGraphExec_t exec = nullptr;
@@ -277,7 +315,17 @@ int run_sequence(lopc_ctx* c, int op, uint8_t* ws, uint32_t gmask, int sweeps,
       (void)hipGraphExecDestroy(old->exec);
       c->graphs.erase(old);
     }
-    c->graphs.push_back(BatchGraph{op, ws, gmask, sweeps, c->persist_pct, 0, exec});
+    BatchGraph g{};
+    g.op = op;
+    g.ws = ws;
+    g.gmask = gmask;
+    g.sweeps = sweeps;
+    g.grid_pct = c->persist_pct;
+    std::memcpy(g.job0, D.job0, sizeof(D.job0));
+    std::memcpy(g.item0, D.item0, sizeof(D.item0));
+    g.tiles = D.tiles;
+    g.exec = exec;
+    c->graphs.push_back(g);
     hit = &c->graphs.back();
   }
   hit->used = ++c->use_clock;
@@ -381,7 +429,7 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
   uint8_t* ws = (uint8_t*)d_ws;
   const int K = ctx->graph_sweeps ? ctx->graph_sweeps : ctx->sweeps_hint;
   int graph = 0;
-  if (int st = run_sequence(ctx, 0, ws, P.gmask, K, hs, &graph)) return st;
+  if (int st = run_sequence(ctx, 0, ws, P.desc, P.gmask, K, hs, &graph)) return st;
   if (int st = read_back(ctx, P, ws, n, hs)) return st;
   const BatchCounters* hc = host_counters(ctx);
   if (hc->err) return LOPC_E_INTERNAL;
@@ -409,8 +457,12 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
         if (t >= kRing && t < next + batch)
           HIP_CTX(ctx, hipMemsetAsync(&bc->cursors[t % kRing], 0, 4, hs));
       }
-      for (uint32_t b = 0; b < batch; ++b)
-        HIP_CTX(ctx, launch_repair_p(bd, dj, next + b, grid_of(ctx, PK_REPAIR), hs));
+      for (uint32_t b = 0; b < batch; ++b) {
+        if (ctx->persist_pct > 0)
+          HIP_CTX(ctx, launch_repair_p(bd, dj, next + b, grid_of(ctx, PK_REPAIR), hs));
+        else
+          HIP_CTX(ctx, launch_repair_d(bd, dj, next + b, P.desc.tiles, hs));
+      }
       if (int st = read_back(ctx, P, ws, n, hs)) return st;
       hc = host_counters(ctx);
       if (hc->err) return LOPC_E_INTERNAL;
@@ -432,9 +484,13 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
       if (next + batch >= kMaxBatchSweeps) return LOPC_E_INTERNAL;
     }
     // encoder state is still clear (the gated encoders did not run)
-    for (int d = 0; d < 2; ++d)
-      if (P.gmask & (d ? 12u : 3u))
+    for (int d = 0; d < 2; ++d) {
+      if (!(P.gmask & (d ? 12u : 3u))) continue;
+      if (ctx->persist_pct > 0)
         HIP_CTX(ctx, launch_encode_p(d, bd, dj, 0, grid_of(ctx, PK_ENCODE), hs));
+      else
+        HIP_CTX(ctx, launch_encode_d(d, bd, dj, 0, items(P.desc, PH_C, 2 * d, 2 * d + 2), hs));
+    }
     HIP_CTX(ctx, launch_finalize_c(bd, dj, 0, hs));
     if (int st = read_back(ctx, P, ws, n, hs)) return st;
     if (!ctx->graph_sweeps) {
@@ -459,7 +515,7 @@ int lopc_decompress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws
   if (int st = batch_common(ctx, 1, n, jobs, d_ws, ws_bytes, hs, P)) return st;
   uint8_t* ws = (uint8_t*)d_ws;
   int graph = 0;
-  if (int st = run_sequence(ctx, 1, ws, P.gmask, 0, hs, &graph)) return st;
+  if (int st = run_sequence(ctx, 1, ws, P.desc, P.gmask, 0, hs, &graph)) return st;
   if (int st = read_back(ctx, P, ws, n, hs)) return st;
   return collect(ctx, P, n);
 }
@@ -476,7 +532,7 @@ int lopc_ctx_last_batch(lopc_ctx* ctx, int n, uint64_t* h_sizes, int32_t* h_stat
 int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void* d_ws,
                         size_t ws_bytes, void* stream, int reps, int* h_pct) {
   if (!ctx || (op != 0 && op != 1) || reps < 1) return LOPC_E_ARG;
-  static const int kCand[] = {25, 50, 100, 200, 400};
+  static const int kCand[] = {0, 50, 100, 200};
   const int keep = ctx->persist_pct;
   int best = keep;
   double best_t = 1e300;
@@ -523,7 +579,7 @@ int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value) {
       ctx->graph_sweeps = (int)value;
       return LOPC_OK;
     case LOPC_OPT_PERSIST_PCT:
-      if (value < 1 || value > 400) return LOPC_E_ARG;
+      if (value < 0 || value > 400) return LOPC_E_ARG;
       ctx->persist_pct = (int)value;
       return LOPC_OK;
     default:

@@ -428,7 +428,7 @@ __device__ __forceinline__ uint8_t record_byte(uint32_t r, const uint8_t* hdr,
 
 // Encodes chunk c of a field and writes its record (Sec. III-B, IV-C).
 template <int K>
-__device__ void encode_body(uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
+__device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
                             const uint32_t* __restrict__ sub, uint64_t* lookback,
                             uint32_t* parts, Params* prm, uint8_t* stream, uint64_t cap,
                             uint32_t nch, uint32_t c) {
@@ -436,12 +436,15 @@ __device__ void encode_body(uint32_t n, const typename Traits<K>::Bin* __restric
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
   constexpr int GPW = (int)(W / 64 / kCW);  // groups per wave
-  __shared__ uint64_t U[kMaxUnits + 2];  // bit planes; later the subbin part
-  __shared__ uint64_t B[kMaxUnits + 2];  // bins part
-  __shared__ uint64_t X[kMaxUnits + 2];  // subbins after RZE_K
+  // 54,248 bytes of LDS in all: three workgroups fit in the 160 KiB of a CU
+  __shared__ uint64_t U[kMaxUnits];      // bit planes; later the subbin part
+  __shared__ uint64_t B[kMaxUnits];      // bins part
+  __shared__ uint64_t X[kMaxUnits + 2];  // subbins after RZE_K (+16 zero bytes)
   __shared__ Scratch sc;
-  __shared__ uint8_t hdr[kRecordHeaderBytes];
-  __shared__ uint64_t s_excl;
+  // the record header and the chunk's offset live in sc.orv, which is free
+  // once both block_or calls are done
+  uint8_t* hdr = (uint8_t*)sc.orv;
+  uint64_t& s_excl = sc.orv[2];
 
   const uint32_t p0 = c * W;
   const uint32_t nc = min(W, n - p0);
@@ -580,7 +583,7 @@ __global__ __launch_bounds__(kCT) void k_encode(
 // ------------------------------------------------------------------ decoder
 // Exclusive offsets of the records from the size table; the sizes must add
 // up to the stream body exactly.
-__device__ void offsets_body(const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
+__device__ __forceinline__ void offsets_body(const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
                              uint64_t* offsets, Params* prm) {
   __shared__ uint64_t sh[kWaves + 1];
   const uint32_t per = (nch + kThreads - 1) / kThreads;
@@ -663,7 +666,7 @@ __device__ __forceinline__ void stage(uint8_t* dst, const uint8_t* src, uint32_t
 
 // Decodes chunk c of a field (Sec. IV-E); a malformed record sets FORMAT.
 template <int K>
-__device__ void decode_body(const uint8_t* __restrict__ stream, uint32_t n,
+__device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, uint32_t n,
                             const uint64_t* __restrict__ offsets, Params* prm,
                             typename Traits<K>::Raw* __restrict__ out, uint32_t nch,
                             uint32_t c) {
@@ -1010,6 +1013,32 @@ __global__ __launch_bounds__(kThreads) void k_finalize_d(const BatchDesc* bd, co
   }
 }
 
+// Direct grids: one workgroup per chunk.  The encoder still takes its chunk
+// from the ticket counter, so chunks start in field-major order.
+template <int K>
+__global__ __launch_bounds__(kCT) void k_encode_d(const BatchDesc* bd, const Job* jobs,
+                                                  int gate_sweep) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  __shared__ uint32_t s_t;
+  BatchCounters* bc = bd->bc;
+  if (gate_sweep > 0 && bc->lens[gate_sweep % kRing]) return;
+  if (threadIdx.x == 0) s_t = bd->item0[PH_C][g0] + atomicAdd(&bc->enc_cursor[K == 4 ? 0 : 1], 1u);
+  __syncthreads();
+  const uint32_t t = s_t;
+  const Job& J = jobs[find_job<&Job::c0>(jobs, (int)bd->job0[g0], (int)bd->job0[g0 + 2], t)];
+  encode_body<K>(J.box.n, (const typename Traits<K>::Bin*)J.bins, J.sub, J.lookback, J.parts,
+                 J.prm, J.stream, J.cap, J.nch, t - J.c0);
+}
+
+template <int K>
+__global__ __launch_bounds__(kCT, 6) void k_decode_d(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  const uint32_t t = bd->item0[PH_C][g0] + blockIdx.x;
+  const Job& J = jobs[find_job<&Job::c0>(jobs, (int)bd->job0[g0], (int)bd->job0[g0 + 2], t)];
+  decode_body<K>(J.stream, J.box.n, J.offsets, J.prm, (typename Traits<K>::Raw*)J.y, J.nch,
+                 t - J.c0);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -1079,6 +1108,22 @@ hipError_t launch_decode_p(int dtype, const BatchDesc* bd, const Job* jobs, int 
 
 hipError_t launch_finalize_d(const BatchDesc* bd, const Job* jobs, hipStream_t s) {
   k_finalize_d<<<4, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_d(int dtype, const BatchDesc* bd, const Job* jobs, int gate_sweep,
+                           uint32_t items, hipStream_t s) {
+  if (!items) return hipSuccess;
+  if (dtype == 0) k_encode_d<4><<<items, kCT, 0, s>>>(bd, jobs, gate_sweep);
+  else k_encode_d<8><<<items, kCT, 0, s>>>(bd, jobs, gate_sweep);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                           hipStream_t s) {
+  if (!items) return hipSuccess;
+  if (dtype == 0) k_decode_d<4><<<items, kCT, 0, s>>>(bd, jobs);
+  else k_decode_d<8><<<items, kCT, 0, s>>>(bd, jobs);
   return hipGetLastError();
 }
 

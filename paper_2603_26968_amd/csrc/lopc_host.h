@@ -21,7 +21,10 @@ struct BatchGraph {
   const void* ws;      // workspace it was captured on
   uint32_t gmask;      // groups present
   int sweeps;          // repair sweeps captured (compress)
-  int grid_pct;        // persistent grid size it was captured with
+  int grid_pct;        // persistent grid size it was captured with (0: direct)
+  uint32_t job0[lopc::kGroups + 1];             // direct grids: the batch shape
+  uint32_t item0[lopc::PH_N][lopc::kGroups + 1];
+  uint32_t tiles;
   uint64_t used;       // last use (for eviction)
   hipGraphExec_t exec;
 };
@@ -47,7 +50,7 @@ struct lopc_ctx {
   int use_graph;       // capture batch sequences as graphs
   int graph_sweeps;    // sweeps per graph (0 = adaptive)
   int sweeps_hint;     // adaptive capture size
-  int persist_pct;     // persistent grid size, percent of resident capacity
+  int persist_pct;     // persistent grid size, % of resident capacity; 0: direct grids
   int per_cu[lopc::PK_COUNT];  // resident blocks per CU (0 = not queried)
   hipStream_t cap_stream;      // stream used for captures
   void* h_plan;        // pinned staging of the plan + job table

@@ -203,6 +203,23 @@ hipError_t launch_decode_p(int dtype, const BatchDesc* bd, const Job* jobs, int 
                            hipStream_t s);
 hipError_t launch_finalize_d(const BatchDesc* bd, const Job* jobs, hipStream_t s);
 
+// Direct-grid variants: one workgroup per item; `items` is the phase's item
+// count of the launch's groups (the repair: the work-list capacity).
+hipError_t launch_minmax_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                           hipStream_t s);
+hipError_t launch_params_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t njobs,
+                           hipStream_t s);
+hipError_t launch_quant_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                          hipStream_t s);
+hipError_t launch_tile0_d(int group, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                          hipStream_t s);
+hipError_t launch_repair_d(const BatchDesc* bd, const Job* jobs, uint32_t sweep, uint32_t tiles,
+                           hipStream_t s);
+hipError_t launch_encode_d(int dtype, const BatchDesc* bd, const Job* jobs, int gate_sweep,
+                           uint32_t items, hipStream_t s);
+hipError_t launch_decode_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                           hipStream_t s);
+
 // Resident blocks per CU of each persistent batch kernel (occupancy query).
 enum { PK_ZERO, PK_MINMAX, PK_PARAMS, PK_QUANT, PK_TILE0, PK_REPAIR, PK_ENCODE, PK_DHEAD,
        PK_DECODE, PK_COUNT };

@@ -20,7 +20,7 @@ namespace {
 
 // ------------------------------------------------------------------ a0
 template <int K>
-__device__ void minmax_body(const typename Traits<K>::Raw* x, uint32_t n, int64_t* part,
+__device__ __forceinline__ void minmax_body(const typename Traits<K>::Raw* x, uint32_t n, int64_t* part,
                             Params* prm, uint32_t blk, uint32_t nblk) {
   using Tr = Traits<K>;
   int64_t lo = INT64_MAX, hi = INT64_MIN;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kThreads) void k_minmax(
 
 
 template <int K>
-__device__ void params_body(int mode, double eb, const int64_t* part, int nblocks,
+__device__ __forceinline__ void params_body(int mode, double eb, const int64_t* part, int nblocks,
                             Params* prm, uint8_t* stream, uint64_t cap, int ndim,
                             int64_t d0, int64_t d1, int64_t d2) {
   using Tr = Traits<K>;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_params(
 // ------------------------------------------------------------------ a1
 // Quantize every point once (Sec. IV-A): 16-byte loads and stores.
 template <int K>
-__device__ void quant_body(const typename Traits<K>::Raw* __restrict__ x, uint32_t n,
+__device__ __forceinline__ void quant_body(const typename Traits<K>::Raw* __restrict__ x, uint32_t n,
                            Params* prm, typename Traits<K>::Bin* __restrict__ bins,
                            uint32_t blk, uint32_t nblk) {
   using Tr = Traits<K>;
@@ -289,7 +289,7 @@ __device__ void mark_neighbours(bool edge, const TileCoord& c, const Tiling& tl,
 // them, then relax with halo subbins 0 (the first sweep of a3).
 // Returns (block-uniform) whether a boundary subbin of the tile is nonzero.
 template <int K, int TZ, int TY, int TX>
-__device__ bool tile0_body(const typename Traits<K>::Raw* __restrict__ x, Box box,
+__device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __restrict__ x, Box box,
                            Tiling tl, const typename Traits<K>::Bin* __restrict__ bins,
                            uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
                            uint32_t* counters, uint32_t t, TileCoord& c) {
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
 // One sweep of tile t if it is marked for it.  Returns (block-uniform) whether
 // a boundary subbin changed; false if the tile did not run.
 template <int TZ, int TY, int TX>
-__device__ bool repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
+__device__ __forceinline__ bool repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
                             uint32_t* __restrict__ sub, const uint32_t* stamp,
                             uint32_t* counters, uint32_t sweep, uint32_t t, TileCoord& c) {
   using G = TileGeom<TZ, TY, TX>;
@@ -606,6 +606,67 @@ __global__ __launch_bounds__(kThreads) void k_repair_p(const BatchDesc* bd, cons
   }
 }
 
+// Direct grids: one workgroup per item (the grid is the phase's item count
+// of the batch), so each kernel keeps the register budget of its body.
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_minmax_d(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  const uint32_t it = bd->item0[PH_MM][g0] + blockIdx.x;
+  const Job& J = jobs[find_job<&Job::mm0>(jobs, (int)bd->job0[g0], (int)bd->job0[g0 + 2], it)];
+  minmax_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.part, J.prm, it - J.mm0,
+                 (uint32_t)J.mm_blocks);
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_params_d(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  const Job& J = jobs[bd->job0[g0] + blockIdx.x];
+  params_body<K>(J.mode, J.eb, J.part, J.mm_blocks, J.prm, J.stream, J.cap, J.ndim,
+                 J.dims[0], J.dims[1], J.ndim == 3 ? J.dims[2] : 1);
+}
+
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_quant_d(const BatchDesc* bd, const Job* jobs) {
+  constexpr int g0 = K == 4 ? 0 : 2;
+  const uint32_t it = bd->item0[PH_Q][g0] + blockIdx.x;
+  const Job& J = jobs[find_job<&Job::q0>(jobs, (int)bd->job0[g0], (int)bd->job0[g0 + 2], it)];
+  quant_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.prm,
+                (typename Traits<K>::Bin*)J.bins, it - J.q0,
+                (J.box.n + kQuantSpan - 1) / kQuantSpan);
+}
+
+template <int K, int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_tile0_d(const BatchDesc* bd, const Job* jobs,
+                                                      int g) {
+  const uint32_t it = bd->item0[PH_T][g] + blockIdx.x;
+  const Job& J = jobs[find_job<&Job::t0>(jobs, (int)bd->job0[g], (int)bd->job0[g + 1], it)];
+  TileCoord c;
+  const bool edge = tile0_body<K, TZ, TY, TX>(
+      (const typename Traits<K>::Raw*)J.x, J.box, J.tl, (const typename Traits<K>::Bin*)J.bins,
+      J.mask, J.sub, &bd->bc->err, it - J.t0, c);
+  mark_list(edge, c, J.tl, J.stamp, J.t0, bd->bc->lens, bd->lists + bd->tiles, 1);
+}
+
+// One sweep: workgroup b takes entry b of the sweep's work list (the grid
+// is the list's capacity; workgroups past its length exit at once).
+__global__ __launch_bounds__(kThreads) void k_repair_d(const BatchDesc* bd, const Job* jobs,
+                                                       uint32_t sweep) {
+  BatchCounters* bc = bd->bc;
+  if (blockIdx.x >= bc->lens[sweep % kRing]) return;
+  const uint32_t item = bd->lists[(sweep & 1) * bd->tiles + blockIdx.x];
+  const Job& J = jobs[find_job<&Job::t0>(jobs, 0, (int)bd->job0[kGroups], item)];
+  uint32_t* list_out = bd->lists + ((sweep + 1) & 1) * bd->tiles;
+  TileCoord c;
+  bool edge;
+  if (J.tl.tz == 1)
+    edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+                                  item - J.t0, c);
+  else
+    edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+                                 item - J.t0, c);
+  if (edge) mark_list(true, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -718,6 +779,49 @@ hipError_t launch_tile0_p(int group, const BatchDesc* bd, const Job* jobs, int g
 hipError_t launch_repair_p(const BatchDesc* bd, const Job* jobs, uint32_t sweep, int grid,
                            hipStream_t s) {
   k_repair_p<<<grid, kThreads, 0, s>>>(bd, jobs, sweep);
+  return hipGetLastError();
+}
+
+hipError_t launch_minmax_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                           hipStream_t s) {
+  if (!items) return hipSuccess;
+  if (dtype == 0) k_minmax_d<4><<<items, kThreads, 0, s>>>(bd, jobs);
+  else k_minmax_d<8><<<items, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_params_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t njobs,
+                           hipStream_t s) {
+  if (!njobs) return hipSuccess;
+  if (dtype == 0) k_params_d<4><<<njobs, kThreads, 0, s>>>(bd, jobs);
+  else k_params_d<8><<<njobs, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                          hipStream_t s) {
+  if (!items) return hipSuccess;
+  if (dtype == 0) k_quant_d<4><<<items, kThreads, 0, s>>>(bd, jobs);
+  else k_quant_d<8><<<items, kThreads, 0, s>>>(bd, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile0_d(int group, const BatchDesc* bd, const Job* jobs, uint32_t items,
+                          hipStream_t s) {
+  if (!items) return hipSuccess;
+  switch (group) {
+    case 0: k_tile0_d<4, 1, 32, 64><<<items, kThreads, 0, s>>>(bd, jobs, 0); break;
+    case 1: k_tile0_d<4, 8, 8, 32><<<items, kThreads, 0, s>>>(bd, jobs, 1); break;
+    case 2: k_tile0_d<8, 1, 32, 64><<<items, kThreads, 0, s>>>(bd, jobs, 2); break;
+    default: k_tile0_d<8, 8, 8, 32><<<items, kThreads, 0, s>>>(bd, jobs, 3); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_repair_d(const BatchDesc* bd, const Job* jobs, uint32_t sweep, uint32_t tiles,
+                           hipStream_t s) {
+  if (!tiles) return hipSuccess;
+  k_repair_d<<<tiles, kThreads, 0, s>>>(bd, jobs, sweep);
   return hipGetLastError();
 }
 

@@ -148,23 +148,42 @@ def test_graph_replays_and_direct_launches_agree(P):
             assert np.array_equal(y.cpu().numpy().view(np.uint8), z.cpu().numpy().view(np.uint8))
 
 
-def test_sweeps_beyond_the_graph_continue(P):
+@pytest.mark.parametrize("pct", [0, 100])
+def test_sweeps_beyond_the_graph_continue(P, pct):
     """With one sweep captured, fields that need more continue with direct
     launches and still give the single-field streams."""
     batch = mixed_batch()
     want = single_streams(P, batch)
     ctx = P.context(0)
     P.lopc_ctx_set_option(ctx, P.LOPC_OPT_GRAPH_SWEEPS, 1)
+    P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, pct)
     try:
-        _say("graph with 1 sweep")
+        _say("graph with 1 sweep, grid mode", pct)
         got, st = batch_streams(P, batch, stats=True)
         assert st["continued"] == 1 and st["repair_sweeps"] > 2
         assert_same_streams(got, want, "continued")
     finally:
         P.lopc_ctx_set_option(ctx, P.LOPC_OPT_GRAPH_SWEEPS, 0)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, 0)
 
 
-@pytest.mark.parametrize("pct", [1, 25, 300])
+def test_autotuner_keeps_results(P):
+    batch = mixed_batch()
+    want = single_streams(P, batch)
+    xs = [to_dev(x) for x, _, _ in batch]
+    ctx = P.context(0)
+    _say("autotune")
+    try:
+        pct = P.autotune_compress_batch(xs, [eb for _, eb, _ in batch],
+                                        [m for _, _, m in batch], reps=1)
+        assert pct in (0, 50, 100, 200)
+        got, _ = batch_streams(P, batch)
+        assert_same_streams(got, want, f"tuned {pct}")
+    finally:
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, 0)
+
+
+@pytest.mark.parametrize("pct", [1, 25, 100, 300])
 def test_persistent_grid_size_does_not_matter(P, pct):
     batch = mixed_batch()
     want = single_streams(P, batch)
@@ -181,7 +200,7 @@ def test_persistent_grid_size_does_not_matter(P, pct):
             torch.cuda.synchronize()
             assert np.array_equal(y.cpu().numpy().view(np.uint8), z.cpu().numpy().view(np.uint8)), i
     finally:
-        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, 100)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, 0)
 
 
 def test_per_field_status_and_device_words(P, ref):
