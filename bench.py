@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--all-eb", action="store_true",
                     help="also time the 1e-2 and 1e-4 bounds of the same field")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
+    ap.add_argument("--eb-sweep", action="store_true",
+                    help="single-field workloads: also run NOA bounds 1e0 .. 1e-6 (CR, "
+                         "throughput, sweeps, bins/subbins byte split)")
     return ap.parse_args()
 
 
@@ -164,6 +167,30 @@ def bench_single(args, name):
                 "decompress_GBps": round(n * k / ((ph["offsets"] + ph["decode"]) * 1e-3) / 1e9, 2),
                 "CR": round(n * k / se.numel(), 3), "repair_sweeps": int(st["repair_sweeps"])}
 
+    if args.eb_sweep:
+        sweep = {}
+        for e in range(0, 7):
+            eb = 10.0 ** (-e)
+            try:
+                dte, ph, st, se = run_steps(P, lopc, ctx, x, eb, 3, bufs, True)
+            except lopc.LopcError as err:  # e.g. a bin range beyond the integer type
+                sweep[f"1e-{e}"] = {"error": str(err)}
+                continue
+            tc = sum(ph[p] for p in ("range", "quant", "repair", "encode"))
+            td = ph["offsets"] + ph["decode"]
+            Se = int(se.numel())
+            sweep[f"1e-{e}"] = {
+                "CR": round(n * k / Se, 3), "GBps_roundtrip": round(n * k / (dte / 3) / 1e9, 2),
+                "compress_GBps": round(n * k / (tc * 1e-3) / 1e9, 2),
+                "decompress_GBps": round(n * k / (td * 1e-3) / 1e9, 2),
+                "repair_ms": round(ph["repair"], 4), "repair_sweeps": int(st["repair_sweeps"]),
+                "active_tiles_total": int(st["active_tiles_total"]),
+                "bins_share": round(st["bins_bytes"] / Se, 4),
+                "subbins_share": round(st["subbins_bytes"] / Se, 4)}
+        extra_sweep = sweep
+    else:
+        extra_sweep = None
+
     dtname = "f32" if k == 4 else "f64"
     out = {
         "metric": METRIC,
@@ -185,6 +212,8 @@ def bench_single(args, name):
     }
     if extra:
         out["other_eb"] = extra
+    if extra_sweep:
+        out["eb_sweep"] = extra_sweep
 
     if not args.no_cpu_baseline:
         # the oracle on a bounded sample: the whole field when it is small,

@@ -252,7 +252,7 @@ def test_decompress_batch_flags_bad_streams(P, ref):
     s = ref.compress(x, 1e-3, ref.NOA)
     good = torch.from_numpy(np.frombuffer(s, np.uint8).copy()).cuda()
     bad = bytearray(s)
-    bad[len(bad) // 2] ^= 0x5A
+    bad[64] ^= 0x04  # first record size: the sizes no longer add up to the body
     corrupt = torch.from_numpy(np.frombuffer(bytes(bad), np.uint8).copy()).cuda()
     streams = [good, corrupt, good]
     outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda") for _ in streams]
