@@ -40,6 +40,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, public spec
+
+
+def _log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 METRIC = "LOPC compress+decompress GB/s (uncompressed bytes / round-trip time), bit-exact"
 
 SINGLE = {
@@ -59,7 +63,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="turb3d",
-                    choices=list(SINGLE) + ["batch", "serve"])
+                    choices=list(SINGLE) + ["batch", "serve", "copy"])
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -118,7 +122,9 @@ def bench_single(args, name):
 
     gen, shape, desc = SINGLE[name]
     dev = torch.device("cuda:0")
+    _log("generating", name)
     xh = getattr(synth, gen)(shape, seed=args.seed)
+    _log("generated")
     n, k = xh.size, xh.itemsize
     x = torch.from_numpy(xh).to(dev)
     ctx = lopc.context(0)
@@ -261,7 +267,9 @@ def bench_batch(args):
     import paper_2603_26968_amd as P
     from paper_2603_26968_amd import lopc, synth
 
+    _log("generating 256 fields")
     fields = synth.batch_fields(256, seed=args.seed)
+    _log("generated", sum(x.nbytes for x, _ in fields) / 1e6, "MB")
     xs = [torch.from_numpy(x).cuda() for x, _ in fields]
     ebs = [eb for _, eb in fields]
     nbytes = sum(x.nbytes for x, _ in fields)
@@ -291,6 +299,7 @@ def bench_batch(args):
         td += t2 - t1
     tc /= args.steps
     td /= args.steps
+    _log("timed", tc, td)
     S = sum(int(s.numel()) for s in streams)
     # identity: every batch stream equals its single-field stream, every
     # decoded field the single-field decode
@@ -345,6 +354,7 @@ def bench_serve(args):
     from paper_2603_26968_amd import serve, synth
 
     n_templates = 64
+    _log("building serving templates")
     base2 = torch.from_numpy(synth.smooth_field()).cuda()
     base3 = torch.from_numpy(synth.turbulence_field((256, 256, 256))).cuda()
     T = []
@@ -416,6 +426,31 @@ def bench_serve(args):
     }
 
 
+# ------------------------------------------------------------------ copy roof
+def bench_copy(args):
+    """A plain device-to-device copy of 256 MiB: the achievable HBM rate, and
+    the kernel whose counters calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    nb = 256 << 20
+    a = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return {"metric": "device-to-device copy GB/s (bytes read + written / time)",
+            "value": round(2 * nb / dt / 1e9, 1), "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+            "data": "synthetic", "config": {"workload": "copy: 256 MiB device to device",
+                                            "bytes_each_way": nb},
+            "frac_of_peak": round(2 * nb / dt / 1e9 / HBM_PEAK_GBPS, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -426,6 +461,8 @@ def main():
         out = bench_batch(args)
     elif args.workload == "serve":
         out = bench_serve(args)
+    elif args.workload == "copy":
+        out = bench_copy(args)
     else:
         out = bench_single(args, args.workload)
     print(json.dumps(out), flush=True)
