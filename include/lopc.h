@@ -75,6 +75,7 @@ typedef struct {
   uint64_t active_tiles_total; /* tiles processed over all sweeps           */
   uint64_t bins_bytes;         /* bytes of all bins parts                   */
   uint64_t subbins_bytes;      /* bytes of all subbin parts                 */
+  uint64_t relax_iterations;   /* in-tile relaxation passes, all tiles/sweeps */
 } lopc_stats;
 
 /* Context for one HIP device: device properties, pinned host slots for the
@@ -166,6 +167,7 @@ typedef struct {
   uint64_t active_tiles_total; /* tiles processed over all sweeps             */
   int graph;                   /* 1: the launch sequence was a graph replay   */
   int continued;               /* 1: sweeps beyond the captured ones ran      */
+  uint64_t relax_iterations;   /* in-tile relaxation passes, all tiles/sweeps */
 } lopc_batch_stats;
 
 /* Workspace bytes a batch of n jobs needs (op 0 = compress, 1 = decompress). */

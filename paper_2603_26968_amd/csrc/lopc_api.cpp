@@ -183,7 +183,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   // repair sweeps (Alg. 1 loop at tile granularity), enqueued in batches; a
   // sweep with no marked tile costs one empty launch.  One read of the status
   // and the per-sweep counters per batch.
-  uint64_t sweeps = 1, active = tl.ntiles;
+  uint64_t sweeps = 1, active = tl.ntiles, relax_iters = 0;
   uint32_t next = 1;  // first sweep of the next batch
   uint32_t batch = 2;
   const size_t report = L.counters + kCounterWords * 4;  // Params + counters
@@ -195,6 +195,12 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     HIP_CTX(ctx, hipStreamSynchronize(hs));
     const uint32_t* hc = (const uint32_t*)((const uint8_t*)ctx->h_prm + L.counters);
     if (hc[0]) return LOPC_E_INTERNAL;
+    relax_iters = 0;
+    for (int q = 0; q < 64; ++q) {
+      uint64_t v;
+      std::memcpy(&v, hc + kRelaxWord + 2 * q, 8);
+      relax_iters += v;
+    }
     int code = status_code(ctx->h_prm->status);
     if (code != LOPC_OK && code != LOPC_E_CAPACITY) {
       *h_stream_size = 0;
@@ -246,6 +252,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     h_stats->eps = hp.eps;
     h_stats->repair_sweeps = sweeps;
     h_stats->active_tiles_total = active;
+    h_stats->relax_iterations = relax_iters;
     h_stats->bins_bytes = hp.bins_bytes;
     h_stats->subbins_bytes = hp.sub_bytes;
   }

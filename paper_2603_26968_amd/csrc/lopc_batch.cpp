@@ -502,6 +502,9 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
   if (h_stats) {
     h_stats->repair_sweeps = sweeps;
     h_stats->active_tiles_total = active;
+    uint64_t it = 0;
+    for (int q = 0; q < 64; ++q) it += host_counters(ctx)->relax_iters[q];
+    h_stats->relax_iterations = it;
     h_stats->graph = graph;
     h_stats->continued = continued ? 1 : 0;
   }

@@ -123,9 +123,9 @@ struct CompressLayout {
   size_t part, bins, mask, sub, total;
 };
 
-// repair counters: [0] internal error flag, [1 + s % 64] tiles marked for
-// sweep s (a ring the host clears after reading)
-constexpr size_t kCounterWords = 1 + 64;
+// repair counters (kCounterWords words): [0] internal error flag,
+// [1 + s % 64] tiles marked for sweep s (a ring the host clears after
+// reading), [kRelaxWord] 64-bit relaxation iteration total
 
 inline CompressLayout compress_layout(const Shape& s, int dtype) {
   const size_t k = dtype == 0 ? 4 : 8;

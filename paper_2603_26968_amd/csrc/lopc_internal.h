@@ -68,6 +68,10 @@ constexpr uint32_t kMinmaxSpan = 65536;
 constexpr uint32_t kQuantSpan = 16384;
 // Work-list ring: slot s % 64 holds sweep s.
 constexpr uint32_t kRing = 64;
+// Single-field repair counters: [0] error flag, [1 + s % 64] tiles marked for
+// sweep s, from [kRelaxWord] 64 64-bit slots of relaxation-pass counts.
+constexpr uint32_t kRelaxWord = 66;
+constexpr uint32_t kCounterWords = kRelaxWord + 128;
 
 // group of a field: 2 * dtype + (3D)
 constexpr int kGroups = 4;
@@ -83,6 +87,7 @@ struct alignas(256) BatchCounters {
   uint32_t pad[2];
   uint32_t lens[kRing];     // tiles listed for sweep s (slot s % 64)
   uint32_t cursors[kRing];  // work-queue cursor of sweep s
+  unsigned long long relax_iters[64];  // relaxation passes (slot = tile % 64)
 };
 
 // Per-field descriptor.  Items of every phase are numbered batch-wide (jobs

@@ -225,27 +225,54 @@ __device__ __forceinline__ TileCoord tile_coord(uint32_t t, const Tiling& tl) {
 }
 
 // local fixed point of the tile (masks of the owned points in registers)
+// the relaxation-iteration slots of the single-field counters block
+__device__ __forceinline__ unsigned long long* relax_total(uint32_t* counters) {
+  return (unsigned long long*)(counters + kRelaxWord);
+}
+
+// Local fixed point of the tile (masks of the owned points in registers):
+// Gauss-Seidel passes over the owned points until none rises; the halo is
+// fixed.  The neighbour values of a point are loaded unconditionally and
+// combined under its mask, so the loads of a point issue back to back
+// instead of one dependent load per set mask bit.  Adds the pass count to one
+// of 64 statistics slots itot[t % 64].
 template <int TZ, int TY, int TX>
-__device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters) {
+__device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
+                      unsigned long long* itot, uint32_t t) {
   using G = TileGeom<TZ, TY, TX>;
-  int doff[14];
-#pragma unroll
-  for (int j = 0; j < 14; ++j)
-    doff[j] = c_off[j][0] * (G::HY * G::HX) + c_off[j][1] * G::HX + c_off[j][2];
+  constexpr int NJ = TZ == 1 ? 6 : 14;  // 2D tiles: the in-plane offsets only
   int iters = 0;
   for (;;) {
     int changed = 0;
-#pragma unroll
+#pragma unroll 2
     for (int k = 0; k < G::PER; ++k) {
-      uint32_t m = mk[k];
+      const uint32_t m = mk[k];
       if (!m) continue;
       const int li = G::local(threadIdx.x + k * kThreads);
-      uint32_t cur = S[li], best = cur;
-      while (m) {
-        int j = __builtin_ctz(m);
-        m &= m - 1;
-        uint32_t v = S[li + doff[j]] + ((j & 1) ? 0u : 1u);
-        best = v > best ? v : best;
+      const uint32_t cur = S[li];
+      uint32_t best = cur;
+      // even j: the neighbour has the higher index, so it adds one
+      if (__ballot(__popc(m) > 3)) {
+        // some lane of the wave has many lower neighbours: load them all at
+        // once and select under the mask
+        uint32_t v[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          v[j] = S[li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2]];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const uint32_t c = v[j] + ((j & 1) ? 0u : 1u);
+          best = ((m >> j) & 1u) && c > best ? c : best;
+        }
+      } else {
+        uint32_t mm = m;
+        while (mm) {
+          const int j = __builtin_ctz(mm);
+          mm &= mm - 1;
+          const uint32_t c = S[li + c_off[j][0] * (G::HY * G::HX) + c_off[j][1] * G::HX +
+                               c_off[j][2]] + ((j & 1) ? 0u : 1u);
+          best = c > best ? c : best;
+        }
       }
       if (best > cur) {
         S[li] = best;
@@ -258,6 +285,7 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters) {
       break;
     }
   }
+  if (threadIdx.x == 0) atomicAdd(&itot[t % 64], (unsigned long long)(iters + 1));
 }
 
 // mark the 26 neighbour tiles for sweep `next`; one atomic per block adds
@@ -292,7 +320,8 @@ template <int K, int TZ, int TY, int TX>
 __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __restrict__ x, Box box,
                            Tiling tl, const typename Traits<K>::Bin* __restrict__ bins,
                            uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
-                           uint32_t* counters, uint32_t t, TileCoord& c) {
+                           uint32_t* counters, unsigned long long* itot, uint32_t t,
+                           TileCoord& c) {
   using Tr = Traits<K>;
   using G = TileGeom<TZ, TY, TX>;
   using Key = typename Tr::Bin;  // keys fit the signed type of the bins
@@ -375,7 +404,7 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
   __syncthreads();
   for (int i = threadIdx.x; i < G::H; i += kThreads) S[i] = 0;
   __syncthreads();
-  relax<TZ, TY, TX>(S, mk, counters);
+  relax<TZ, TY, TX>(S, mk, counters, itot, t);
   int edge = 0;
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
@@ -399,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
     uint32_t* counters) {
   TileCoord c;
   const bool edge = tile0_body<K, TZ, TY, TX>(x, box, tl, bins, mask, sub, counters,
-                                              blockIdx.x, c);
+                                              relax_total(counters), blockIdx.x, c);
   mark_neighbours(edge, c, tl, stamp, counters, 1);
 }
 
@@ -410,7 +439,8 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
 template <int TZ, int TY, int TX>
 __device__ __forceinline__ bool repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
                             uint32_t* __restrict__ sub, const uint32_t* stamp,
-                            uint32_t* counters, uint32_t sweep, uint32_t t, TileCoord& c) {
+                            uint32_t* counters, unsigned long long* itot, uint32_t sweep,
+                            uint32_t t, TileCoord& c) {
   using G = TileGeom<TZ, TY, TX>;
   __shared__ uint32_t S[G::H];
   // one read decides for the whole block (a neighbour may raise the stamp
@@ -450,7 +480,7 @@ __device__ __forceinline__ bool repair_body(Box box, Tiling tl, const uint16_t* 
   uint32_t old[G::PER];
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) old[k] = S[G::local(threadIdx.x + k * kThreads)];
-  relax<TZ, TY, TX>(S, mk, counters);
+  relax<TZ, TY, TX>(S, mk, counters, itot, t);
   int edge = 0;
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
@@ -471,7 +501,8 @@ __global__ __launch_bounds__(kThreads) void k_repair(
     uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
     uint32_t sweep) {
   TileCoord c;
-  if (repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, sweep, blockIdx.x, c))
+  if (repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, relax_total(counters),
+                              sweep, blockIdx.x, c))
     mark_neighbours(true, c, tl, stamp, counters, sweep + 1);
 }
 
@@ -572,7 +603,8 @@ __global__ __launch_bounds__(kThreads) void k_tile0_p(const BatchDesc* bd, const
     TileCoord c;
     const bool edge = tile0_body<K, TZ, TY, TX>(
         (const typename Traits<K>::Raw*)J.x, J.box, J.tl,
-        (const typename Traits<K>::Bin*)J.bins, J.mask, J.sub, &bc->err, it - J.t0, c);
+        (const typename Traits<K>::Bin*)J.bins, J.mask, J.sub, &bc->err, bc->relax_iters,
+        it - J.t0, c);
     mark_list(edge, c, J.tl, J.stamp, J.t0, bc->lens, list1, 1);
   }
 }
@@ -597,10 +629,10 @@ __global__ __launch_bounds__(kThreads) void k_repair_p(const BatchDesc* bd, cons
     TileCoord c;
     bool edge;
     if (J.tl.tz == 1)
-      edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+      edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
                                     item - J.t0, c);
     else
-      edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+      edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
                                    item - J.t0, c);
     if (edge) mark_list(true, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
   }
@@ -643,7 +675,7 @@ __global__ __launch_bounds__(kThreads) void k_tile0_d(const BatchDesc* bd, const
   TileCoord c;
   const bool edge = tile0_body<K, TZ, TY, TX>(
       (const typename Traits<K>::Raw*)J.x, J.box, J.tl, (const typename Traits<K>::Bin*)J.bins,
-      J.mask, J.sub, &bd->bc->err, it - J.t0, c);
+      J.mask, J.sub, &bd->bc->err, bd->bc->relax_iters, it - J.t0, c);
   mark_list(edge, c, J.tl, J.stamp, J.t0, bd->bc->lens, bd->lists + bd->tiles, 1);
 }
 
@@ -659,10 +691,10 @@ __global__ __launch_bounds__(kThreads) void k_repair_d(const BatchDesc* bd, cons
   TileCoord c;
   bool edge;
   if (J.tl.tz == 1)
-    edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+    edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
                                   item - J.t0, c);
   else
-    edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, sweep,
+    edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
                                  item - J.t0, c);
   if (edge) mark_list(true, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
 }

@@ -49,7 +49,7 @@ class LopcError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("repair_sweeps", ctypes.c_uint64),
                 ("active_tiles_total", ctypes.c_uint64), ("bins_bytes", ctypes.c_uint64),
-                ("subbins_bytes", ctypes.c_uint64)]
+                ("subbins_bytes", ctypes.c_uint64), ("relax_iterations", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -67,7 +67,8 @@ class Job(ctypes.Structure):
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("repair_sweeps", ctypes.c_uint64), ("active_tiles_total", ctypes.c_uint64),
-                ("graph", ctypes.c_int), ("continued", ctypes.c_int)]
+                ("graph", ctypes.c_int), ("continued", ctypes.c_int),
+                ("relax_iterations", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
