@@ -508,39 +508,51 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
     put_bytes(hdr + 12, slen, 4);
   }
 
-  // decoupled look-back for this chunk's offset in the stream body
-  if (threadIdx.x == 0) {
+  // decoupled look-back for this chunk's offset in the stream body: wave 0
+  // reads 64 predecessors per round trip (lane l reads chunk c - 1 - l - 64r)
+  // and adds the sizes up to the nearest inclusive prefix
+  if (threadIdx.x < 64) {
     uint64_t excl = 0;
-    if (c == 0) {
-      __hip_atomic_store(&lookback[0], kLbInc | size, __ATOMIC_RELAXED,
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&lookback[c], (c == 0 ? kLbInc : kLbAgg) | size, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&lookback[c], kLbAgg | size, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-      int64_t j = (int64_t)c - 1;
+    if (c > 0) {
+      int64_t j0 = (int64_t)c - 1;
       uint32_t spins = 0;
-      while (j >= 0) {
-        uint64_t v = __hip_atomic_load(&lookback[j], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t st = v & ~kLbVal;
-        if (st == 0) {
-          if (++spins > (1u << 26)) {  // never reached when every chunk runs
-            set_status(prm, ST_INTERNAL);
+      for (;;) {
+        const int64_t j = j0 - lane();
+        uint64_t v = kLbInc;  // before the first chunk: an inclusive prefix of 0
+        if (j >= 0)
+          v = __hip_atomic_load(&lookback[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t st = v & ~kLbVal;
+        const uint64_t inc = __ballot(st == kLbInc);
+        const uint64_t open = __ballot(st == 0);
+        // lanes up to and including the nearest inclusive one (all if none)
+        const uint64_t need = inc ? ((inc & (0ull - inc)) << 1) - 1ull : ~0ull;
+        if (open & need) {  // a needed predecessor has not published yet
+          if (++spins > (1u << 24)) {  // never reached when every chunk runs
+            if (threadIdx.x == 0) set_status(prm, ST_INTERNAL);
             break;
           }
           __builtin_amdgcn_s_sleep(1);
           continue;
         }
-        excl += v & kLbVal;
-        if (st == kLbInc) break;
-        --j;
+        uint64_t x = ((need >> lane()) & 1ull) ? (v & kLbVal) : 0ull;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+        excl += x;
+        if (inc) break;
+        j0 -= 64;
       }
-      __hip_atomic_store(&lookback[c], kLbInc | (excl + size), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x == 0)
+        __hip_atomic_store(&lookback[c], kLbInc | (excl + size), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
-    s_excl = excl;
-    parts[2 * c] = blen;
-    parts[2 * c + 1] = slen;
+    if (threadIdx.x == 0) {
+      s_excl = excl;
+      parts[2 * c] = blen;
+      parts[2 * c + 1] = slen;
+    }
   }
   __syncthreads();
   const uint64_t body = kHeaderBytes + 4ull * nch;
