@@ -185,7 +185,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   // and the per-sweep counters per batch.
   uint64_t sweeps = 1, active = tl.ntiles, relax_iters = 0;
   uint32_t next = 1;  // first sweep of the next batch
-  uint32_t batch = 2;
+  uint32_t batch = 4;  // typical bounds converge within the first group
   const size_t report = L.counters + kCounterWords * 4;  // Params + counters
   for (;;) {
     for (uint32_t b = 0; b < batch; ++b)

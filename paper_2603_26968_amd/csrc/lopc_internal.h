@@ -64,7 +64,7 @@ struct Tiling {
 // serves every batch of the same composition and workspace.
 
 // Points per item of the batched min/max and quantize passes.
-constexpr uint32_t kMinmaxSpan = 65536;
+constexpr uint32_t kMinmaxSpan = 16384;
 constexpr uint32_t kQuantSpan = 16384;
 // Work-list ring: slot s % 64 holds sweep s.
 constexpr uint32_t kRing = 64;

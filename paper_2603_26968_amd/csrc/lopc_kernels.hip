@@ -20,33 +20,59 @@ namespace {
 
 // ------------------------------------------------------------------ a0
 template <int K>
-__device__ __forceinline__ void minmax_body(const typename Traits<K>::Raw* x, uint32_t n, int64_t* part,
-                            Params* prm, uint32_t blk, uint32_t nblk) {
+__device__ __forceinline__ void minmax_body(const typename Traits<K>::Raw* x, uint32_t n,
+                                            int64_t* part, Params* prm, uint32_t blk,
+                                            uint32_t nblk) {
   using Tr = Traits<K>;
+  using Raw = typename Tr::Raw;
+  constexpr int V = 16 / K;  // values per 16-byte vector
+  constexpr int U = 4;       // vectors in flight per thread
   int64_t lo = INT64_MAX, hi = INT64_MIN;
   bool bad = false;
-  for (uint32_t i = blk * kThreads + threadIdx.x; i < n; i += nblk * kThreads) {
-    typename Tr::Raw u = x[i];
+  auto take = [&](Raw u) {
     bad |= !Tr::finite(u);
-    int64_t k = Tr::key(u);
+    const int64_t k = Tr::key(u);
     lo = k < lo ? k : lo;
     hi = k > hi ? k : hi;
+  };
+  const uint32_t nv = n / V, stride = nblk * kThreads;
+  uint32_t i = blk * kThreads + threadIdx.x;
+  for (; i + (U - 1) * stride < nv; i += U * stride) {
+    Raw u[U][V];
+#pragma unroll
+    for (int q = 0; q < U; ++q) *(uint4*)u[q] = ((const uint4*)x)[i + q * stride];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+      for (int k = 0; k < V; ++k) take(u[q][k]);
   }
+  for (; i < nv; i += stride) {
+    Raw u[V];
+    *(uint4*)u = ((const uint4*)x)[i];
+#pragma unroll
+    for (int k = 0; k < V; ++k) take(u[k]);
+  }
+  for (uint32_t t = nv * V + blk * kThreads + threadIdx.x; t < n; t += stride) take(x[t]);
   if (bad) set_status(prm, ST_NONFINITE);
-  __shared__ int64_t slo[kThreads], shi[kThreads];
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      slo[threadIdx.x] = min(slo[threadIdx.x], slo[threadIdx.x + s]);
-      shi[threadIdx.x] = max(shi[threadIdx.x], shi[threadIdx.x + s]);
-    }
-    __syncthreads();
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) {
+    const int64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
   }
+  __shared__ int64_t slo[kWaves], shi[kWaves];
+  if (lane() == 0) {
+    slo[wave()] = lo;
+    shi[wave()] = hi;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    part[2 * blk] = slo[0];
-    part[2 * blk + 1] = shi[0];
+    for (int w = 1; w < kWaves; ++w) {
+      lo = slo[w] < lo ? slo[w] : lo;
+      hi = shi[w] > hi ? shi[w] : hi;
+    }
+    part[2 * blk] = lo;
+    part[2 * blk + 1] = hi;
   }
 }
 
