@@ -53,14 +53,17 @@ __device__ __forceinline__ uint8_t* kept(Scratch& sc, int l) {
   return l == 0 ? sc.kp0 : (l == 1 ? sc.kp1 : sc.kp2);
 }
 
-// bitmap sizes of the RZE levels for `items` items; returns the top level
-__device__ __forceinline__ int rze_levels(uint32_t items, uint32_t* sz) {
+// Bitmap bytes of RZE level l for `items` items: ceil(items / 8^(l+1)) (each
+// level is the bitmap of the one below; nested ceilings compose).  Computed
+// rather than tabulated so that nothing lands in a private array.
+__device__ __forceinline__ uint32_t lvl_size(uint32_t items, int l) {
+  const uint32_t sh = 3u * (uint32_t)(l + 1);
+  return (items + (1u << sh) - 1u) >> sh;
+}
+// the top level: the first whose bitmap has at most 8 bytes
+__device__ __forceinline__ int rze_top(uint32_t items) {
   int top = 0;
-  sz[0] = (items + 7) / 8;
-  while (sz[top] > 8) {
-    sz[top + 1] = (sz[top] + 7) / 8;
-    ++top;
-  }
+  while (lvl_size(items, top) > 8) ++top;
   return top;
 }
 
@@ -198,10 +201,11 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
   }
   __syncthreads();
   const uint32_t npay = round_prefix(sc, rounds);
-  uint32_t sz[8];
-  const int top = rze_levels(items, sz);
-  for (int l = 0; l < top; ++l) level_encode(lvl(sc, l), sz[l], lvl(sc, l + 1), kept(sc, l), sc.nkept[l], sc);
-  uint32_t out_len = sz[top] + npay * W;
+  const int top = rze_top(items);
+  const uint32_t sz_top = lvl_size(items, top);
+  for (int l = 0; l < top; ++l)
+    level_encode(lvl(sc, l), lvl_size(items, l), lvl(sc, l + 1), kept(sc, l), sc.nkept[l], sc);
+  uint32_t out_len = sz_top + npay * W;
   for (int l = 0; l < top; ++l) out_len += sc.nkept[l];
   if (out_len >= len) {
     const uint8_t* ub = (const uint8_t*)U;
@@ -214,8 +218,8 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
   uint32_t pos = 0;
   {
     const uint8_t* tb = lvl(sc, top);
-    for (uint32_t i = threadIdx.x; i < sz[top]; i += kCT) out[i] = tb[i];
-    pos = sz[top];
+    for (uint32_t i = threadIdx.x; i < sz_top; i += kCT) out[i] = tb[i];
+    pos = sz_top;
   }
   for (int l = top - 1; l >= 0; --l) {
     const uint8_t* kb = kept(sc, l);
@@ -279,17 +283,18 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
   const uint32_t rounds = (NU + 63) / 64;
-  uint32_t sz[8];
-  const int top = rze_levels(items, sz);
-  if (sz[top] > in_len) return false;
+  const int top = rze_top(items);
+  const uint32_t sz_top = lvl_size(items, top);
+  if (sz_top > in_len) return false;
   {
     uint8_t* tb = lvl(sc, top);
-    if (threadIdx.x < 16) tb[threadIdx.x] = threadIdx.x < sz[top] ? in[threadIdx.x] : (uint8_t)0;
+    if (threadIdx.x < 16) tb[threadIdx.x] = threadIdx.x < sz_top ? in[threadIdx.x] : (uint8_t)0;
   }
   __syncthreads();
-  uint32_t pos = sz[top];
+  uint32_t pos = sz_top;
   for (int l = top - 1; l >= 0; --l)
-    if (!level_decode(lvl(sc, l + 1), sz[l], in, pos, in_len, lvl(sc, l), sc)) return false;
+    if (!level_decode(lvl(sc, l + 1), lvl_size(items, l), in, pos, in_len, lvl(sc, l), sc))
+      return false;
   // lv0 holds `items` bitmap bits
   for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t ci = __popc(unit_bits<W>(sc, r * 64 + lane(), NU, items));
