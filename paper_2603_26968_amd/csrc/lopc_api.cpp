@@ -62,6 +62,7 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->graph_sweeps = 0;
   c->sweeps_hint = 16;
   c->persist_pct = 0;
+  c->sweep_hint = 4;
   *out = c;
   return LOPC_OK;
 }
@@ -180,19 +181,30 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
                             (uint16_t*)(ws + L.mask), sub, stamp, counters, hs));
   HIP_CTX(ctx, mark(ctx, 2, hs));
 
-  // repair sweeps (Alg. 1 loop at tile granularity), enqueued in batches; a
-  // sweep with no marked tile costs one empty launch.  One read of the status
-  // and the per-sweep counters per batch.
+  // repair sweeps (Alg. 1 loop at tile granularity).  The first group of K
+  // sweeps (K from the previous call on this context) is enqueued together
+  // with the encoder, which runs only if no tile is marked for sweep K + 1;
+  // one read of the status, the counters and Params then ends a typical
+  // call.  Otherwise sweeps continue in groups (4, 8, 16), one read per
+  // group, and the encoder runs after them.  A sweep with no marked tile
+  // costs one empty launch.
   uint64_t sweeps = 1, active = tl.ntiles, relax_iters = 0;
-  uint32_t next = 1;  // first sweep of the next batch
-  uint32_t batch = 4;  // typical bounds converge within the first group
+  const uint32_t K = (uint32_t)ctx->sweep_hint;
   const size_t report = L.counters + kCounterWords * 4;  // Params + counters
+  for (uint32_t t = 1; t <= K; ++t)
+    HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
+                               counters, t, hs));
+  HIP_CTX(ctx, mark(ctx, 3, hs));
+  HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
+                             (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream, stream_cap,
+                             counters + 1 + ((K + 1) & 63), hs));
+  HIP_CTX(ctx, mark(ctx, 4, hs));
+  if (h_stats)
+    HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+  HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
+  HIP_CTX(ctx, hipStreamSynchronize(hs));
+  uint32_t next = 1, batch = K;
   for (;;) {
-    for (uint32_t b = 0; b < batch; ++b)
-      HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
-                                 counters, next + b, hs));
-    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
-    HIP_CTX(ctx, hipStreamSynchronize(hs));
     const uint32_t* hc = (const uint32_t*)((const uint8_t*)ctx->h_prm + L.counters);
     if (hc[0]) return LOPC_E_INTERNAL;
     relax_iters = 0;
@@ -220,22 +232,31 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
       }
     }
     if (done) break;
-    // clear the ring slots consumed by this batch (marks for sweep next+batch
-    // stay: the next batch starts with it)
+    // clear the ring slots consumed by this group (marks for sweep
+    // next + batch stay: the next group starts with it)
     for (uint32_t t = next; t < next + batch; ++t)
       HIP_CTX(ctx, hipMemsetAsync(counters + 1 + (t & 63), 0, 4, hs));
     next += batch;
-    batch = std::min<uint32_t>(batch * 2, 16);
+    batch = next == K + 1 ? 4 : std::min<uint32_t>(batch * 2, 16);
     if (next + batch >= kMaxSweeps) return LOPC_E_INTERNAL;
+    for (uint32_t b = 0; b < batch; ++b)
+      HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
+                                 counters, next + b, hs));
+    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
+    HIP_CTX(ctx, hipStreamSynchronize(hs));
   }
-
-  HIP_CTX(ctx, mark(ctx, 3, hs));
-  HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
-                        (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream,
-                        stream_cap, hs));
-  HIP_CTX(ctx, mark(ctx, 4, hs));
-  if (h_stats)
-    HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+  // the next call starts with as many sweeps as this one needed, plus one
+  ctx->sweep_hint = (int)std::min<uint64_t>(16, std::max<uint64_t>(2, sweeps));
+  if (next > 1) {
+    // the gated encoder did not run: encode now
+    HIP_CTX(ctx, mark(ctx, 3, hs));
+    HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
+                               (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream, stream_cap,
+                               nullptr, hs));
+    HIP_CTX(ctx, mark(ctx, 4, hs));
+    if (h_stats)
+      HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+  }
   HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
   HIP_CTX(ctx, hipStreamSynchronize(hs));
   if (ctx->timing) {
@@ -312,7 +333,6 @@ static int decompress_core(lopc_ctx* ctx, const uint8_t* hdr, const void* d_stre
   uint8_t* ws = (uint8_t*)d_ws;
   Params* prm = (Params*)ws;
   uint64_t* offsets = (uint64_t*)(ws + align256(sizeof(Params)));
-  HIP_CTX(ctx, hipMemsetAsync(prm, 0, sizeof(Params), hs));
   HIP_CTX(ctx, mark(ctx, 5, hs));
   HIP_CTX(ctx, launch_offsets((const uint8_t*)d_stream, (uint32_t)nch,
                               stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs));

@@ -583,13 +583,16 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
 }
 
 // Single field: chunks are taken in ticket order (the look-back of a chunk
-// only waits for chunks whose workgroups already run).
+// only waits for chunks whose workgroups already run).  Skipped entirely
+// when gate is given and *gate != 0 (the repair sweeps enqueued before it
+// have not reached the fixed point; the host then sweeps on and encodes).
 template <int K>
 __global__ __launch_bounds__(kCT) void k_encode(
     uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
     const uint32_t* __restrict__ sub, uint64_t* lookback, uint32_t* parts,
-    Params* prm, uint8_t* stream, uint64_t cap, uint32_t nch) {
+    Params* prm, uint8_t* stream, uint64_t cap, uint32_t nch, const uint32_t* gate) {
   __shared__ uint32_t s_chunk;
+  if (gate && *gate) return;
   if (threadIdx.x == 0) s_chunk = atomicAdd(&prm->ticket, 1u);
   __syncthreads();
   const uint32_t c = s_chunk;
@@ -617,9 +620,12 @@ __device__ __forceinline__ void offsets_body(const uint8_t* stream, uint32_t nch
   if (threadIdx.x == 0 && total != body_bytes) set_status(prm, ST_FORMAT);
 }
 
+// Single field: also starts the decoder's status word (no separate clear).
 __global__ __launch_bounds__(kThreads) void k_offsets(
     const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
     uint64_t* offsets, Params* prm) {
+  if (threadIdx.x == 0) prm->status = 0;
+  __syncthreads();
   offsets_body(stream, nch, body_bytes, offsets, prm);
 }
 
@@ -1061,15 +1067,16 @@ __global__ __launch_bounds__(kCT, 6) void k_decode_d(const BatchDesc* bd, const 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_encode(int dtype, uint32_t n, const void* bins,
                          const uint32_t* sub, uint64_t* lookback, uint32_t* parts,
-                         Params* prm, uint8_t* stream, size_t cap, hipStream_t s) {
+                         Params* prm, uint8_t* stream, size_t cap, const uint32_t* gate,
+                         hipStream_t s) {
   uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
   uint32_t nch = (n + W - 1) / W;
   if (dtype == 0)
     k_encode<4><<<nch, kCT, 0, s>>>(n, (const int32_t*)bins, sub, lookback, parts, prm,
-                                    stream, cap, nch);
+                                    stream, cap, nch, gate);
   else
     k_encode<8><<<nch, kCT, 0, s>>>(n, (const int64_t*)bins, sub, lookback, parts, prm,
-                                    stream, cap, nch);
+                                    stream, cap, nch, gate);
   return hipGetLastError();
 }
 

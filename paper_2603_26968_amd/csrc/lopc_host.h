@@ -46,6 +46,7 @@ struct lopc_ctx {
   int timing;
   hipEvent_t ev[8];
   double ms[LOPC_PHASES];
+  int sweep_hint;      // single field: repair sweeps enqueued before the first read
   // batches
   int use_graph;       // capture batch sequences as graphs
   int graph_sweeps;    // sweeps per graph (0 = adaptive)

@@ -174,7 +174,7 @@ hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask,
 hipError_t launch_encode(int dtype, uint32_t n, const void* bins,
                          const uint32_t* sub, uint64_t* lookback,
                          uint32_t* parts, Params* prm, uint8_t* stream,
-                         size_t cap, hipStream_t s);
+                         size_t cap, const uint32_t* gate, hipStream_t s);
 hipError_t launch_sum_parts(const uint32_t* parts, uint32_t nch, Params* prm,
                             hipStream_t s);
 hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
