@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lopc_device.h"
 
@@ -352,13 +353,15 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
   using G = TileGeom<TZ, TY, TX>;
   using Key = typename Tr::Bin;  // keys fit the signed type of the bins
   using Bin = typename Tr::Bin;
+  // key and bin of a halo point side by side: one LDS read per neighbour
+  // (one 8-byte read for float32, one 16-byte read for float64)
+  using KB = typename std::conditional<K == 4, uint2, ulonglong2>::type;
   constexpr int NJ = TZ == 1 ? 6 : 14;  // 2D: only the in-plane offsets
-  constexpr int kKB = G::H * (int)(sizeof(Key) + sizeof(Bin));
+  constexpr int kKB = G::H * (int)sizeof(KB);
   constexpr int kBytes = kKB > G::H * 4 ? kKB : G::H * 4;
   constexpr int HL = (G::H + kThreads - 1) / kThreads;  // halo loads per thread
   __shared__ __attribute__((aligned(16))) uint8_t buf[kBytes];
-  Key* KY = (Key*)buf;
-  Bin* BN = (Bin*)(buf + G::H * sizeof(Key));
+  KB* P = (KB*)buf;
   uint32_t* S = (uint32_t*)buf;  // reused once the flags are built
 
   c = tile_coord<TZ, TY, TX>(t, tl);
@@ -385,8 +388,10 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
     for (int q = 0; q < HL; ++q) {
       const int i = threadIdx.x + q * kThreads;
       if (i < G::H) {
-        KY[i] = (Key)Tr::key(u[q]);
-        BN[i] = b[q];
+        KB e;
+        e.x = (decltype(e.x))(Key)Tr::key(u[q]);
+        e.y = (decltype(e.y))b[q];
+        P[i] = e;
       }
     }
   }
@@ -403,14 +408,18 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
     const int z = c.z0 + iz, y = c.y0 + iy, xx = c.x0 + ix;
     uint32_t m = 0;
     const int li = G::local(i);
-    const Key kp = KY[li];
-    const Bin bp = BN[li];
+    const KB ep = P[li];
+    const Key kp = (Key)ep.x;
+    const Bin bp = (Bin)ep.y;
     if (inner) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int ln = li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2];
-        const Key kq = KY[ln];
-        if (BN[ln] == bp && (kq < kp || (kq == kp && (j & 1)))) m |= 1u << j;
+        const KB eq = P[ln];
+        const Key kq = (Key)eq.x;
+        // branch-free: same bin, and lower in (value, index) order
+        const bool lower = (kq < kp) | ((kq == kp) & ((j & 1) != 0));
+        m |= (uint32_t)(((Bin)eq.y == bp) & lower) << j;
       }
       mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)m;
     } else if (z < box.nz && y < box.ny && xx < box.nx) {
@@ -420,8 +429,11 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
         if (zz < 0 || zz >= box.nz || yy < 0 || yy >= box.ny || xq < 0 || xq >= box.nx)
           continue;
         const int ln = li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2];
-        const Key kq = KY[ln];
-        if (BN[ln] == bp && (kq < kp || (kq == kp && (j & 1)))) m |= 1u << j;  // odd j: lower index
+        const KB eq = P[ln];
+        const Key kq = (Key)eq.x;
+        // odd j: the neighbour has the lower index
+        const bool lower = (kq < kp) | ((kq == kp) & ((j & 1) != 0));
+        m |= (uint32_t)(((Bin)eq.y == bp) & lower) << j;
       }
       mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)m;
     }
