@@ -126,38 +126,6 @@ __device__ void level_encode(const uint8_t* cur, uint32_t n, uint8_t* nxt,
   __syncthreads();
 }
 
-// Inverse of level_encode: child byte i = the last kept byte at or before i
-// (0 if none), reading the kept bytes from in[pos...).  Returns false if they
-// run past in_len.
-__device__ bool level_decode(const uint8_t* par, uint32_t n, const uint8_t* in,
-                             uint32_t& pos, uint32_t in_len, uint8_t* child,
-                             Scratch& sc) {
-  const uint32_t np = (n + 7) / 8;
-  uint32_t pb = 0;
-  if (threadIdx.x < np) {
-    pb = par[threadIdx.x];
-    uint32_t valid = n - threadIdx.x * 8;
-    if (valid < 8) pb &= (1u << valid) - 1;
-  }
-  uint32_t tot;
-  uint32_t e = block_excl_scan<uint32_t, kCW>((uint32_t)__popc(pb), sc.scan, tot);
-  if (pos + tot > in_len) return false;
-  if (threadIdx.x < np + 1) {
-    uint32_t i0 = threadIdx.x * 8;
-    for (uint32_t b = 0; b < 8; ++b) {
-      uint8_t v = 0;
-      if (i0 + b < n) {
-        if ((pb >> b) & 1) ++e;
-        v = e ? in[pos + e - 1] : (uint8_t)0;
-      }
-      child[i0 + b] = v;  // bytes past n are zero padding
-    }
-  }
-  pos += tot;
-  __syncthreads();
-  return true;
-}
-
 // RZE_W over the first `len` bytes of the unit array U (zero beyond len)
 // into out.  Units from `nua` on are known to be zero (bit planes above the
 // highest set bit) and are skipped.  Returns the output length; pt = 1 when
@@ -277,33 +245,119 @@ __device__ __forceinline__ uint32_t unit_bits(const Scratch& sc, uint32_t u, uin
   }
 }
 
+// One level of the bitmap recursion undone by one wave (no block barrier):
+// child byte i = the last kept byte at or before i (0 if none), the kept
+// bytes read from in[pos...); lane l handles parent bytes [P*l, P*l + P).
+// Returns false (wave-uniform) if the kept bytes run past in_len.
+__device__ bool level_decode_w(const uint8_t* par, uint32_t n, const uint8_t* in,
+                               uint32_t& pos, uint32_t in_len, uint8_t* child) {
+  const uint32_t np = (n + 7) / 8;    // <= 256
+  const uint32_t P = (np + 63) / 64;  // <= 4
+  uint32_t pb[4];
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t idx = (uint32_t)lane() * P + q;
+    pb[q] = 0;
+    if ((uint32_t)q < P && idx < np) {
+      uint32_t v = par[idx];
+      const uint32_t valid = n - idx * 8;
+      if (valid < 8) v &= (1u << valid) - 1;
+      pb[q] = v;
+    }
+    c += (uint32_t)__popc(pb[q]);
+  }
+  const uint32_t incl = wave_incl_scan(c);
+  const uint32_t tot = __shfl(incl, 63, 64);
+  if (pos + tot > in_len) return false;
+  uint32_t e = incl - c;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t idx = (uint32_t)lane() * P + q;
+    if ((uint32_t)q < P && idx < np) {
+      const uint32_t i0 = idx * 8;
+      uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        uint32_t v = 0;
+        if (i0 + b < n) {
+          if ((pb[q] >> b) & 1) ++e;
+          v = e ? in[pos + e - 1] : 0u;
+        }
+        if (b < 4) w0 |= v << (8 * b);
+        else w1 |= v << (8 * (b - 4));
+      }
+      ((uint32_t*)child)[2 * idx] = w0;  // bytes past n are zero
+      ((uint32_t*)child)[2 * idx + 1] = w1;
+    }
+  }
+  pos += tot;
+  __builtin_amdgcn_wave_barrier();
+  return true;
+}
+
+// Front half of an RZE decode, on wave 0 alone: the top bitmap, every level
+// down to the items' bitmap lv0, the payload offset of every round of 64
+// units (sc.rpre, exclusive) and the consistency of the total with in_len.
+// Leaves sc.nkept[0] = ok and sc.nkept[1] = offset of the payload.
+template <int W>
+__device__ void rze_decode_head(const uint8_t* in, uint32_t in_len, uint32_t items,
+                                uint32_t rounds, Scratch& sc) {
+  const int top = rze_top(items);
+  const uint32_t sz_top = lvl_size(items, top);
+  bool ok = sz_top <= in_len;
+  uint32_t pos = sz_top;
+  if (ok) {
+    uint8_t* tb = lvl(sc, top);
+    if (lane() < 16) tb[lane()] = (uint32_t)lane() < sz_top ? in[lane()] : (uint8_t)0;
+    __builtin_amdgcn_wave_barrier();
+    for (int l = top - 1; l >= 0 && ok; --l)
+      ok = level_decode_w(lvl(sc, l + 1), lvl_size(items, l), in, pos, in_len, lvl(sc, l));
+  }
+  if (ok) {
+    // items of round r: bits [64r * 8/W, 64(r + 1) * 8/W) of lv0, i.e. 8/W
+    // 64-bit words; bits from `items` on do not count
+    constexpr uint32_t WPR = 8 / W;
+    const uint64_t* lw = (const uint64_t*)sc.lv0;
+    uint32_t cnt = 0;
+    if ((uint32_t)lane() < rounds) {
+#pragma unroll
+      for (uint32_t q = 0; q < WPR; ++q) {
+        const uint32_t w = (uint32_t)lane() * WPR + q;
+        if (64ull * w < items) {
+          const uint64_t valid = items - 64ull * w;
+          const uint64_t m = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
+          cnt += (uint32_t)__popcll(lw[w] & m);
+        }
+      }
+    }
+    const uint32_t incl = wave_incl_scan(cnt);
+    if ((uint32_t)lane() < rounds) sc.rpre[lane()] = incl - cnt;
+    const uint32_t npay = __shfl(incl, 63, 64);
+    ok = pos + npay * W == in_len;
+  }
+  if (lane() == 0) {
+    sc.nkept[0] = ok ? 1u : 0u;
+    sc.nkept[1] = pos;
+  }
+}
+
+// Inverse of rze_encode: in[0, in_len) -> the first `len` bytes of U (units
+// rounded up; bytes past len are zero).  Returns false on malformed input;
+// never reads outside [in, in + in_len).  If G > 0 the units are bit planes
+// of G groups and sc.planes receives the mask of planes holding a nonzero
+// unit.  Three block barriers: after the front half (wave 0), after the
+// payload, after the plane mask.
 template <int W>
 __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
                            uint64_t* U, Scratch& sc, uint32_t G) {
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
   const uint32_t rounds = (NU + 63) / 64;
-  const int top = rze_top(items);
-  const uint32_t sz_top = lvl_size(items, top);
-  if (sz_top > in_len) return false;
-  {
-    uint8_t* tb = lvl(sc, top);
-    if (threadIdx.x < 16) tb[threadIdx.x] = threadIdx.x < sz_top ? in[threadIdx.x] : (uint8_t)0;
-  }
+  if (wave() == 0) rze_decode_head<W>(in, in_len, items, rounds, sc);
   __syncthreads();
-  uint32_t pos = sz_top;
-  for (int l = top - 1; l >= 0; --l)
-    if (!level_decode(lvl(sc, l + 1), lvl_size(items, l), in, pos, in_len, lvl(sc, l), sc))
-      return false;
-  // lv0 holds `items` bitmap bits
-  for (uint32_t r = wave(); r < rounds; r += kCW) {
-    const uint32_t ci = __popc(unit_bits<W>(sc, r * 64 + lane(), NU, items));
-    const uint32_t inc = __ballot(ci != 0u) ? wave_incl_scan(ci) : 0u;
-    if (lane() == 63) sc.rpre[r] = inc;
-  }
-  __syncthreads();
-  const uint32_t npay = round_prefix(sc, rounds);
-  if (pos + npay * W != in_len) return false;
+  if (!sc.nkept[0]) return false;
+  const uint32_t pos = sc.nkept[1];
   uint64_t pm = 0;
   for (uint32_t r = wave(); r < rounds; r += kCW) {
     const uint32_t u = r * 64 + lane();
