@@ -174,10 +174,8 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
                              nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
                              s.d, hs));
   HIP_CTX(ctx, mark(ctx, 1, hs));
-  // quantize; then order flags + first relaxation, fused per tile
-  HIP_CTX(ctx, launch_quant(dtype, d_field, (uint32_t)s.n, prm, ws + L.bins,
-                            (int)std::min<uint64_t>(4096, (s.n + 1023) / 1024), hs));
-  HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, ws + L.bins,
+  // quantize, order flags and first relaxation, fused per tile
+  HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
                             (uint16_t*)(ws + L.mask), sub, stamp, counters, hs));
   HIP_CTX(ctx, mark(ctx, 2, hs));
 

@@ -239,11 +239,9 @@ hipError_t enqueue(lopc_ctx* c, int op, uint8_t* ws, const BatchDesc& D, uint32_
       if (pers) {
         Q(launch_minmax_p(d, bd, jobs, grid_of(c, PK_MINMAX), s));
         Q(launch_params_p(d, bd, jobs, grid_of(c, PK_PARAMS), s));
-        Q(launch_quant_p(d, bd, jobs, grid_of(c, PK_QUANT), s));
       } else {
         Q(launch_minmax_d(d, bd, jobs, items(D, PH_MM, g0, g1), s));
         Q(launch_params_d(d, bd, jobs, D.job0[g1] - D.job0[g0], s));
-        Q(launch_quant_d(d, bd, jobs, items(D, PH_Q, g0, g1), s));
       }
     }
     for (int g = 0; g < kGroups; ++g) {

@@ -165,7 +165,7 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
                          hipStream_t s);
 hipError_t launch_quant(int dtype, const void* x, uint32_t n, Params* prm, void* bins,
                         int nblocks, hipStream_t s);
-hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, const void* bins,
+hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
                         uint32_t* counters, hipStream_t s);
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask,

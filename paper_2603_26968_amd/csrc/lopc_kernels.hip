@@ -345,7 +345,7 @@ __device__ void mark_neighbours(bool edge, const TileCoord& c, const Tiling& tl,
 // Returns (block-uniform) whether a boundary subbin of the tile is nonzero.
 template <int K, int TZ, int TY, int TX>
 __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __restrict__ x, Box box,
-                           Tiling tl, const typename Traits<K>::Bin* __restrict__ bins,
+                           Tiling tl, Params* prm, typename Traits<K>::Bin* __restrict__ bins,
                            uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
                            uint32_t* counters, unsigned long long* itot, uint32_t t,
                            TileCoord& c) {
@@ -366,34 +366,37 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
 
   c = tile_coord<TZ, TY, TX>(t, tl);
   {
-    // issue every load of the halo first, then store to LDS
+    // the values of the halo (every load issued first); their bins are
+    // computed here (Sec. IV-A), not read back from a separate pass
     typename Tr::Raw u[HL];
-    Bin b[HL];
 #pragma unroll
     for (int q = 0; q < HL; ++q) {
       const int i = threadIdx.x + q * kThreads;
       u[q] = 0;
-      b[q] = 0;
       if (i < G::H) {
         int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
         int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
-        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx) {
-          const int64_t g = ((int64_t)z * box.ny + y) * box.nx + xx;
-          u[q] = x[g];
-          b[q] = bins[g];
-        }
+        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx)
+          u[q] = x[((int64_t)z * box.ny + y) * box.nx + xx];
       }
     }
+    const double inv = prm->inv;
+    bool bad_v = false, bad_r = false;
 #pragma unroll
     for (int q = 0; q < HL; ++q) {
       const int i = threadIdx.x + q * kThreads;
       if (i < G::H) {
+        bad_v |= !Tr::finite(u[q]);
+        const int64_t bq = Tr::q(Tr::to_double(u[q]), inv);
+        bad_r |= bq > Tr::kBinLimit || bq < -Tr::kBinLimit;
         KB e;
         e.x = (decltype(e.x))(Key)Tr::key(u[q]);
-        e.y = (decltype(e.y))b[q];
+        e.y = (decltype(e.y))(Bin)bq;
         P[i] = e;
       }
     }
+    if (bad_v) set_status(prm, ST_NONFINITE);
+    if (bad_r) set_status(prm, ST_RANGE);
   }
   __syncthreads();
 
@@ -411,6 +414,8 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
     const KB ep = P[li];
     const Key kp = (Key)ep.x;
     const Bin bp = (Bin)ep.y;
+    if (z < box.nz && y < box.ny && xx < box.nx)
+      bins[((int64_t)z * box.ny + y) * box.nx + xx] = bp;  // for the encoder
     if (inner) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -460,12 +465,12 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
 
 template <int K, int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_tile0(
-    const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl,
-    const typename Traits<K>::Bin* __restrict__ bins,
+    const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl, Params* prm,
+    typename Traits<K>::Bin* __restrict__ bins,
     uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
     uint32_t* counters) {
   TileCoord c;
-  const bool edge = tile0_body<K, TZ, TY, TX>(x, box, tl, bins, mask, sub, counters,
+  const bool edge = tile0_body<K, TZ, TY, TX>(x, box, tl, prm, bins, mask, sub, counters,
                                               relax_total(counters), blockIdx.x, c);
   mark_neighbours(edge, c, tl, stamp, counters, 1);
 }
@@ -640,8 +645,8 @@ __global__ __launch_bounds__(kThreads) void k_tile0_p(const BatchDesc* bd, const
     __syncthreads();
     TileCoord c;
     const bool edge = tile0_body<K, TZ, TY, TX>(
-        (const typename Traits<K>::Raw*)J.x, J.box, J.tl,
-        (const typename Traits<K>::Bin*)J.bins, J.mask, J.sub, &bc->err, bc->relax_iters,
+        (const typename Traits<K>::Raw*)J.x, J.box, J.tl, J.prm,
+        (typename Traits<K>::Bin*)J.bins, J.mask, J.sub, &bc->err, bc->relax_iters,
         it - J.t0, c);
     mark_list(edge, c, J.tl, J.stamp, J.t0, bc->lens, list1, 1);
   }
@@ -712,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void k_tile0_d(const BatchDesc* bd, const
   const Job& J = jobs[find_job<&Job::t0>(jobs, (int)bd->job0[g], (int)bd->job0[g + 1], it)];
   TileCoord c;
   const bool edge = tile0_body<K, TZ, TY, TX>(
-      (const typename Traits<K>::Raw*)J.x, J.box, J.tl, (const typename Traits<K>::Bin*)J.bins,
+      (const typename Traits<K>::Raw*)J.x, J.box, J.tl, J.prm, (typename Traits<K>::Bin*)J.bins,
       J.mask, J.sub, &bd->bc->err, bd->bc->relax_iters, it - J.t0, c);
   mark_list(edge, c, J.tl, J.stamp, J.t0, bd->bc->lens, bd->lists + bd->tiles, 1);
 }
@@ -771,23 +776,23 @@ hipError_t launch_quant(int dtype, const void* x, uint32_t n, Params* prm, void*
   return hipGetLastError();
 }
 
-hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, const void* bins,
+hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
                         uint32_t* counters, hipStream_t s) {
   if (t.tz == 1) {
     if (dtype == 0)
-      k_tile0<4, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t,
-                                                           (const int32_t*)bins, mask, sub, stamp, counters);
+      k_tile0<4, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
+                                                           (int32_t*)bins, mask, sub, stamp, counters);
     else
-      k_tile0<8, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t,
-                                                           (const int64_t*)bins, mask, sub, stamp, counters);
+      k_tile0<8, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
+                                                           (int64_t*)bins, mask, sub, stamp, counters);
   } else {
     if (dtype == 0)
-      k_tile0<4, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t,
-                                                          (const int32_t*)bins, mask, sub, stamp, counters);
+      k_tile0<4, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
+                                                          (int32_t*)bins, mask, sub, stamp, counters);
     else
-      k_tile0<8, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t,
-                                                          (const int64_t*)bins, mask, sub, stamp, counters);
+      k_tile0<8, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
+                                                          (int64_t*)bins, mask, sub, stamp, counters);
   }
   return hipGetLastError();
 }
