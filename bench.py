@@ -182,6 +182,18 @@ def bench_single(args, name):
             "frac": round(kernels[dom]["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": kernels[dom]["bytes"]}
 
+    # the reconstruction's invariants, checked on the device (error bound,
+    # order of every edge, critical types)
+    torch.cuda.synchronize()
+    tv = time.perf_counter()
+    rep = P.verify(x, bufs[3], stats["eps"])
+    tv = time.perf_counter() - tv
+    check = {k: rep[k] for k in ("bound_violations", "order_violations", "type_mismatches",
+                                 "max_abs_error", "edges")}
+    check["critical_points"] = dict(zip(("regular", "minima", "maxima", "saddles"),
+                                         rep["types_orig"]))
+    check["ms"] = round(tv * 1e3, 3)
+
     gpu_stream = s.cpu().numpy().tobytes()
     gpu_y = bufs[3].cpu().numpy()
 
@@ -240,6 +252,7 @@ def bench_single(args, name):
         "bins_bytes": int(stats["bins_bytes"]), "subbins_bytes": int(stats["subbins_bytes"]),
         "kernels": {q: {"ms": round(v["ms"], 4), "GBps": round(v["GBps"], 1)} for q, v in kernels.items()},
         "roofline": roof,
+        "invariants": check,
     }
     if extra:
         out["other_eb"] = extra

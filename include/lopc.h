@@ -222,6 +222,31 @@ int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void
 enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT = 3 };
 int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value);
 
+/* ------------------------------------------------------------------ checks
+ * What LOPC guarantees of a reconstruction d_recon of d_orig (same dtype and
+ * shape), measured on the device: the error bound |x - x'| <= eps, checked
+ * exactly [Sec. IV-A]; the (value, index) order of the two ends of every
+ * edge of the triangulation, ties broken by the lower index [Sec. II,
+ * Sec. IV-E]; and the critical type of every vertex (minimum: no lower link
+ * vertex; maximum: no upper one; regular: one connected component each;
+ * saddle otherwise; boundary vertices use the in-grid part of the link)
+ * [Sec. II].  d_ws: lopc_verify_workspace_size() bytes. */
+typedef struct {
+  uint64_t points;
+  uint64_t bound_violations;   /* points with |x - x'| > eps               */
+  double max_abs_error;        /* largest |x - x'| (rounded to binary64)   */
+  uint64_t edges;              /* edges with both ends in the grid         */
+  uint64_t order_violations;   /* edges whose end points swapped order     */
+  uint64_t types_orig[4];      /* regular, minima, maxima, saddles         */
+  uint64_t types_recon[4];
+  uint64_t type_mismatches;    /* vertices whose critical type changed     */
+} lopc_verify_report;
+
+size_t lopc_verify_workspace_size(void);
+int lopc_verify(lopc_ctx* ctx, const void* d_orig, const void* d_recon, int dtype, int ndim,
+                const int64_t* dims, double eps, void* d_ws, size_t ws_bytes, void* stream,
+                lopc_verify_report* h_report);
+
 /* Static text for a status code. */
 const char* lopc_strerror(int status);
 

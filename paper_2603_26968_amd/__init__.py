@@ -18,7 +18,7 @@ _BINDING = (
     "lopc_compress_batch", "lopc_decompress_batch", "lopc_ctx_last_batch",
     "lopc_ctx_set_option", "LOPC_OPT_BATCH_GRAPH", "LOPC_OPT_GRAPH_SWEEPS",
     "LOPC_OPT_PERSIST_PCT", "lopc_ctx_last_batch_headers", "lopc_batch_autotune",
-    "autotune_compress_batch",
+    "autotune_compress_batch", "verify", "VerifyReport", "lopc_verify",
 )
 
 

@@ -372,6 +372,42 @@ int lopc_decompress_h(lopc_ctx* ctx, const void* h_header, const void* d_stream,
                          field_cap, d_ws, ws_bytes, (hipStream_t)stream);
 }
 
+size_t lopc_verify_workspace_size(void) { return 256; }
+
+int lopc_verify(lopc_ctx* ctx, const void* d_orig, const void* d_recon, int dtype, int ndim,
+                const int64_t* dims, double eps, void* d_ws, size_t ws_bytes, void* stream,
+                lopc_verify_report* h_report) {
+  if (!ctx || !d_orig || !d_recon || !d_ws || !h_report || (dtype != 0 && dtype != 1))
+    return LOPC_E_ARG;
+  Shape s;
+  if (int st = make_shape(ndim, dims, &s)) return st;
+  if (ws_bytes < 256 || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
+  const uint64_t k = dtype == 0 ? 4 : 8;
+  if (((uintptr_t)d_orig & (k - 1)) || ((uintptr_t)d_recon & (k - 1))) return LOPC_E_ARG;
+  if (!std::isfinite(eps) || !(eps >= 0)) return LOPC_E_BOUND;
+  hipStream_t hs = (hipStream_t)stream;
+  HIP_CTX(ctx, hipSetDevice(ctx->device));
+  unsigned long long* out = (unsigned long long*)d_ws;
+  HIP_CTX(ctx, hipMemsetAsync(out, 0, 256, hs));
+  const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->num_cu * 8,
+                                                                   (s.n + 255) / 256));
+  HIP_CTX(ctx, launch_verify(dtype, d_orig, d_recon, s.box, eps, out, blocks, hs));
+  unsigned long long* h = (unsigned long long*)ctx->h_cnt;
+  HIP_CTX(ctx, hipMemcpyAsync(h, out, 14 * 8, hipMemcpyDeviceToHost, hs));
+  HIP_CTX(ctx, hipStreamSynchronize(hs));
+  h_report->points = h[0];
+  h_report->bound_violations = h[1];
+  std::memcpy(&h_report->max_abs_error, &h[2], 8);
+  h_report->edges = h[3];
+  h_report->order_violations = h[4];
+  for (int i = 0; i < 4; ++i) {
+    h_report->types_orig[i] = h[5 + i];
+    h_report->types_recon[i] = h[9 + i];
+  }
+  h_report->type_mismatches = h[13];
+  return LOPC_OK;
+}
+
 int lopc_ctx_last_header(lopc_ctx* ctx, void* h_header) {
   if (!ctx || !h_header) return LOPC_E_ARG;
   if (!ctx->have_header) return LOPC_E_ARG;

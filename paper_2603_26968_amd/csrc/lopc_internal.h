@@ -225,6 +225,10 @@ hipError_t launch_encode_d(int dtype, const BatchDesc* bd, const Job* jobs, int 
 hipError_t launch_decode_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
                            hipStream_t s);
 
+// Invariant checker (lopc_verify.hip): adds 14 report words to out.
+hipError_t launch_verify(int dtype, const void* x, const void* y, Box box, double eps,
+                         unsigned long long* out, int blocks, hipStream_t s);
+
 // Resident blocks per CU of each persistent batch kernel (occupancy query).
 enum { PK_ZERO, PK_MINMAX, PK_PARAMS, PK_QUANT, PK_TILE0, PK_REPAIR, PK_ENCODE, PK_DHEAD,
        PK_DECODE, PK_COUNT };

@@ -32,7 +32,8 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_ctx_last_timings", "lopc_ctx_last_hip_error", "lopc_decompress_h",
            "lopc_ctx_last_header", "lopc_batch_workspace_size", "lopc_compress_batch",
            "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option",
-           "lopc_ctx_last_batch_headers", "lopc_batch_autotune")
+           "lopc_ctx_last_batch_headers", "lopc_batch_autotune", "lopc_verify",
+           "lopc_verify_workspace_size")
 LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT = 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
@@ -72,6 +73,19 @@ class BatchStats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class VerifyReport(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_uint64), ("bound_violations", ctypes.c_uint64),
+                ("max_abs_error", ctypes.c_double), ("edges", ctypes.c_uint64),
+                ("order_violations", ctypes.c_uint64), ("types_orig", ctypes.c_uint64 * 4),
+                ("types_recon", ctypes.c_uint64 * 4), ("type_mismatches", ctypes.c_uint64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["types_orig"] = list(self.types_orig)
+        d["types_recon"] = list(self.types_recon)
+        return d
 
 
 _lib = None
@@ -130,6 +144,11 @@ def load() -> ctypes.CDLL:
     L.lopc_ctx_last_batch.restype = ci
     L.lopc_batch_autotune.argtypes = [vp, ci, ci, jp, vp, sz, vp, ci, ctypes.POINTER(ci)]
     L.lopc_batch_autotune.restype = ci
+    L.lopc_verify_workspace_size.argtypes = []
+    L.lopc_verify_workspace_size.restype = sz
+    L.lopc_verify.argtypes = [vp, vp, vp, ci, ci, i64p, cd, vp, sz, vp,
+                              ctypes.POINTER(VerifyReport)]
+    L.lopc_verify.restype = ci
     L.lopc_ctx_last_batch_headers.argtypes = [vp, ci, vp]
     L.lopc_ctx_last_batch_headers.restype = ci
     L.lopc_ctx_set_option.argtypes = [vp, ci, ctypes.c_int64]
@@ -402,6 +421,24 @@ def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
     if st:
         raise LopcError(st, "lopc_decompress", ctx)
     return out
+
+
+def verify(x: torch.Tensor, y: torch.Tensor, eps: float, ctx=None) -> dict:
+    """Check a reconstruction y of x on the device: error bound, order of
+    every edge, critical types (lopc_verify).  Returns the report as a dict
+    (types in the order regular, minima, maxima, saddles)."""
+    code = _check_field(x)
+    if y.shape != x.shape or y.dtype != x.dtype or not y.is_contiguous() or y.device != x.device:
+        raise ValueError("y must be a contiguous tensor of x's shape, dtype and device")
+    ctx = context(x.device.index) if ctx is None else ctx
+    ws = torch.empty(load().lopc_verify_workspace_size(), dtype=torch.uint8, device=x.device)
+    rep = VerifyReport()
+    st = load().lopc_verify(ctx, x.data_ptr(), y.data_ptr(), code, x.dim(), _dims(x.shape),
+                            float(eps), ws.data_ptr(), ws.numel(),
+                            torch.cuda.current_stream(x.device).cuda_stream, ctypes.byref(rep))
+    if st:
+        raise LopcError(st, "lopc_verify", ctx)
+    return rep.as_dict()
 
 
 # ------------------------------------------------------------------ batches
