@@ -75,7 +75,7 @@ int make_plan(int op, int n, const lopc_job* in, uintptr_t ws, Plan& P, int* bad
   P.jobs.assign(n, Job{});
   BatchDesc& D = P.desc;
   std::memset(&D, 0, sizeof(D));
-  uint64_t it[PH_N] = {0, 0, 0, 0};
+  uint64_t it[PH_N] = {0, 0, 0};
   int g_prev = -1;
   for (int q = 0; q < n; ++q) {
     const int i = P.order[q];
@@ -111,11 +111,9 @@ int make_plan(int op, int n, const lopc_job* in, uintptr_t ws, Plan& P, int* bad
       J.stream_size = j.in_bytes;
     }
     J.mm0 = (uint32_t)it[PH_MM];
-    J.q0 = (uint32_t)it[PH_Q];
     J.t0 = (uint32_t)it[PH_T];
     J.c0 = (uint32_t)it[PH_C];
     it[PH_MM] += (uint64_t)J.mm_blocks;
-    it[PH_Q] += (s.n + kQuantSpan - 1) / kQuantSpan;
     it[PH_T] += J.tl.ntiles;
     it[PH_C] += J.nch;
   }

@@ -63,9 +63,8 @@ struct Tiling {
 // memory (the plan below and the job table), so one captured launch sequence
 // serves every batch of the same composition and workspace.
 
-// Points per item of the batched min/max and quantize passes.
+// Points per item of the batched min/max pass.
 constexpr uint32_t kMinmaxSpan = 16384;
-constexpr uint32_t kQuantSpan = 16384;
 // Work-list ring: slot s % 64 holds sweep s.
 constexpr uint32_t kRing = 64;
 // Single-field repair counters: [0] error flag, [1 + s % 64] tiles marked for
@@ -75,7 +74,7 @@ constexpr uint32_t kCounterWords = kRelaxWord + 128;
 
 // group of a field: 2 * dtype + (3D)
 constexpr int kGroups = 4;
-enum { PH_MM = 0, PH_Q = 1, PH_T = 2, PH_C = 3, PH_N = 4 };
+enum { PH_MM = 0, PH_T = 1, PH_C = 2, PH_N = 3 };
 
 // Counters at the start of a batch workspace (cleared with the rest of the
 // zeroed prefix at the start of every batch).
@@ -115,7 +114,7 @@ struct Job {
   uint32_t* parts;
   int64_t* part;      // min/max partials
   uint64_t* offsets;  // record offsets (decompress)
-  uint32_t mm0, q0, t0, c0;
+  uint32_t mm0, t0, c0;
 };
 
 // Result of one field, read back by the host after the batch.
@@ -163,8 +162,6 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
                          int nblocks, Params* prm, uint8_t* stream,
                          size_t cap, int ndim, const int64_t* dims,
                          hipStream_t s);
-hipError_t launch_quant(int dtype, const void* x, uint32_t n, Params* prm, void* bins,
-                        int nblocks, hipStream_t s);
 hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
                         uint32_t* counters, hipStream_t s);
@@ -193,8 +190,6 @@ hipError_t launch_minmax_p(int dtype, const BatchDesc* bd, const Job* jobs, int 
                            hipStream_t s);
 hipError_t launch_params_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
                            hipStream_t s);
-hipError_t launch_quant_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
-                          hipStream_t s);
 hipError_t launch_tile0_p(int group, const BatchDesc* bd, const Job* jobs, int grid,
                           hipStream_t s);
 hipError_t launch_repair_p(const BatchDesc* bd, const Job* jobs, uint32_t sweep, int grid,
@@ -214,8 +209,6 @@ hipError_t launch_minmax_d(int dtype, const BatchDesc* bd, const Job* jobs, uint
                            hipStream_t s);
 hipError_t launch_params_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t njobs,
                            hipStream_t s);
-hipError_t launch_quant_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
-                          hipStream_t s);
 hipError_t launch_tile0_d(int group, const BatchDesc* bd, const Job* jobs, uint32_t items,
                           hipStream_t s);
 hipError_t launch_repair_d(const BatchDesc* bd, const Job* jobs, uint32_t sweep, uint32_t tiles,
@@ -230,7 +223,7 @@ hipError_t launch_verify(int dtype, const void* x, const void* y, Box box, doubl
                          unsigned long long* out, int blocks, hipStream_t s);
 
 // Resident blocks per CU of each persistent batch kernel (occupancy query).
-enum { PK_ZERO, PK_MINMAX, PK_PARAMS, PK_QUANT, PK_TILE0, PK_REPAIR, PK_ENCODE, PK_DHEAD,
+enum { PK_ZERO, PK_MINMAX, PK_PARAMS, PK_TILE0, PK_REPAIR, PK_ENCODE, PK_DHEAD,
        PK_DECODE, PK_COUNT };
 int batch_blocks_per_cu(int kernel);
 int codec_blocks_per_cu(int kernel);

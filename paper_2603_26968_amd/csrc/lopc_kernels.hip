@@ -161,51 +161,6 @@ __global__ __launch_bounds__(kThreads) void k_params(
 }
 
 
-// ------------------------------------------------------------------ a1
-// Quantize every point once (Sec. IV-A): 16-byte loads and stores.
-template <int K>
-__device__ __forceinline__ void quant_body(const typename Traits<K>::Raw* __restrict__ x, uint32_t n,
-                           Params* prm, typename Traits<K>::Bin* __restrict__ bins,
-                           uint32_t blk, uint32_t nblk) {
-  using Tr = Traits<K>;
-  using Raw = typename Tr::Raw;
-  using Bin = typename Tr::Bin;
-  constexpr int V = 16 / K;  // values per 16-byte vector
-  const double inv = prm->inv;
-  bool bad_v = false, bad_r = false;
-  const uint32_t nv = n / V;
-  for (uint32_t i = blk * kThreads + threadIdx.x; i < nv; i += nblk * kThreads) {
-    Raw u[V];
-    Bin b[V];
-    *(uint4*)u = ((const uint4*)x)[i];
-#pragma unroll
-    for (int k = 0; k < V; ++k) {
-      bad_v |= !Tr::finite(u[k]);
-      int64_t q = Tr::q(Tr::to_double(u[k]), inv);
-      bad_r |= q > Tr::kBinLimit || q < -Tr::kBinLimit;
-      b[k] = (Bin)q;
-    }
-    ((uint4*)bins)[i] = *(const uint4*)b;
-  }
-  for (uint32_t i = nv * V + blk * kThreads + threadIdx.x; i < n; i += nblk * kThreads) {
-    Raw u = x[i];
-    bad_v |= !Tr::finite(u);
-    int64_t q = Tr::q(Tr::to_double(u), inv);
-    bad_r |= q > Tr::kBinLimit || q < -Tr::kBinLimit;
-    bins[i] = (Bin)q;
-  }
-  if (bad_v) set_status(prm, ST_NONFINITE);
-  if (bad_r) set_status(prm, ST_RANGE);
-}
-
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_quant(
-    const typename Traits<K>::Raw* __restrict__ x, uint32_t n, Params* prm,
-    typename Traits<K>::Bin* __restrict__ bins) {
-  quant_body<K>(x, n, prm, bins, blockIdx.x, gridDim.x);
-}
-
-
 // ------------------------------------------------------------------ a3
 // Tiles of the subbin repair.  A workgroup owns a TZ x TY x TX tile and keeps
 // the subbins of the tile plus a one-point halo in LDS.  It relaxes them in
@@ -620,19 +575,6 @@ __global__ __launch_bounds__(kThreads) void k_params_p(const BatchDesc* bd, cons
   }
 }
 
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_quant_p(const BatchDesc* bd, const Job* jobs) {
-  constexpr int g0 = K == 4 ? 0 : 2;
-  const uint32_t i1 = bd->item0[PH_Q][g0 + 2];
-  const int j0 = (int)bd->job0[g0], j1 = (int)bd->job0[g0 + 2];
-  for (uint32_t it = bd->item0[PH_Q][g0] + blockIdx.x; it < i1; it += gridDim.x) {
-    const Job& J = jobs[find_job<&Job::q0>(jobs, j0, j1, it)];
-    quant_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.prm,
-                  (typename Traits<K>::Bin*)J.bins, it - J.q0,
-                  (J.box.n + kQuantSpan - 1) / kQuantSpan);
-  }
-}
-
 template <int K, int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_tile0_p(const BatchDesc* bd, const Job* jobs,
                                                       int g) {
@@ -700,16 +642,6 @@ __global__ __launch_bounds__(kThreads) void k_params_d(const BatchDesc* bd, cons
                  J.dims[0], J.dims[1], J.ndim == 3 ? J.dims[2] : 1);
 }
 
-template <int K>
-__global__ __launch_bounds__(kThreads) void k_quant_d(const BatchDesc* bd, const Job* jobs) {
-  constexpr int g0 = K == 4 ? 0 : 2;
-  const uint32_t it = bd->item0[PH_Q][g0] + blockIdx.x;
-  const Job& J = jobs[find_job<&Job::q0>(jobs, (int)bd->job0[g0], (int)bd->job0[g0 + 2], it)];
-  quant_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.prm,
-                (typename Traits<K>::Bin*)J.bins, it - J.q0,
-                (J.box.n + kQuantSpan - 1) / kQuantSpan);
-}
-
 template <int K, int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_tile0_d(const BatchDesc* bd, const Job* jobs,
                                                       int g) {
@@ -764,15 +696,6 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
   else
     k_params<8><<<1, kThreads, 0, s>>>(mode, eb, (const int64_t*)part, nblocks, prm,
                                        stream, cap, ndim, dims[0], dims[1], d2);
-  return hipGetLastError();
-}
-
-hipError_t launch_quant(int dtype, const void* x, uint32_t n, Params* prm, void* bins,
-                        int nblocks, hipStream_t s) {
-  if (dtype == 0)
-    k_quant<4><<<nblocks, kThreads, 0, s>>>((const uint32_t*)x, n, prm, (int32_t*)bins);
-  else
-    k_quant<8><<<nblocks, kThreads, 0, s>>>((const uint64_t*)x, n, prm, (int64_t*)bins);
   return hipGetLastError();
 }
 
@@ -833,13 +756,6 @@ hipError_t launch_params_p(int dtype, const BatchDesc* bd, const Job* jobs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_quant_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
-                          hipStream_t s) {
-  if (dtype == 0) k_quant_p<4><<<grid, kThreads, 0, s>>>(bd, jobs);
-  else k_quant_p<8><<<grid, kThreads, 0, s>>>(bd, jobs);
-  return hipGetLastError();
-}
-
 hipError_t launch_tile0_p(int group, const BatchDesc* bd, const Job* jobs, int grid,
                           hipStream_t s) {
   switch (group) {
@@ -873,14 +789,6 @@ hipError_t launch_params_d(int dtype, const BatchDesc* bd, const Job* jobs, uint
   return hipGetLastError();
 }
 
-hipError_t launch_quant_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
-                          hipStream_t s) {
-  if (!items) return hipSuccess;
-  if (dtype == 0) k_quant_d<4><<<items, kThreads, 0, s>>>(bd, jobs);
-  else k_quant_d<8><<<items, kThreads, 0, s>>>(bd, jobs);
-  return hipGetLastError();
-}
-
 hipError_t launch_tile0_d(int group, const BatchDesc* bd, const Job* jobs, uint32_t items,
                           hipStream_t s) {
   if (!items) return hipSuccess;
@@ -908,7 +816,6 @@ int batch_blocks_per_cu(int kernel) {
     case PK_ZERO: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_zero_p, kThreads, 0); break;
     case PK_MINMAX: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_minmax_p<8>, kThreads, 0); break;
     case PK_PARAMS: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_params_p<8>, kThreads, 0); break;
-    case PK_QUANT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_quant_p<8>, kThreads, 0); break;
     case PK_TILE0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_tile0_p<8, 8, 8, 32>, kThreads, 0); break;
     case PK_REPAIR: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_p, kThreads, 0); break;
     default: break;
