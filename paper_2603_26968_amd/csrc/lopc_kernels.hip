@@ -190,6 +190,16 @@ struct TileGeom {
   }
 };
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// index.  Give each XCD a contiguous range of tiles instead, so that tiles
+// that share halo data share an L2: workgroup b (of n) takes tile
+// start(b % 8) + b / 8.  A bijection of [0, n); only locality depends on
+// the dealing order.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
+  const uint32_t x = b & 7u, per = n >> 3, rem = n & 7u;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
 struct TileCoord {
   int tz, ty, tx, z0, y0, x0;
 };
@@ -426,7 +436,8 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
     uint32_t* counters) {
   TileCoord c;
   const bool edge = tile0_body<K, TZ, TY, TX>(x, box, tl, prm, bins, mask, sub, counters,
-                                              relax_total(counters), blockIdx.x, c);
+                                              relax_total(counters),
+                                              xcd_tile(blockIdx.x, gridDim.x), c);
   mark_neighbours(edge, c, tl, stamp, counters, 1);
 }
 
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_repair(
     uint32_t sweep) {
   TileCoord c;
   if (repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, relax_total(counters),
-                              sweep, blockIdx.x, c))
+                              sweep, xcd_tile(blockIdx.x, gridDim.x), c))
     mark_neighbours(true, c, tl, stamp, counters, sweep + 1);
 }
 
@@ -645,7 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_params_d(const BatchDesc* bd, cons
 template <int K, int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_tile0_d(const BatchDesc* bd, const Job* jobs,
                                                       int g) {
-  const uint32_t it = bd->item0[PH_T][g] + blockIdx.x;
+  const uint32_t it = bd->item0[PH_T][g] + xcd_tile(blockIdx.x, gridDim.x);
   const Job& J = jobs[find_job<&Job::t0>(jobs, (int)bd->job0[g], (int)bd->job0[g + 1], it)];
   TileCoord c;
   const bool edge = tile0_body<K, TZ, TY, TX>(
