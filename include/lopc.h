@@ -257,17 +257,24 @@ const char* lopc_strerror(int status);
  * every call synchronise after each launch so that a failure names its kernel. */
 const char* lopc_ctx_last_hip_error(lopc_ctx* ctx, int* code);
 
-/* Phase timing (for benchmarks).  When enabled, each compress/decompress call
- * records HIP events on its stream between its phases and, after its final
- * synchronisation, stores the elapsed milliseconds of each phase:
- *   LOPC_PHASE_RANGE    compress: NOA min/max + error parameters
- *   LOPC_PHASE_QUANT    compress: quantize + order mask
+/* Phase timing (for benchmarks).  `phases` is a bit mask over the phases
+ * below (1 << LOPC_PHASE_x; LOPC_TIMING_ALL: every phase; 0: off).  In each
+ * compress/decompress call the first kernel of a timed phase records its
+ * start and the last its end in HIP events, taken from the dispatches
+ * themselves; a timed kernel still delays the next launch by a few
+ * microseconds, so time only the phases needed.  After its final
+ * synchronisation the call stores the elapsed milliseconds of each timed
+ * phase (0 for the others):
+ *   LOPC_PHASE_RANGE    compress: NOA min/max (with the workspace clear) +
+ *                       error parameters
+ *   LOPC_PHASE_QUANT    compress: quantize + order flags + first relaxation
  *   LOPC_PHASE_REPAIR   compress: all repair sweeps (host waits included)
  *   LOPC_PHASE_ENCODE   compress: chunk encoder + stream assembly
  *   LOPC_PHASE_OFFSETS  decompress: record offsets
  *   LOPC_PHASE_DECODE   decompress: chunk decoder + reconstruction
  * lopc_ctx_last_timings copies min(n, LOPC_PHASES) values of the most recent
- * call of each kind (unset phases are 0) and returns LOPC_OK. */
+ * call of each kind and returns LOPC_OK.  A mask with other bits set is
+ * LOPC_E_ARG. */
 enum {
   LOPC_PHASE_RANGE = 0,
   LOPC_PHASE_QUANT = 1,
@@ -275,9 +282,10 @@ enum {
   LOPC_PHASE_ENCODE = 3,
   LOPC_PHASE_OFFSETS = 4,
   LOPC_PHASE_DECODE = 5,
-  LOPC_PHASES = 6
+  LOPC_PHASES = 6,
+  LOPC_TIMING_ALL = (1 << LOPC_PHASES) - 1
 };
-int lopc_ctx_set_timing(lopc_ctx* ctx, int enable);
+int lopc_ctx_set_timing(lopc_ctx* ctx, int phases);
 int lopc_ctx_last_timings(lopc_ctx* ctx, double* h_ms, int n);
 
 #ifdef __cplusplus

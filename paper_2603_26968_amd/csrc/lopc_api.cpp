@@ -56,7 +56,7 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
     const char* v = std::getenv("LOPC_SYNC_CHECK");
     c->sync_check = v && v[0] == '1';
   }
-  for (int i = 0; i < 8; ++i) c->ev[i] = nullptr;
+  for (hipEvent_t& e : c->ev) e = nullptr;
   for (int i = 0; i < LOPC_PHASES; ++i) c->ms[i] = 0.0;
   c->use_graph = 1;
   c->graph_sweeps = 0;
@@ -75,18 +75,18 @@ void lopc_ctx_destroy(lopc_ctx* ctx) {
   if (ctx->h_plan) (void)hipHostFree(ctx->h_plan);
   if (ctx->h_back) (void)hipHostFree(ctx->h_back);
   if (ctx->h_prm) (void)hipHostFree(ctx->h_prm);
-  for (int i = 0; i < 8; ++i)
-    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  for (hipEvent_t e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
-int lopc_ctx_set_timing(lopc_ctx* ctx, int enable) {
-  if (!ctx) return LOPC_E_ARG;
-  if (enable && !ctx->ev[0]) {
+int lopc_ctx_set_timing(lopc_ctx* ctx, int phases) {
+  if (!ctx || (phases & ~LOPC_TIMING_ALL)) return LOPC_E_ARG;
+  if (phases && !ctx->ev[0]) {
     HIP_TRY(hipSetDevice(ctx->device));
-    for (int i = 0; i < 8; ++i) HIP_TRY(hipEventCreate(&ctx->ev[i]));
+    for (hipEvent_t& e : ctx->ev) HIP_TRY(hipEventCreate(&e));
   }
-  ctx->timing = enable ? 1 : 0;
+  ctx->timing = phases;
   return LOPC_OK;
 }
 
@@ -157,27 +157,28 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   uint32_t* sub = (uint32_t*)(ws + L.sub);
   uint32_t* stamp = (uint32_t*)(ws + L.stamp);
   uint32_t* counters = (uint32_t*)(ws + L.counters);
-  uint64_t* lookback = (uint64_t*)(ws + L.lookback);
+  uint64_t* offs = (uint64_t*)(ws + L.offs);
   const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
   const uint64_t nch = (s.n + W - 1) / W;
   Tiling tl = make_tiling(s.box);
 
-  HIP_CTX(ctx, mark(ctx, 0, hs));
-  HIP_CTX(ctx, hipMemsetAsync(ws, 0, L.zero_end, hs));
-
   int nblocks = (int)std::min<uint64_t>(kMinmaxBlocks, (s.n + 2047) / 2048);
   if (nblocks < 1) nblocks = 1;
+  // the zeroed prefix of the workspace is cleared by the range pass (NOA),
+  // else by a fill kernel
   if (mode == LOPC_EB_NOA)
     HIP_CTX(ctx, launch_minmax(dtype, d_field, (uint32_t)s.n, (double*)(ws + L.part),
-                               nblocks, prm, hs));
+                               nblocks, ws, L.zero_end, hs, ev_first(ctx, LOPC_PHASE_RANGE)));
+  else
+    HIP_CTX(ctx, launch_zero_n((uint32_t*)ws, L.zero_end / 4, hs,
+                               ev_first(ctx, LOPC_PHASE_RANGE)));
   HIP_CTX(ctx, launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
                              nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
-                             s.d, hs));
-  HIP_CTX(ctx, mark(ctx, 1, hs));
+                             s.d, hs, ev_last(ctx, LOPC_PHASE_RANGE)));
   // quantize, order flags and first relaxation, fused per tile
   HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
-                            (uint16_t*)(ws + L.mask), sub, stamp, counters, hs));
-  HIP_CTX(ctx, mark(ctx, 2, hs));
+                            (uint16_t*)(ws + L.mask), sub, stamp, counters, hs,
+                            ev_only(ctx, LOPC_PHASE_QUANT)));
 
   // repair sweeps (Alg. 1 loop at tile granularity).  The first group of K
   // sweeps (K from the previous call on this context) is enqueued together
@@ -189,14 +190,16 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   uint64_t sweeps = 1, active = tl.ntiles, relax_iters = 0;
   const uint32_t K = (uint32_t)ctx->sweep_hint;
   const size_t report = L.counters + kCounterWords * 4;  // Params + counters
-  for (uint32_t t = 1; t <= K; ++t)
+  for (uint32_t t = 1; t <= K; ++t) {
+    Ev e = t == 1 ? ev_first(ctx, LOPC_PHASE_REPAIR) : Ev{};
+    if (t == K) e.b = ev_last(ctx, LOPC_PHASE_REPAIR).b;
     HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
-                               counters, t, hs));
-  HIP_CTX(ctx, mark(ctx, 3, hs));
-  HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
-                             (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream, stream_cap,
-                             counters + 1 + ((K + 1) & 63), hs));
-  HIP_CTX(ctx, mark(ctx, 4, hs));
+                               counters, t, hs, e));
+  }
+  HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, (uint16_t*)(ws + L.mask),
+                             ws + L.tail, offs, (uint32_t*)(ws + L.parts), prm,
+                             (uint8_t*)d_stream, stream_cap, counters + 1 + ((K + 1) & 63), hs,
+                             ev_only(ctx, LOPC_PHASE_ENCODE)));
   if (h_stats)
     HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
   HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
@@ -239,7 +242,8 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     if (next + batch >= kMaxSweeps) return LOPC_E_INTERNAL;
     for (uint32_t b = 0; b < batch; ++b)
       HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
-                                 counters, next + b, hs));
+                                 counters, next + b, hs,
+                                 b + 1 == batch ? ev_last(ctx, LOPC_PHASE_REPAIR) : Ev{}));
     HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
     HIP_CTX(ctx, hipStreamSynchronize(hs));
   }
@@ -247,21 +251,17 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   ctx->sweep_hint = (int)std::min<uint64_t>(16, std::max<uint64_t>(2, sweeps));
   if (next > 1) {
     // the gated encoder did not run: encode now
-    HIP_CTX(ctx, mark(ctx, 3, hs));
-    HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, lookback,
+    HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub,
+                               (uint16_t*)(ws + L.mask), ws + L.tail, offs,
                                (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream, stream_cap,
-                               nullptr, hs));
-    HIP_CTX(ctx, mark(ctx, 4, hs));
+                               nullptr, hs, ev_only(ctx, LOPC_PHASE_ENCODE)));
     if (h_stats)
       HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
+    HIP_CTX(ctx, hipStreamSynchronize(hs));
   }
-  HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
-  HIP_CTX(ctx, hipStreamSynchronize(hs));
   if (ctx->timing) {
-    ctx->ms[LOPC_PHASE_RANGE] = span(ctx, 0, 1);
-    ctx->ms[LOPC_PHASE_QUANT] = span(ctx, 1, 2);
-    ctx->ms[LOPC_PHASE_REPAIR] = span(ctx, 2, 3);
-    ctx->ms[LOPC_PHASE_ENCODE] = span(ctx, 3, 4);
+    for (int p = LOPC_PHASE_RANGE; p <= LOPC_PHASE_ENCODE; ++p) ctx->ms[p] = phase_ms(ctx, p);
   }
   const Params& hp = *ctx->h_prm;
   *h_stream_size = (size_t)hp.stream_size;
@@ -331,18 +331,15 @@ static int decompress_core(lopc_ctx* ctx, const uint8_t* hdr, const void* d_stre
   uint8_t* ws = (uint8_t*)d_ws;
   Params* prm = (Params*)ws;
   uint64_t* offsets = (uint64_t*)(ws + align256(sizeof(Params)));
-  HIP_CTX(ctx, mark(ctx, 5, hs));
   HIP_CTX(ctx, launch_offsets((const uint8_t*)d_stream, (uint32_t)nch,
-                              stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs));
-  HIP_CTX(ctx, mark(ctx, 6, hs));
+                              stream_size - kHeaderBytes - 4 * nch, offsets, prm, hs,
+                              ev_only(ctx, LOPC_PHASE_OFFSETS)));
   HIP_CTX(ctx, launch_decode(dtype, (const uint8_t*)d_stream, (uint32_t)s.n, offsets,
-                             prm, d_field, hs));
-  HIP_CTX(ctx, mark(ctx, 7, hs));
+                             prm, d_field, hs, ev_only(ctx, LOPC_PHASE_DECODE)));
   HIP_CTX(ctx, hipMemcpyAsync(&ctx->h_prm->status, &prm->status, 4, hipMemcpyDeviceToHost, hs));
   HIP_CTX(ctx, hipStreamSynchronize(hs));
   if (ctx->timing) {
-    ctx->ms[LOPC_PHASE_OFFSETS] = span(ctx, 5, 6);
-    ctx->ms[LOPC_PHASE_DECODE] = span(ctx, 6, 7);
+    for (int p = LOPC_PHASE_OFFSETS; p <= LOPC_PHASE_DECODE; ++p) ctx->ms[p] = phase_ms(ctx, p);
   }
   return status_code(ctx->h_prm->status);
 }

@@ -8,13 +8,17 @@
 // (RZE_4) or 1 (RZE_8) bitmap bits, so bitmaps, counts and payload offsets
 // come from wave scans over units instead of per-byte work.
 //
-// Chunk offsets in the stream come from a decoupled look-back over a
-// ticket-ordered chunk queue (a workgroup only waits for chunks that started
-// before it).  A look-back word packs its state and size into 64 bits, so it
-// carries no other data and relaxed device-scope atomics suffice: release or
-// acquire at that scope would write back / invalidate the per-XCD L2 on every
-// publication.
+// Chunk offsets in the stream.  A single field: every workgroup parks its
+// record in rows of the workspace that its own chunk has finished with, a
+// one-workgroup scan turns the record sizes into offsets and a placement
+// kernel copies the records into the stream, so no workgroup waits for
+// another.  Batches: a decoupled look-back over a ticket-ordered chunk queue
+// (a workgroup only waits for chunks that started before it).  A look-back
+// word packs its state and size into 64 bits, so it carries no other data
+// and relaxed device-scope atomics suffice: release or acquire at that scope
+// would write back / invalidate the per-XCD L2 on every publication.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -485,12 +489,46 @@ __device__ __forceinline__ uint8_t record_byte(uint32_t r, const uint8_t* hdr,
   return r < slen ? sp[r] : (uint8_t)0;
 }
 
-// Encodes chunk c of a field and writes its record (Sec. III-B, IV-C).
-template <int K>
+// Where the record of chunk c of a single field waits for its offset: the
+// chunk's rows of the bins, subbins and order-flag arrays, in that order
+// (free once the encoder has read the chunk; nothing reads them after it),
+// and a separate place for the last chunk, whose rows may be short.  The
+// rows hold W*sizeof(Bin) + 4W + 2W bytes: 40 KiB for binary32, 28 KiB for
+// binary64.  A record is at most 16 + (bins part) + (subbin part) bytes with
+// each part at most the bit-plane bytes of its stage input: 16 + 16 KiB +
+// 16 KiB for binary32; for binary64 the subbins (below 2^32) fill at most 32
+// of the 64 planes, so that part stays under 8 KiB plus its bitmaps, about
+// 24.3 KiB in all.  The encoder still checks the room.
+struct RecordSlots {
+  uint8_t* seg[3];   // chunk 0's rows
+  uint32_t len[3];   // bytes of one chunk's rows in each
+  uint8_t* tail;     // the last chunk's place
+  uint32_t tail_len;
+};
+
+__device__ __forceinline__ uint32_t* slot_word(const RecordSlots& S, uint32_t c, bool last,
+                                               uint32_t q) {
+  uint32_t r = 4 * q;
+  if (last) return (uint32_t*)(S.tail + r);
+  if (r < S.len[0]) return (uint32_t*)(S.seg[0] + (size_t)c * S.len[0] + r);
+  r -= S.len[0];
+  if (r < S.len[1]) return (uint32_t*)(S.seg[1] + (size_t)c * S.len[1] + r);
+  r -= S.len[1];
+  return (uint32_t*)(S.seg[2] + (size_t)c * S.len[2] + r);
+}
+
+__device__ __forceinline__ uint32_t record_size(uint32_t blen, uint32_t slen) {
+  return (kRecordHeaderBytes + blen + slen + 3) & ~3u;
+}
+
+// Encodes chunk c of a field (Sec. III-B, IV-C).  kSlot: parks the record
+// in its slot (single field; offsets and placement follow in their own
+// kernels); else writes it into the stream after a decoupled look-back.
+template <int K, bool kSlot>
 __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
                             const uint32_t* __restrict__ sub, uint64_t* lookback,
                             uint32_t* parts, Params* prm, uint8_t* stream, uint64_t cap,
-                            uint32_t nch, uint32_t c) {
+                            uint32_t nch, uint32_t c, const RecordSlots& S) {
   using Tr = Traits<K>;
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
@@ -556,7 +594,7 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
   __syncthreads();
   const uint32_t slen = rze_encode<1>(X, smid, (smid + 7) / 8, (uint8_t*)U, sc, pt_s2);
 
-  const uint32_t size = (kRecordHeaderBytes + blen + slen + 3) & ~3u;
+  const uint32_t size = record_size(blen, slen);
   if (threadIdx.x == 0) {
     hdr[0] = (uint8_t)pt_b;
     hdr[1] = (uint8_t)(pt_s1 | (pt_s2 << 1));
@@ -565,6 +603,31 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
     put_bytes(hdr + 4, blen, 4);
     put_bytes(hdr + 8, smid, 4);
     put_bytes(hdr + 12, slen, 4);
+  }
+  if constexpr (kSlot) {
+    if (threadIdx.x == 0) {
+      parts[2 * c] = blen;
+      parts[2 * c + 1] = slen;
+      if (kHeaderBytes + 4ull * c + 4 <= cap)
+        *(uint32_t*)(stream + kHeaderBytes + 4ull * c) = size;
+    }
+    __syncthreads();  // hdr
+    const bool last = c == nch - 1;
+    const uint32_t room = last ? S.tail_len : S.len[0] + S.len[1] + S.len[2];
+    if (size <= room) {
+      const uint8_t* bp = (const uint8_t*)B;
+      const uint8_t* sp = (const uint8_t*)U;
+      for (uint32_t q = threadIdx.x; q < size / 4; q += kCT) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          w |= (uint32_t)record_byte(4 * q + b, hdr, bp, blen, sp, slen) << (8 * b);
+        *slot_word(S, c, last, q) = w;
+      }
+    } else if (threadIdx.x == 0) {
+      set_status(prm, ST_INTERNAL);
+    }
+    return;
   }
 
   // decoupled look-back for this chunk's offset in the stream body: wave 0
@@ -636,22 +699,87 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
   }
 }
 
-// Single field: chunks are taken in ticket order (the look-back of a chunk
-// only waits for chunks whose workgroups already run).  Skipped entirely
-// when gate is given and *gate != 0 (the repair sweeps enqueued before it
-// have not reached the fixed point; the host then sweeps on and encodes).
+// Single field, one workgroup per chunk: encode and park the record.  This
+// kernel and the two after it are skipped entirely when gate is given and
+// *gate != 0 (the repair sweeps enqueued before them have not reached the
+// fixed point; the host then sweeps on and encodes).
 template <int K>
 __global__ __launch_bounds__(kCT) void k_encode(
     uint32_t n, const typename Traits<K>::Bin* __restrict__ bins,
-    const uint32_t* __restrict__ sub, uint64_t* lookback, uint32_t* parts,
-    Params* prm, uint8_t* stream, uint64_t cap, uint32_t nch, const uint32_t* gate) {
-  __shared__ uint32_t s_chunk;
+    const uint32_t* __restrict__ sub, uint32_t* parts, Params* prm, uint8_t* stream,
+    uint64_t cap, uint32_t nch, RecordSlots S, const uint32_t* gate) {
   if (gate && *gate) return;
-  if (threadIdx.x == 0) s_chunk = atomicAdd(&prm->ticket, 1u);
-  __syncthreads();
-  const uint32_t c = s_chunk;
-  if (c >= nch) return;
-  encode_body<K>(n, bins, sub, lookback, parts, prm, stream, cap, nch, c);
+  encode_body<K, true>(n, bins, sub, nullptr, parts, prm, stream, cap, nch, blockIdx.x, S);
+}
+
+// Single field: exclusive offsets of the records in the stream body from
+// their part sizes, 4096 chunks per pass (four per thread, read as two
+// 16-byte vectors); the stream size.
+constexpr int kOT = 1024;  // threads of the offset scan
+__global__ __launch_bounds__(kOT) void k_record_offsets(const uint32_t* parts, uint32_t nch,
+                                                        uint64_t* offs, Params* prm,
+                                                        const uint32_t* gate) {
+  if (gate && *gate) return;
+  __shared__ uint64_t sh[kOT / 64 + 1];
+  uint64_t carry = 0;
+  for (uint32_t t0 = 0; t0 < nch; t0 += 4 * kOT) {
+    const uint32_t i = t0 + 4 * threadIdx.x;
+    uint32_t sz[4];
+    if (i + 3 < nch) {
+      const uint4 a = ((const uint4*)parts)[i / 2], b = ((const uint4*)parts)[i / 2 + 1];
+      sz[0] = record_size(a.x, a.y);
+      sz[1] = record_size(a.z, a.w);
+      sz[2] = record_size(b.x, b.y);
+      sz[3] = record_size(b.z, b.w);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        sz[k] = i + k < nch ? record_size(parts[2 * (i + k)], parts[2 * (i + k) + 1]) : 0u;
+    }
+    const uint64_t sum = (uint64_t)sz[0] + sz[1] + sz[2] + sz[3];
+    uint64_t total;
+    uint64_t off = carry + block_excl_scan<uint64_t, kOT / 64>(sum, sh, total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i + k < nch) offs[i + k] = off;
+      off += sz[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) prm->stream_size = kHeaderBytes + 4ull * nch + carry;
+}
+
+// Single field, one workgroup per chunk: copy the parked record to its
+// offset (ST_CAPACITY when the stream buffer is too short for it).
+__global__ __launch_bounds__(kThreads) void k_place(const uint32_t* parts, const uint64_t* offs,
+                                                    uint32_t nch, RecordSlots S, Params* prm,
+                                                    uint8_t* stream, uint64_t cap,
+                                                    const uint32_t* gate) {
+  if (gate && *gate) return;
+  const uint32_t c = blockIdx.x;
+  const uint32_t size = record_size(parts[2 * c], parts[2 * c + 1]);
+  const uint64_t dst = kHeaderBytes + 4ull * nch + offs[c];
+  const bool last = c == nch - 1;
+  if (size > (last ? S.tail_len : S.len[0] + S.len[1] + S.len[2])) return;  // flagged already
+  if (dst + size > cap) {
+    if (threadIdx.x == 0) set_status(prm, ST_CAPACITY);
+    return;
+  }
+  uint32_t* out = (uint32_t*)(stream + dst);
+  const uint32_t nw = size / 4;
+  for (uint32_t q0 = 0; q0 < nw; q0 += 4 * kThreads) {
+    uint32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t q = q0 + k * kThreads + threadIdx.x;
+      v[k] = q < nw ? *slot_word(S, c, last, q) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t q = q0 + k * kThreads + threadIdx.x;
+      if (q < nw) out[q] = v[k];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ decoder
@@ -988,8 +1116,8 @@ __global__ __launch_bounds__(kCT) void k_encode_p(const BatchDesc* bd, const Job
     const uint32_t t = s_t;
     if (t >= i1) break;
     const Job& J = jobs[find_job<&Job::c0>(jobs, j0, j1, t)];
-    encode_body<K>(J.box.n, (const typename Traits<K>::Bin*)J.bins, J.sub, J.lookback,
-                   J.parts, J.prm, J.stream, J.cap, J.nch, t - J.c0);
+    encode_body<K, false>(J.box.n, (const typename Traits<K>::Bin*)J.bins, J.sub, J.lookback,
+                          J.parts, J.prm, J.stream, J.cap, J.nch, t - J.c0, RecordSlots{});
   }
 }
 
@@ -1103,8 +1231,8 @@ __global__ __launch_bounds__(kCT) void k_encode_d(const BatchDesc* bd, const Job
   __syncthreads();
   const uint32_t t = s_t;
   const Job& J = jobs[find_job<&Job::c0>(jobs, (int)bd->job0[g0], (int)bd->job0[g0 + 2], t)];
-  encode_body<K>(J.box.n, (const typename Traits<K>::Bin*)J.bins, J.sub, J.lookback, J.parts,
-                 J.prm, J.stream, J.cap, J.nch, t - J.c0);
+  encode_body<K, false>(J.box.n, (const typename Traits<K>::Bin*)J.bins, J.sub, J.lookback,
+                        J.parts, J.prm, J.stream, J.cap, J.nch, t - J.c0, RecordSlots{});
 }
 
 template <int K>
@@ -1119,18 +1247,34 @@ __global__ __launch_bounds__(kCT, 6) void k_decode_d(const BatchDesc* bd, const 
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_encode(int dtype, uint32_t n, const void* bins,
-                         const uint32_t* sub, uint64_t* lookback, uint32_t* parts,
+hipError_t launch_encode(int dtype, uint32_t n, const void* bins, uint32_t* sub,
+                         uint16_t* mask, uint8_t* tail, uint64_t* offs, uint32_t* parts,
                          Params* prm, uint8_t* stream, size_t cap, const uint32_t* gate,
-                         hipStream_t s) {
-  uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
-  uint32_t nch = (n + W - 1) / W;
+                         hipStream_t s, Ev ev) {
+  const uint32_t K = dtype == 0 ? 4 : 8;
+  const uint32_t W = kChunkBytes / K;
+  const uint32_t nch = (n + W - 1) / W;
+  RecordSlots S;
+  S.seg[0] = (uint8_t*)bins;
+  S.seg[1] = (uint8_t*)sub;
+  S.seg[2] = (uint8_t*)mask;
+  S.len[0] = W * K;
+  S.len[1] = W * 4;
+  S.len[2] = W * 2;
+  S.tail = tail;
+  S.tail_len = kRecordTailBytes;
   if (dtype == 0)
-    k_encode<4><<<nch, kCT, 0, s>>>(n, (const int32_t*)bins, sub, lookback, parts, prm,
-                                    stream, cap, nch, gate);
+    hipExtLaunchKernelGGL(k_encode<4>, dim3(nch), dim3(kCT), 0, s, ev.a, nullptr, 0, n,
+                          (const int32_t*)bins, (const uint32_t*)sub, parts, prm, stream,
+                          (uint64_t)cap, nch, S, gate);
   else
-    k_encode<8><<<nch, kCT, 0, s>>>(n, (const int64_t*)bins, sub, lookback, parts, prm,
-                                    stream, cap, nch, gate);
+    hipExtLaunchKernelGGL(k_encode<8>, dim3(nch), dim3(kCT), 0, s, ev.a, nullptr, 0, n,
+                          (const int64_t*)bins, (const uint32_t*)sub, parts, prm, stream,
+                          (uint64_t)cap, nch, S, gate);
+  k_record_offsets<<<1, kOT, 0, s>>>(parts, nch, offs, prm, gate);
+  hipExtLaunchKernelGGL(k_place, dim3(nch), dim3(kThreads), 0, s, nullptr, ev.b, 0,
+                        (const uint32_t*)parts, (const uint64_t*)offs, nch, S, prm, stream,
+                        (uint64_t)cap, gate);
   return hipGetLastError();
 }
 
@@ -1142,20 +1286,23 @@ hipError_t launch_sum_parts(const uint32_t* parts, uint32_t nch, Params* prm,
 
 hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
                           uint64_t body_bytes, uint64_t* offsets, Params* prm,
-                          hipStream_t s) {
-  k_offsets<<<1, kThreads, 0, s>>>(stream, nch, body_bytes, offsets, prm);
+                          hipStream_t s, Ev ev) {
+  hipExtLaunchKernelGGL(k_offsets, dim3(1), dim3(kThreads), 0, s, ev.a, ev.b, 0, stream, nch,
+                        body_bytes, offsets, prm);
   return hipGetLastError();
 }
 
 hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
                          const uint64_t* offsets, Params* prm, void* field,
-                         hipStream_t s) {
+                         hipStream_t s, Ev ev) {
   uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
   uint32_t nch = (n + W - 1) / W;
   if (dtype == 0)
-    k_decode<4><<<nch, kCT, 0, s>>>(stream, n, offsets, prm, (uint32_t*)field);
+    hipExtLaunchKernelGGL(k_decode<4>, dim3(nch), dim3(kCT), 0, s, ev.a, ev.b, 0, stream, n,
+                          offsets, prm, (uint32_t*)field);
   else
-    k_decode<8><<<nch, kCT, 0, s>>>(stream, n, offsets, prm, (uint64_t*)field);
+    hipExtLaunchKernelGGL(k_decode<8>, dim3(nch), dim3(kCT), 0, s, ev.a, ev.b, 0, stream, n,
+                          offsets, prm, (uint64_t*)field);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ struct lopc_ctx {
   int sync_check;  // LOPC_SYNC_CHECK=1: synchronise after every launch
   // phase timing
   int timing;
-  hipEvent_t ev[8];
+  hipEvent_t ev[2 * LOPC_PHASES];  // per phase: first kernel's start, last kernel's end
   double ms[LOPC_PHASES];
   int sweep_hint;      // single field: repair sweeps enqueued before the first read
   // batches
@@ -120,8 +120,8 @@ inline Tiling make_tiling(const Box& b) {
 }
 
 struct CompressLayout {
-  size_t prm, counters, stamp, lookback, parts, zero_end;  // zeroed prefix
-  size_t part, bins, mask, sub, total;
+  size_t prm, counters, stamp, zero_end;  // zeroed prefix
+  size_t offs, parts, part, bins, mask, sub, tail, total;
 };
 
 // repair counters (kCounterWords words): [0] internal error flag,
@@ -138,13 +138,14 @@ inline CompressLayout compress_layout(const Shape& s, int dtype) {
   L.prm = o; o += align256(sizeof(Params));
   L.counters = o; o += align256(kCounterWords * 4);
   L.stamp = o; o += align256((size_t)t.ntiles * 4);
-  L.lookback = o; o += align256(nch * 8);
-  L.parts = o; o += align256(nch * 8);
   L.zero_end = o;
+  L.offs = o; o += align256(nch * 8);
+  L.parts = o; o += align256(nch * 8);
   L.part = o; o += align256(16 * kMinmaxBlocks);
   L.bins = o; o += align256(s.n * k);
   L.mask = o; o += align256(s.n * 2);
   L.sub = o; o += align256(s.n * 4);
+  L.tail = o; o += align256(kRecordTailBytes);
   L.total = o;
   return L;
 }
@@ -183,14 +184,19 @@ inline int status_code(uint32_t st) {
     }                                                                 \
   } while (0)
 
-// event i of the current call (no-op unless timing is on)
-inline hipError_t mark(lopc_ctx* c, int i, hipStream_t s) {
-  return c->timing ? hipEventRecord(c->ev[i], s) : hipSuccess;
+// timing events for the kernels of phase p (none unless timing is on):
+// the first kernel of the phase records its start, the last its end
+inline bool timed(const lopc_ctx* c, int p) { return (c->timing >> p) & 1; }
+inline Ev ev_first(lopc_ctx* c, int p) { return timed(c, p) ? Ev{c->ev[2 * p], nullptr} : Ev{}; }
+inline Ev ev_last(lopc_ctx* c, int p) { return timed(c, p) ? Ev{nullptr, c->ev[2 * p + 1]} : Ev{}; }
+inline Ev ev_only(lopc_ctx* c, int p) {
+  return timed(c, p) ? Ev{c->ev[2 * p], c->ev[2 * p + 1]} : Ev{};
 }
-// elapsed ms between events a and b (after the stream has synchronised)
-inline double span(lopc_ctx* c, int a, int b) {
+// ms of phase p (after the stream has drained; 0 unless timed)
+inline double phase_ms(lopc_ctx* c, int p) {
   float ms = 0.f;
-  if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.0;
+  if (!timed(c, p)) return 0.0;
+  if (hipEventElapsedTime(&ms, c->ev[2 * p], c->ev[2 * p + 1]) != hipSuccess) return 0.0;
   return (double)ms;
 }
 

@@ -11,6 +11,9 @@ namespace lopc {
 constexpr uint32_t kChunkBytes = 16384;  // 16 kB chunks (Sec. III-B / IV-C)
 constexpr uint32_t kHeaderBytes = 64;
 constexpr uint32_t kRecordHeaderBytes = 16;
+// room for the largest record of a chunk: header + two parts of at most the
+// chunk's bytes each
+constexpr uint32_t kRecordTailBytes = kRecordHeaderBytes + 2 * kChunkBytes;
 constexpr uint32_t kMagic = 0x43504F4Cu;  // "LOPC"
 constexpr uint32_t kVersion = 1;
 constexpr uint64_t kMaxPoints = 0xFFFFFFFFull;  // subbins kept in 32 bits
@@ -154,38 +157,51 @@ __device__ __forceinline__ int find_job(const Job* jobs, int lo, int hi, uint32_
   return lo;
 }
 
+// Timing events of one launch: a receives the kernel's start, b its end,
+// both taken from the dispatch itself (hipExtLaunchKernel), so timing adds
+// no packet between kernels; null = not recorded.
+struct Ev {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
 // Launchers (lopc_kernels.hip).  All enqueue on `s` and return the HIP
-// status of the last launch.
+// status of the last launch.  launch_minmax also clears zero_bytes (a
+// multiple of 16) at zero.
 hipError_t launch_minmax(int dtype, const void* x, uint32_t n, double* part,
-                         int nblocks, Params* prm, hipStream_t s);
+                         int nblocks, void* zero, size_t zero_bytes, hipStream_t s, Ev ev = {});
 hipError_t launch_params(int dtype, int mode, double eb, const double* part,
                          int nblocks, Params* prm, uint8_t* stream,
                          size_t cap, int ndim, const int64_t* dims,
-                         hipStream_t s);
+                         hipStream_t s, Ev ev = {});
 hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
-                        uint32_t* counters, hipStream_t s);
+                        uint32_t* counters, hipStream_t s, Ev ev = {});
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask,
                          uint32_t* sub, uint32_t* stamp, uint32_t* counters,
-                         uint32_t sweep, hipStream_t s);
-hipError_t launch_encode(int dtype, uint32_t n, const void* bins,
-                         const uint32_t* sub, uint64_t* lookback,
-                         uint32_t* parts, Params* prm, uint8_t* stream,
-                         size_t cap, const uint32_t* gate, hipStream_t s);
+                         uint32_t sweep, hipStream_t s, Ev ev = {});
+// Encoder of a single field: encodes every chunk, parking its record in the
+// chunk's rows of bins / sub / mask (which it overwrites) or, for the last
+// chunk, in tail (kRecordTailBytes); then the record offsets (into offs, one
+// per chunk) and the placement into the stream.  Ev: start of the first
+// kernel, end of the last.
+hipError_t launch_encode(int dtype, uint32_t n, const void* bins, uint32_t* sub,
+                         uint16_t* mask, uint8_t* tail, uint64_t* offs, uint32_t* parts,
+                         Params* prm, uint8_t* stream, size_t cap, const uint32_t* gate,
+                         hipStream_t s, Ev ev = {});
 hipError_t launch_sum_parts(const uint32_t* parts, uint32_t nch, Params* prm,
                             hipStream_t s);
 hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
                           uint64_t body_bytes, uint64_t* offsets,
-                          Params* prm, hipStream_t s);
+                          Params* prm, hipStream_t s, Ev ev = {});
 hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
                          const uint64_t* offsets, Params* prm, void* field,
-                         hipStream_t s);
+                         hipStream_t s, Ev ev = {});
 
 // Batch launchers (persistent grids; `grid` blocks drain the queue).  Every
 // launch reads the plan `bd` and the job table `jobs` that follows it.
 // `gate_sweep` > 0: skip unless no tile was listed for that sweep.
 hipError_t launch_zero_p(const BatchDesc* bd, int grid, hipStream_t s);
-hipError_t launch_zero_n(uint32_t* words, uint64_t nwords, hipStream_t s);
+hipError_t launch_zero_n(uint32_t* words, uint64_t nwords, hipStream_t s, Ev ev = {});
 hipError_t launch_minmax_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
                            hipStream_t s);
 hipError_t launch_params_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,

@@ -9,6 +9,7 @@
 // subbin raising Alg. 1 / Alg. 2 / Sec. IV-B; lossless stages Sec. III-B and
 // Sec. IV-C; decoding rule Sec. IV-E.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <algorithm>
@@ -22,16 +23,14 @@ namespace {
 // ------------------------------------------------------------------ a0
 template <int K>
 __device__ __forceinline__ void minmax_body(const typename Traits<K>::Raw* x, uint32_t n,
-                                            int64_t* part, Params* prm, uint32_t blk,
-                                            uint32_t nblk) {
+                                            int64_t* part, uint32_t blk, uint32_t nblk) {
   using Tr = Traits<K>;
   using Raw = typename Tr::Raw;
   constexpr int V = 16 / K;  // values per 16-byte vector
   constexpr int U = 4;       // vectors in flight per thread
+  // non-finite values are flagged by the tile pass, which sees every point
   int64_t lo = INT64_MAX, hi = INT64_MIN;
-  bool bad = false;
   auto take = [&](Raw u) {
-    bad |= !Tr::finite(u);
     const int64_t k = Tr::key(u);
     lo = k < lo ? k : lo;
     hi = k > hi ? k : hi;
@@ -54,7 +53,6 @@ __device__ __forceinline__ void minmax_body(const typename Traits<K>::Raw* x, ui
     for (int k = 0; k < V; ++k) take(u[k]);
   }
   for (uint32_t t = nv * V + blk * kThreads + threadIdx.x; t < n; t += stride) take(x[t]);
-  if (bad) set_status(prm, ST_NONFINITE);
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) {
     const int64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
@@ -79,8 +77,13 @@ __device__ __forceinline__ void minmax_body(const typename Traits<K>::Raw* x, ui
 
 template <int K>
 __global__ __launch_bounds__(kThreads) void k_minmax(
-    const typename Traits<K>::Raw* x, uint32_t n, int64_t* part, Params* prm) {
-  minmax_body<K>(x, n, part, prm, blockIdx.x, gridDim.x);
+    const typename Traits<K>::Raw* x, uint32_t n, int64_t* part, uint4* zero, uint32_t nzero) {
+  // the zeroed prefix of the workspace (Params, counters, stamps, look-back
+  // words), which no earlier work of the call touches, is cleared here
+  // rather than by a separate fill
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < nzero; i += gridDim.x * kThreads)
+    zero[i] = make_uint4(0, 0, 0, 0);
+  minmax_body<K>(x, n, part, blockIdx.x, gridDim.x);
 }
 
 
@@ -569,7 +572,7 @@ __global__ __launch_bounds__(kThreads) void k_minmax_p(const BatchDesc* bd, cons
   for (uint32_t it = bd->item0[PH_MM][g0] + blockIdx.x; it < i1; it += gridDim.x) {
     const Job& J = jobs[find_job<&Job::mm0>(jobs, j0, j1, it)];
     __syncthreads();
-    minmax_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.part, J.prm, it - J.mm0,
+    minmax_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.part, it - J.mm0,
                    (uint32_t)J.mm_blocks);
   }
 }
@@ -641,7 +644,7 @@ __global__ __launch_bounds__(kThreads) void k_minmax_d(const BatchDesc* bd, cons
   constexpr int g0 = K == 4 ? 0 : 2;
   const uint32_t it = bd->item0[PH_MM][g0] + blockIdx.x;
   const Job& J = jobs[find_job<&Job::mm0>(jobs, (int)bd->job0[g0], (int)bd->job0[g0 + 2], it)];
-  minmax_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.part, J.prm, it - J.mm0,
+  minmax_body<K>((const typename Traits<K>::Raw*)J.x, J.box.n, J.part, it - J.mm0,
                  (uint32_t)J.mm_blocks);
 }
 
@@ -689,55 +692,64 @@ __global__ __launch_bounds__(kThreads) void k_repair_d(const BatchDesc* bd, cons
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_minmax(int dtype, const void* x, uint32_t n, double* part,
-                         int nblocks, Params* prm, hipStream_t s) {
+                         int nblocks, void* zero, size_t zero_bytes, hipStream_t s, Ev ev) {
+  const uint32_t nz = (uint32_t)(zero_bytes / 16);
   if (dtype == 0)
-    k_minmax<4><<<nblocks, kThreads, 0, s>>>((const uint32_t*)x, n, (int64_t*)part, prm);
+    hipExtLaunchKernelGGL(k_minmax<4>, dim3(nblocks), dim3(kThreads), 0, s, ev.a, ev.b, 0,
+                          (const uint32_t*)x, n, (int64_t*)part, (uint4*)zero, nz);
   else
-    k_minmax<8><<<nblocks, kThreads, 0, s>>>((const uint64_t*)x, n, (int64_t*)part, prm);
+    hipExtLaunchKernelGGL(k_minmax<8>, dim3(nblocks), dim3(kThreads), 0, s, ev.a, ev.b, 0,
+                          (const uint64_t*)x, n, (int64_t*)part, (uint4*)zero, nz);
   return hipGetLastError();
 }
 
 hipError_t launch_params(int dtype, int mode, double eb, const double* part,
                          int nblocks, Params* prm, uint8_t* stream, size_t cap,
-                         int ndim, const int64_t* dims, hipStream_t s) {
+                         int ndim, const int64_t* dims, hipStream_t s, Ev ev) {
   int64_t d2 = ndim == 3 ? dims[2] : 1;
   if (dtype == 0)
-    k_params<4><<<1, kThreads, 0, s>>>(mode, eb, (const int64_t*)part, nblocks, prm,
-                                       stream, cap, ndim, dims[0], dims[1], d2);
+    hipExtLaunchKernelGGL(k_params<4>, dim3(1), dim3(kThreads), 0, s, ev.a, ev.b, 0, mode, eb,
+                          (const int64_t*)part, nblocks, prm, stream, (uint64_t)cap, ndim,
+                          dims[0], dims[1], d2);
   else
-    k_params<8><<<1, kThreads, 0, s>>>(mode, eb, (const int64_t*)part, nblocks, prm,
-                                       stream, cap, ndim, dims[0], dims[1], d2);
+    hipExtLaunchKernelGGL(k_params<8>, dim3(1), dim3(kThreads), 0, s, ev.a, ev.b, 0, mode, eb,
+                          (const int64_t*)part, nblocks, prm, stream, (uint64_t)cap, ndim,
+                          dims[0], dims[1], d2);
   return hipGetLastError();
 }
 
 hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
-                        uint32_t* counters, hipStream_t s) {
+                        uint32_t* counters, hipStream_t s, Ev ev) {
+  const dim3 g(t.ntiles), b(kThreads);
   if (t.tz == 1) {
     if (dtype == 0)
-      k_tile0<4, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
-                                                           (int32_t*)bins, mask, sub, stamp, counters);
+      hipExtLaunchKernelGGL(k_tile0<4, 1, 32, 64>, g, b, 0, s, ev.a, ev.b, 0, (const uint32_t*)x,
+                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters);
     else
-      k_tile0<8, 1, 32, 64><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
-                                                           (int64_t*)bins, mask, sub, stamp, counters);
+      hipExtLaunchKernelGGL(k_tile0<8, 1, 32, 64>, g, b, 0, s, ev.a, ev.b, 0, (const uint64_t*)x,
+                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters);
   } else {
     if (dtype == 0)
-      k_tile0<4, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint32_t*)x, box, t, prm,
-                                                          (int32_t*)bins, mask, sub, stamp, counters);
+      hipExtLaunchKernelGGL(k_tile0<4, 8, 8, 32>, g, b, 0, s, ev.a, ev.b, 0, (const uint32_t*)x,
+                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters);
     else
-      k_tile0<8, 8, 8, 32><<<t.ntiles, kThreads, 0, s>>>((const uint64_t*)x, box, t, prm,
-                                                          (int64_t*)bins, mask, sub, stamp, counters);
+      hipExtLaunchKernelGGL(k_tile0<8, 8, 8, 32>, g, b, 0, s, ev.a, ev.b, 0, (const uint64_t*)x,
+                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
                          uint32_t* stamp, uint32_t* counters, uint32_t sweep,
-                         hipStream_t s) {
+                         hipStream_t s, Ev ev) {
+  const dim3 g(t.ntiles), b(kThreads);
   if (t.tz == 1)
-    k_repair<1, 32, 64><<<t.ntiles, kThreads, 0, s>>>(box, t, mask, sub, stamp, counters, sweep);
+    hipExtLaunchKernelGGL(k_repair<1, 32, 64>, g, b, 0, s, ev.a, ev.b, 0, box, t, mask, sub,
+                          stamp, counters, sweep);
   else
-    k_repair<8, 8, 32><<<t.ntiles, kThreads, 0, s>>>(box, t, mask, sub, stamp, counters, sweep);
+    hipExtLaunchKernelGGL(k_repair<8, 8, 32>, g, b, 0, s, ev.a, ev.b, 0, box, t, mask, sub,
+                          stamp, counters, sweep);
   return hipGetLastError();
 }
 
@@ -746,10 +758,10 @@ hipError_t launch_zero_p(const BatchDesc* bd, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_zero_n(uint32_t* words, uint64_t nwords, hipStream_t s) {
+hipError_t launch_zero_n(uint32_t* words, uint64_t nwords, hipStream_t s, Ev ev) {
   if (!nwords) return hipSuccess;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(1024, (nwords + kThreads - 1) / kThreads);
-  k_zero_n<<<grid, kThreads, 0, s>>>(words, nwords);
+  hipExtLaunchKernelGGL(k_zero_n, dim3(grid), dim3(kThreads), 0, s, ev.a, ev.b, 0, words, nwords);
   return hipGetLastError();
 }
 

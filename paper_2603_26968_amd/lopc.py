@@ -170,8 +170,18 @@ def lopc_ctx_destroy(ctx: int) -> None:
     load().lopc_ctx_destroy(ctx)
 
 
-def lopc_ctx_set_timing(ctx: int, enable: bool) -> None:
-    st = load().lopc_ctx_set_timing(ctx, 1 if enable else 0)
+def lopc_ctx_set_timing(ctx: int, phases=True) -> None:
+    """Time the phases named in ``phases`` (names from PHASES) in the calls
+    that follow; True: every phase, False / empty: none."""
+    if phases is True:
+        mask = (1 << len(PHASES)) - 1
+    elif not phases:
+        mask = 0
+    else:
+        mask = 0
+        for p in phases:
+            mask |= 1 << PHASES.index(p)
+    st = load().lopc_ctx_set_timing(ctx, mask)
     if st:
         raise LopcError(st, "lopc_ctx_set_timing")
 
@@ -234,13 +244,14 @@ def lopc_stream_info(header: bytes) -> dict:
 
 
 def lopc_compress(ctx, d_field, dtype_code, shape, error_bound, mode, d_stream, cap,
-                  d_ws, ws_bytes, stream):
-    """Raw call: returns (status, stream size, Stats)."""
+                  d_ws, ws_bytes, stream, want_stats: bool = True):
+    """Raw call: returns (status, stream size, Stats or None)."""
     size = ctypes.c_size_t()
-    stats = Stats()
+    stats = Stats() if want_stats else None
     st = load().lopc_compress(ctx, d_field, dtype_code, len(shape), _dims(shape),
                               float(error_bound), mode, d_stream, cap, ctypes.byref(size),
-                              d_ws, ws_bytes, stream, ctypes.byref(stats))
+                              d_ws, ws_bytes, stream,
+                              ctypes.byref(stats) if want_stats else None)
     return st, size.value, stats
 
 
@@ -383,7 +394,7 @@ def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = Fals
     s = torch.cuda.current_stream(dev).cuda_stream
     st, size, stt = lopc_compress(ctx, x.data_ptr(), code, tuple(x.shape), error_bound,
                                   _mode(mode), out.data_ptr(), out.numel(),
-                                  workspace.data_ptr(), workspace.numel(), s)
+                                  workspace.data_ptr(), workspace.numel(), s, stats)
     if st:
         raise LopcError(st, "lopc_compress", ctx)
     res = [out[:size]]

@@ -209,6 +209,14 @@ def test_turb3d_full_size(P, ref, eb):
     check(P, ref, x, eb, "noa", "turb3d 256^3")
 
 
+def test_more_chunks_than_one_offset_pass(P, ref):
+    """binary64, 4160 chunks: the record-offset scan takes 4096 chunks per
+    pass, so the second pass and its carry are exercised (ragged tail of 64
+    chunks)."""
+    x = synth.turbulence_field((130, 256, 256), seed=5, dtype=np.float64)
+    check(P, ref, x, 1e-3, "noa", "turb3d f64 130x256x256")
+
+
 def test_smooth2d_full_size(P, ref):
     check(P, ref, synth.smooth_field(), 1e-3, "noa", "smooth2d 512^2")
 
@@ -263,3 +271,33 @@ def test_header_passthrough(P, ref):
     except P.LopcError as e:
         assert e.code == lopc.LOPC_E_FORMAT
     torch.cuda.synchronize()
+
+
+def test_phase_timing_mask(P, ref):
+    """Phase timing: the phases in the mask report positive times, the others
+    0; outputs are those of an untimed call; a mask with unknown bits is
+    refused."""
+    from paper_2603_26968_amd import lopc
+    _say("phase timing mask")
+    x = synth.gaussian_bumps((40, 33, 29), seed=4)
+    t = torch.from_numpy(x).cuda()
+    ctx = lopc.lopc_ctx_create(0)
+    try:
+        want = ref.compress(x, 1e-3, ref.NOA)
+        for phases in (True, ("encode", "decode"), ("range", "repair", "offsets")):
+            lopc.lopc_ctx_set_timing(ctx, phases)
+            s = P.compress(t, 1e-3, "noa", ctx=ctx)
+            ms_c = lopc.lopc_ctx_last_timings(ctx)
+            y = P.decompress(s, ctx=ctx)
+            ms_d = lopc.lopc_ctx_last_timings(ctx)
+            torch.cuda.synchronize()
+            assert s.cpu().numpy().tobytes() == want
+            assert same_bits(y.cpu().numpy(), ref.decompress(want))
+            on = set(lopc.PHASES) if phases is True else set(phases)
+            for p in lopc.PHASES:
+                v = (ms_d if p in ("offsets", "decode") else ms_c)[p]
+                assert (v > 0) == (p in on), (phases, p, v)
+        lopc.lopc_ctx_set_timing(ctx, False)
+        assert lopc.load().lopc_ctx_set_timing(ctx, 1 << 6) == lopc.LOPC_E_ARG
+    finally:
+        lopc.lopc_ctx_destroy(ctx)
