@@ -130,13 +130,27 @@ __device__ void level_encode(const uint8_t* cur, uint32_t n, uint8_t* nxt,
   __syncthreads();
 }
 
+// LDS position of BIT_K unit u (plane u / G, group u % G).  In a full chunk
+// (G = 64 or 32, a power of two) the groups of plane j are stored
+// XOR-permuted by j, so the 8K lanes that store the planes of one group (a
+// row stride of G units) reach distinct LDS banks instead of one; partial
+// chunks keep the plain order (mask 0).
+struct UnitSwizzle {
+  uint32_t shift, mask;
+  __device__ __forceinline__ uint32_t operator()(uint32_t u) const {
+    return u ^ ((u >> shift) & mask);
+  }
+};
+
 // RZE_W over the first `len` bytes of the unit array U (zero beyond len)
 // into out.  Units from `nua` on are known to be zero (bit planes above the
 // highest set bit) and are skipped.  Returns the output length; pt = 1 when
 // the input is stored verbatim because the output would not be smaller.
+// U may be stored swizzled (sw); the output is in plain byte order.
 template <int W>
 __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
-                               uint8_t* out, Scratch& sc, int& pt) {
+                               uint8_t* out, Scratch& sc, int& pt,
+                               UnitSwizzle sw = UnitSwizzle{0, 0}) {
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
   const uint32_t rounds = (NU + 63) / 64;
@@ -150,7 +164,7 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
   }
   for (uint32_t r = wave(); r < ra; r += kCW) {
     const uint32_t u = r * 64 + lane();
-    const uint64_t v = u < NU ? U[u] : 0ull;
+    const uint64_t v = u < NU ? U[sw(u)] : 0ull;
     uint32_t mi, ci;
     if (W == 1) {
       mi = nonzero_bytes(v);
@@ -181,7 +195,7 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
   for (int l = 0; l < top; ++l) out_len += sc.nkept[l];
   if (out_len >= len) {
     const uint8_t* ub = (const uint8_t*)U;
-    for (uint32_t i = threadIdx.x; i < len; i += kCT) out[i] = ub[i];
+    for (uint32_t i = threadIdx.x; i < len; i += kCT) out[i] = ub[8 * sw(i >> 3) + (i & 7)];
     pt = 1;
     __syncthreads();
     return len;
@@ -200,7 +214,7 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
   }
   for (uint32_t r = wave(); r < ra; r += kCW) {
     const uint32_t u = r * 64 + lane();
-    const uint64_t v = u < NU ? U[u] : 0ull;
+    const uint64_t v = u < NU ? U[sw(u)] : 0ull;
     uint32_t ci;
     if (W == 1) ci = __popc(nonzero_bytes(v));
     else if (W == 4) ci = ((uint32_t)v != 0u) + ((v >> 32) != 0ull);
@@ -412,7 +426,7 @@ __device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
 // 64*g + lane of group g = wave + kCW*i.  Planes >= np are zero.
 template <int K, int GPW>
 __device__ void bit_encode(const typename Traits<K>::Word (&wv)[GPW], uint32_t G,
-                           uint32_t np, uint64_t* U) {
+                           uint32_t np, uint64_t* U, UnitSwizzle sw) {
 #pragma unroll
   for (int i = 0; i < GPW; ++i) {
     const uint32_t g = wave() + kCW * i;
@@ -422,7 +436,7 @@ __device__ void bit_encode(const typename Traits<K>::Word (&wv)[GPW], uint32_t G
       uint64_t b = __ballot((wv[i] >> j) & 1);
       if (lane() == (int)j) mine = b;
     }
-    if (lane() < 8 * K) U[lane() * G + g] = mine;
+    if (lane() < 8 * K) U[sw(lane() * G + g)] = mine;
   }
 }
 
@@ -550,9 +564,12 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
   const uint32_t L = m * K;
   const Word M = (Word)0xAAAAAAAAAAAAAAAAull;
 
+  const UnitSwizzle sw{(uint32_t)__builtin_ctz(W / 64), G == W / 64 ? G - 1 : 0u};
+
   // bins: DIFFNB_K (delta from the previous bin, 0 before the chunk, then
-  // negabinary), zero words up to m, BIT_K, RZE_1
-  Word wv[GPW];
+  // negabinary), zero words up to m, BIT_K, RZE_1.  The subbins are loaded
+  // here as well, so that their memory latency overlaps the bins stages.
+  Word wv[GPW], sv[GPW];
   uint64_t orv = 0;
 #pragma unroll
   for (int i = 0; i < GPW; ++i) {
@@ -565,31 +582,26 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
       Word d = cur - prev;
       v = (d + M) ^ M;
     }
+    sv[i] = j < nc ? (Word)sub[p0 + j] : (Word)0;
     wv[i] = v;
     orv |= (uint64_t)v;
   }
   orv = block_or(orv, sc);
   uint32_t np = orv ? 64 - (uint32_t)__builtin_clzll(orv) : 0;
-  bit_encode<K, GPW>(wv, G, np, U);
+  bit_encode<K, GPW>(wv, G, np, U, sw);
   __syncthreads();
   int pt_b = 0, pt_s1 = 0, pt_s2 = 0;
-  const uint32_t blen = rze_encode<1>(U, L, np * G, (uint8_t*)B, sc, pt_b);
+  const uint32_t blen = rze_encode<1>(U, L, np * G, (uint8_t*)B, sc, pt_b, sw);
 
   // subbins: zero words up to m, BIT_K, RZE_K, RZE_1
   orv = 0;
 #pragma unroll
-  for (int i = 0; i < GPW; ++i) {
-    const uint32_t g = wave() + kCW * i;
-    const uint32_t j = g * 64 + lane();
-    Word v = j < nc ? (Word)sub[p0 + j] : (Word)0;
-    wv[i] = v;
-    orv |= (uint64_t)v;
-  }
+  for (int i = 0; i < GPW; ++i) orv |= (uint64_t)sv[i];
   orv = block_or(orv, sc);
   np = orv ? 64 - (uint32_t)__builtin_clzll(orv) : 0;
-  bit_encode<K, GPW>(wv, G, np, U);
+  bit_encode<K, GPW>(sv, G, np, U, sw);
   __syncthreads();
-  const uint32_t smid = rze_encode<K>(U, L, np * G, (uint8_t*)X, sc, pt_s1);
+  const uint32_t smid = rze_encode<K>(U, L, np * G, (uint8_t*)X, sc, pt_s1, sw);
   if (threadIdx.x < 16) ((uint8_t*)X)[smid + threadIdx.x] = 0;  // zero units past smid
   __syncthreads();
   const uint32_t slen = rze_encode<1>(X, smid, (smid + 7) / 8, (uint8_t*)U, sc, pt_s2);
@@ -865,8 +877,21 @@ __device__ __forceinline__ bool bin_floor_key(int64_t b, double inv,
 // copy n bytes from global src (4-byte aligned base) to LDS dst
 __device__ __forceinline__ void stage(uint8_t* dst, const uint8_t* src, uint32_t n) {
   const uint32_t nw = (n + 3) / 4;
-  for (uint32_t i = threadIdx.x; i < nw; i += kCT)
-    ((uint32_t*)dst)[i] = ((const uint32_t*)src)[i];
+  const uint32_t* s = (const uint32_t*)src;
+  uint32_t* d = (uint32_t*)dst;
+  for (uint32_t i0 = 0; i0 < nw; i0 += 4 * kCT) {
+    uint32_t v[4];  // four loads in flight per thread
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = i0 + k * kCT + threadIdx.x;
+      v[k] = i < nw ? s[i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = i0 + k * kCT + threadIdx.x;
+      if (i < nw) d[i] = v[k];
+    }
+  }
 }
 
 // Decodes chunk c of a field (Sec. IV-E); a malformed record sets FORMAT.
@@ -888,30 +913,37 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
   const uint32_t p0 = c * W, nc = min(W, n - p0);
   const uint32_t m = (nc + 63) / 64 * 64, G = m / 64, L = m * K;
   const uint64_t body = kHeaderBytes + 4ull * nch;
+  // the record's size and offset are read together with the status;
   // offsets inconsistent (one read decides for the block: other chunks may
   // set the flag concurrently)
-  if (__syncthreads_or(threadIdx.x == 0 && (prm->status & ST_FORMAT))) return;
   const uint32_t rsize = ((const uint32_t*)(stream + kHeaderBytes))[c];
-  const uint8_t* rec = stream + body + offsets[c];
+  const uint64_t roff = offsets[c];
   if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
+  if (__syncthreads_or(threadIdx.x == 0 && (prm->status & ST_FORMAT))) return;
+  const uint8_t* rec = stream + body + roff;
   if (rsize < kRecordHeaderBytes || (rsize & 3)) {
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
     return;
   }
+  // a record that fits in Mb (every record of a chunk that compresses at all)
+  // comes in with one load per word, its parts are then read from LDS; the
+  // header is read (scalar loads) while the words are in flight
+  const bool whole = rsize <= 8 * (kMaxUnits + 2);
+  if (whole) stage((uint8_t*)Mb, rec, rsize);
+  const uint8_t* hd = rec;
   const double inv = __longlong_as_double(*(const long long*)(stream + 56));
   const double winv = 1.0 / inv;
-  const uint32_t bfl = rec[0], sfl = rec[1];
-  const uint32_t npts = rec[2] | (rec[3] << 8);
-  const uint32_t blen = *(const uint32_t*)(rec + 4);
-  const uint32_t smid = *(const uint32_t*)(rec + 8);
-  const uint32_t slen = *(const uint32_t*)(rec + 12);
+  const uint32_t bfl = hd[0], sfl = hd[1];
+  const uint32_t npts = hd[2] | (hd[3] << 8);
+  const uint32_t blen = *(const uint32_t*)(hd + 4);
+  const uint32_t smid = *(const uint32_t*)(hd + 8);
+  const uint32_t slen = *(const uint32_t*)(hd + 12);
   bool ok = !(bfl & ~1u) && !(sfl & ~3u) && npts == nc && blen <= L &&
             smid <= L && slen <= L;
   const uint32_t used = kRecordHeaderBytes + blen + slen;
   ok = ok && ((used + 3) & ~3u) == rsize;
-  if (ok && threadIdx.x < rsize - used && rec[used + threadIdx.x] != 0) s_bad = 1;
-  __syncthreads();
+  if (ok && threadIdx.x < rsize - used && hd[used + threadIdx.x] != 0) s_bad = 1;
+  __syncthreads();  // s_bad, and the staged record
   ok = ok && !s_bad;
   if (!ok) {
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
@@ -919,16 +951,19 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
   }
 
   // bins: RZE_1 -> BIT_K -> negabinary -> prefix sum (words kept in registers)
-  stage((uint8_t*)Mb, rec + kRecordHeaderBytes, blen);
-  __syncthreads();
+  const uint64_t* bsrc = Mb + (whole ? kRecordHeaderBytes / 8 : 0);
+  if (!whole) {
+    stage((uint8_t*)Mb, rec + kRecordHeaderBytes, blen);
+    __syncthreads();
+  }
   const uint64_t* planes;
   uint64_t pm0 = 0;
   if (bfl & 1) {
     ok = blen == L;
-    planes = Mb;
+    planes = bsrc;
     if (ok) pm0 = nonzero_planes<K>(planes, G, sc);
   } else {
-    ok = rze_decode<1>((const uint8_t*)Mb, blen, L, U, sc, G);
+    ok = rze_decode<1>((const uint8_t*)bsrc, blen, L, U, sc, G);
     planes = U;
     pm0 = sc.planes;
   }
@@ -982,10 +1017,15 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
     }
   }
 
-  // subbins: RZE_1 -> RZE_K -> BIT_K
+  // subbins: RZE_1 -> RZE_K -> BIT_K (the part goes to U, free now)
   const uint32_t soff = kRecordHeaderBytes + blen;
   const uint32_t shift = soff & 3u;
-  stage((uint8_t*)U, rec + (soff - shift), slen + shift);
+  if (whole) {
+    const uint32_t* src = (const uint32_t*)((const uint8_t*)Mb + (soff - shift));
+    for (uint32_t i = threadIdx.x; i < (slen + shift + 3) / 4; i += kCT) ((uint32_t*)U)[i] = src[i];
+  } else {
+    stage((uint8_t*)U, rec + (soff - shift), slen + shift);
+  }
   __syncthreads();
   const uint8_t* sp = (const uint8_t*)U + shift;
   if (sfl & 2) {
