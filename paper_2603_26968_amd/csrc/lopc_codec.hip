@@ -367,7 +367,7 @@ __device__ void rze_decode_head(const uint8_t* in, uint32_t in_len, uint32_t ite
 // unit.  Three block barriers: after the front half (wave 0), after the
 // payload, after the plane mask.
 template <int W>
-__device__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
+__device__ __forceinline__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
                            uint64_t* U, Scratch& sc, uint32_t G) {
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
