@@ -110,10 +110,11 @@ def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing, want_stats=True):
     return (t1 - t0), {k: v / max(steps, 1) for k, v in phase.items()}, stats, s
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary of
-    the turb3d workload (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel),
-    or None if it was taken on other kernel sources than the current ones."""
+def measured_traffic(phase):
+    """HBM bytes per launch of the kernels of codec phase `phase` ("encode"
+    or "decode") from the committed counter summary of the turb3d workload
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel), or None if it was
+    taken on other kernel sources than the current ones."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "turb3d_256_f32_eb1e-3_traffic.md")
     if not os.path.exists(path):
@@ -124,7 +125,7 @@ def measured_traffic(kernel):
         h.update(open(os.path.join(ROOT, "paper_2603_26968_amd", "csrc", f), "rb").read())
     src = h.hexdigest()[:16]
     for line in open(path):
-        if line.startswith("traffic ") and f" {kernel} " in line and f"sources={src}" in line:
+        if line.startswith("traffic ") and f" {phase} " in line and f"sources={src}" in line:
             fields = dict(kv.split("=") for kv in line.split() if "=" in kv)
             return int(fields["fetch_bytes"]) + int(fields["write_bytes"])
     return None
@@ -175,9 +176,10 @@ def bench_single(args, name):
     t_d = phase["offsets"] + phase["decode"]
     value = n * k / (dt / args.steps) / 1e9
 
-    # algorithmic bytes of the two codec kernels: the decoder reads the
-    # stream and writes the field; the encoder reads bins and subbins and
-    # writes the stream
+    # algorithmic bytes of the two codec phases: the decoder reads the
+    # stream and writes the field; the encoder (k_encode, which parks each
+    # record in rows it has consumed, k_record_offsets and k_place, timed
+    # together) reads bins and subbins and writes the stream
     dec_bytes = S + n * k
     dec_gbps = dec_bytes / (phase_k["decode"] * 1e-3) / 1e9 if phase_k["decode"] else 0.0
     enc_bytes = n * k + n * 4 + S
@@ -187,8 +189,8 @@ def bench_single(args, name):
         "encode": {"ms": phase_k["encode"], "bytes": enc_bytes, "GBps": enc_gbps},
     }
     dom = max(kernels, key=lambda q: kernels[q]["ms"])
-    kname = "k_decode" if dom == "decode" else "k_encode"
-    traffic = measured_traffic(kname) if name == "turb3d" and args.eb == 1e-3 else None
+    kname = "k_decode" if dom == "decode" else "k_encode+k_record_offsets+k_place"
+    traffic = measured_traffic(dom) if name == "turb3d" and args.eb == 1e-3 else None
     roof = {"bound": "hbm", "kernel": kname,
             "achieved": round(kernels[dom]["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(kernels[dom]["GBps"] / HBM_PEAK_GBPS, 4), "traffic": traffic,
