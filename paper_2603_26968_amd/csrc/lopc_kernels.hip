@@ -193,6 +193,39 @@ struct TileGeom {
   }
 };
 
+// Neighbour tiles reached from owned point i along the stencil offsets in
+// `bits` (a subset of the point's 14 / 6 offsets), as a 27-bit set: bit
+// (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1) for tile offset (dz, dy, dx).
+// Offsets that stay inside the tile add nothing.
+template <int TZ, int TY, int TX>
+__device__ __forceinline__ uint32_t out_dirs(int i, uint32_t bits) {
+  const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
+  uint32_t d = 0;
+  while (bits) {
+    const int j = __builtin_ctz(bits);
+    bits &= bits - 1;
+    const int z = iz + c_off[j][0], y = iy + c_off[j][1], x = ix + c_off[j][2];
+    const int dz = z < 0 ? -1 : (z >= TZ ? 1 : 0), dy = y < 0 ? -1 : (y >= TY ? 1 : 0),
+              dx = x < 0 ? -1 : (x >= TX ? 1 : 0);
+    if (dz | dy | dx) d |= 1u << ((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
+  }
+  return d;
+}
+
+// OR of v over the workgroup (every thread gets it)
+__device__ __forceinline__ uint32_t block_or32(uint32_t v) {
+  __shared__ uint32_t w[kWaves];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v |= __shfl_xor(v, d, 64);
+  if (lane() == 0) w[wave()] = v;
+  __syncthreads();
+  uint32_t r = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) r |= w[q];
+  __syncthreads();
+  return r;
+}
+
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
 // index.  Give each XCD a contiguous range of tiles instead, so that tiles
 // that share halo data share an L2: workgroup b (of n) takes tile
@@ -283,13 +316,14 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
   if (threadIdx.x == 0) atomicAdd(&itot[t % 64], (unsigned long long)(iters + 1));
 }
 
-// mark the 26 neighbour tiles for sweep `next`; one atomic per block adds
-// the number of newly marked tiles to counters[1 + next % 64]
-__device__ void mark_neighbours(bool edge, const TileCoord& c, const Tiling& tl,
+// mark the neighbour tiles in `dirs` (27-bit set, see out_dirs) for sweep
+// `next`; one atomic per block adds the number of newly marked tiles to
+// counters[1 + next % 64]
+__device__ void mark_neighbours(uint32_t dirs, const TileCoord& c, const Tiling& tl,
                                 uint32_t* stamp, uint32_t* counters,
                                 uint32_t next) {
   bool newly = false;
-  if (edge && threadIdx.x < 27) {
+  if (threadIdx.x < 27 && ((dirs >> threadIdx.x) & 1u)) {
     int dz = (int)threadIdx.x / 9 - 1, dy = ((int)threadIdx.x / 3) % 3 - 1,
         dx = (int)threadIdx.x % 3 - 1;
     int nz = c.tz + dz, ny = c.ty + dy, nx = c.tx + dx;
@@ -310,9 +344,11 @@ __device__ void mark_neighbours(bool edge, const TileCoord& c, const Tiling& tl,
 // First pass, fused: build the order flags of the owned points (a2, the
 // flags of Alg. 1) from the bins and values of the tile and its halo, write
 // them, then relax with halo subbins 0 (the first sweep of a3).
-// Returns (block-uniform) whether a boundary subbin of the tile is nonzero.
+// Returns (block-uniform) the neighbour tiles to sweep next: those holding a
+// point that has a nonzero boundary point of this tile as a same-bin lower
+// neighbour (only their relaxation depends on it).
 template <int K, int TZ, int TY, int TX>
-__device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __restrict__ x, Box box,
+__device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __restrict__ x, Box box,
                            Tiling tl, Params* prm, typename Traits<K>::Bin* __restrict__ bins,
                            uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
                            uint32_t* counters, unsigned long long* itot, uint32_t t,
@@ -371,13 +407,15 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
   // the halo lies inside the grid: no neighbour needs a bounds check
   const bool inner = c.z0 - G::ZO >= 0 && c.z0 + TZ - 1 + G::ZO < box.nz && c.y0 >= 1 &&
                      c.y0 + TY < box.ny && c.x0 >= 1 && c.x0 + TX < box.nx;
-  uint16_t mk[G::PER];
+  // per owned point: mk = same bin and lower (the flags), up = same bin and
+  // higher (the neighbours whose relaxation depends on this point)
+  uint16_t mk[G::PER], up[G::PER];
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
     const int i = threadIdx.x + k * kThreads;
     const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
     const int z = c.z0 + iz, y = c.y0 + iy, xx = c.x0 + ix;
-    uint32_t m = 0;
+    uint32_t sm = 0, lm = 0;
     const int li = G::local(i);
     const KB ep = P[li];
     const Key kp = (Key)ep.x;
@@ -392,9 +430,10 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
         const Key kq = (Key)eq.x;
         // branch-free: same bin, and lower in (value, index) order
         const bool lower = (kq < kp) | ((kq == kp) & ((j & 1) != 0));
-        m |= (uint32_t)(((Bin)eq.y == bp) & lower) << j;
+        sm |= (uint32_t)((Bin)eq.y == bp) << j;
+        lm |= (uint32_t)lower << j;
       }
-      mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)m;
+      mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)(sm & lm);
     } else if (z < box.nz && y < box.ny && xx < box.nx) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -406,17 +445,19 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
         const Key kq = (Key)eq.x;
         // odd j: the neighbour has the lower index
         const bool lower = (kq < kp) | ((kq == kp) & ((j & 1) != 0));
-        m |= (uint32_t)(((Bin)eq.y == bp) & lower) << j;
+        sm |= (uint32_t)((Bin)eq.y == bp) << j;
+        lm |= (uint32_t)lower << j;
       }
-      mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)m;
+      mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)(sm & lm);
     }
-    mk[k] = (uint16_t)m;
+    mk[k] = (uint16_t)(sm & lm);
+    up[k] = (uint16_t)(sm & ~lm);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < G::H; i += kThreads) S[i] = 0;
   __syncthreads();
   relax<TZ, TY, TX>(S, mk, counters, itot, t);
-  int edge = 0;
+  uint32_t dirs = 0;
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
     const int i = threadIdx.x + k * kThreads;
@@ -425,10 +466,10 @@ __device__ __forceinline__ bool tile0_body(const typename Traits<K>::Raw* __rest
     if (z < box.nz && y < box.ny && xx < box.nx) {
       const uint32_t v = S[G::local(i)];
       sub[((int64_t)z * box.ny + y) * box.nx + xx] = v;
-      if (v && G::on_edge(i)) edge = 1;
+      if (v && up[k]) dirs |= out_dirs<TZ, TY, TX>(i, up[k]);
     }
   }
-  return __syncthreads_or(edge) != 0;
+  return block_or32(dirs);
 }
 
 template <int K, int TZ, int TY, int TX>
@@ -438,73 +479,94 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
     uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
     uint32_t* counters) {
   TileCoord c;
-  const bool edge = tile0_body<K, TZ, TY, TX>(x, box, tl, prm, bins, mask, sub, counters,
-                                              relax_total(counters),
-                                              xcd_tile(blockIdx.x, gridDim.x), c);
-  mark_neighbours(edge, c, tl, stamp, counters, 1);
+  const uint32_t dirs = tile0_body<K, TZ, TY, TX>(x, box, tl, prm, bins, mask, sub, counters,
+                                                  relax_total(counters),
+                                                  xcd_tile(blockIdx.x, gridDim.x), c);
+  mark_neighbours(dirs, c, tl, stamp, counters, 1);
 }
 
 
 // Later sweeps: tiles marked for this sweep reload their halo and relax.
-// One sweep of tile t if it is marked for it.  Returns (block-uniform) whether
-// a boundary subbin changed; false if the tile did not run.
+// One sweep of tile t if it is marked for it.  Returns (block-uniform) the
+// neighbour tiles holding a point whose flags name a changed boundary point
+// of this tile as a lower neighbour (0 if the tile did not run).
 template <int TZ, int TY, int TX>
-__device__ __forceinline__ bool repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
+__device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
                             uint32_t* __restrict__ sub, const uint32_t* stamp,
                             uint32_t* counters, unsigned long long* itot, uint32_t sweep,
                             uint32_t t, TileCoord& c) {
   using G = TileGeom<TZ, TY, TX>;
+  constexpr int NJ = TZ == 1 ? 6 : 14;
   __shared__ uint32_t S[G::H];
+  __shared__ uint16_t M[G::H];  // flags of the halo and the owned points
   // one read decides for the whole block (a neighbour may raise the stamp
   // concurrently)
-  if (!__syncthreads_or(threadIdx.x == 0 && stamp[t] >= sweep)) return false;
+  if (!__syncthreads_or(threadIdx.x == 0 && stamp[t] >= sweep)) return 0;
   c = tile_coord<TZ, TY, TX>(t, tl);
   constexpr int HL = (G::H + kThreads - 1) / kThreads;
   {
     uint32_t hv[HL];
+    uint16_t hm[HL];
 #pragma unroll
     for (int q = 0; q < HL; ++q) {
       const int i = threadIdx.x + q * kThreads;
       hv[q] = 0;
+      hm[q] = 0;
       if (i < G::H) {
         int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
         int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, x = c.x0 + hx - 1;
-        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx)
-          hv[q] = sub[((int64_t)z * box.ny + y) * box.nx + x];
+        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx) {
+          const int64_t g = ((int64_t)z * box.ny + y) * box.nx + x;
+          hv[q] = sub[g];
+          hm[q] = mask[g];
+        }
       }
     }
 #pragma unroll
     for (int q = 0; q < HL; ++q) {
       const int i = threadIdx.x + q * kThreads;
-      if (i < G::H) S[i] = hv[q];
+      if (i < G::H) {
+        S[i] = hv[q];
+        M[i] = hm[q];
+      }
     }
   }
-  uint16_t mk[G::PER];
-#pragma unroll
-  for (int k = 0; k < G::PER; ++k) {
-    const int i = threadIdx.x + k * kThreads;
-    const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
-    const int z = c.z0 + iz, y = c.y0 + iy, x = c.x0 + ix;
-    mk[k] = (z < box.nz && y < box.ny && x < box.nx)
-                ? mask[((int64_t)z * box.ny + y) * box.nx + x] : (uint16_t)0;
-  }
   __syncthreads();
+  uint16_t mk[G::PER];
   uint32_t old[G::PER];
 #pragma unroll
-  for (int k = 0; k < G::PER; ++k) old[k] = S[G::local(threadIdx.x + k * kThreads)];
+  for (int k = 0; k < G::PER; ++k) {
+    const int li = G::local(threadIdx.x + k * kThreads);
+    mk[k] = M[li];
+    old[k] = S[li];
+  }
   relax<TZ, TY, TX>(S, mk, counters, itot, t);
-  int edge = 0;
+  uint32_t dirs = 0;
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
     const int i = threadIdx.x + k * kThreads;
-    const uint32_t v = S[G::local(i)];
+    const int li = G::local(i);
+    const uint32_t v = S[li];
     if (v != old[k]) {
       const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
       sub[((int64_t)(c.z0 + iz) * box.ny + c.y0 + iy) * box.nx + c.x0 + ix] = v;
-      if (G::on_edge(i)) edge = 1;
+      if (G::on_edge(i)) {
+        // halo neighbours whose flags name this point (offset j from here is
+        // offset j ^ 1 from there)
+        uint32_t dep = 0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int z = iz + kOff[j][0], y = iy + kOff[j][1], x = ix + kOff[j][2];
+          if (z < 0 || z >= TZ || y < 0 || y >= TY || x < 0 || x >= TX) {
+            const int ln = li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2];
+            dep |= (uint32_t)((M[ln] >> (j ^ 1)) & 1u) << j;
+          }
+        }
+        if (dep) dirs |= out_dirs<TZ, TY, TX>(i, dep);
+      }
     }
   }
-  return __syncthreads_or(edge) != 0;
+  return block_or32(dirs);
 }
 
 template <int TZ, int TY, int TX>
@@ -513,9 +575,10 @@ __global__ __launch_bounds__(kThreads) void k_repair(
     uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
     uint32_t sweep) {
   TileCoord c;
-  if (repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, relax_total(counters),
-                              sweep, xcd_tile(blockIdx.x, gridDim.x), c))
-    mark_neighbours(true, c, tl, stamp, counters, sweep + 1);
+  const uint32_t dirs = repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters,
+                                                relax_total(counters), sweep,
+                                                xcd_tile(blockIdx.x, gridDim.x), c);
+  if (dirs) mark_neighbours(dirs, c, tl, stamp, counters, sweep + 1);
 }
 
 
@@ -523,15 +586,16 @@ __global__ __launch_bounds__(kThreads) void k_repair(
 // ------------------------------------------------------------------ batches
 // Persistent kernels: a fixed grid drains the batch-wide items of one phase.
 
-// mark the 26 neighbour tiles of a tile of a batch field for sweep `next`
-// and append the newly marked ones (as batch-wide tile items) to that
-// sweep's work list; each tile is listed at most once per sweep
-__device__ void mark_list(bool edge, const TileCoord& c, const Tiling& tl, uint32_t* stamp,
+// mark the neighbour tiles in `dirs` (27-bit set, see out_dirs) of a tile of
+// a batch field for sweep `next` and append the newly marked ones (as
+// batch-wide tile items) to that sweep's work list; each tile is listed at
+// most once per sweep
+__device__ void mark_list(uint32_t dirs, const TileCoord& c, const Tiling& tl, uint32_t* stamp,
                           uint32_t t0, uint32_t* lens, uint32_t* list, uint32_t next) {
   if (threadIdx.x >= 64) return;
   bool newly = false;
   uint32_t item = 0;
-  if (edge && threadIdx.x < 27) {
+  if (threadIdx.x < 27 && ((dirs >> threadIdx.x) & 1u)) {
     int dz = (int)threadIdx.x / 9 - 1, dy = ((int)threadIdx.x / 3) % 3 - 1,
         dx = (int)threadIdx.x % 3 - 1;
     int nz = c.tz + dz, ny = c.ty + dy, nx = c.tx + dx;
@@ -600,11 +664,11 @@ __global__ __launch_bounds__(kThreads) void k_tile0_p(const BatchDesc* bd, const
     const Job& J = jobs[find_job<&Job::t0>(jobs, j0, j1, it)];
     __syncthreads();
     TileCoord c;
-    const bool edge = tile0_body<K, TZ, TY, TX>(
+    const uint32_t dirs = tile0_body<K, TZ, TY, TX>(
         (const typename Traits<K>::Raw*)J.x, J.box, J.tl, J.prm,
         (typename Traits<K>::Bin*)J.bins, J.mask, J.sub, &bc->err, bc->relax_iters,
         it - J.t0, c);
-    mark_list(edge, c, J.tl, J.stamp, J.t0, bc->lens, list1, 1);
+    mark_list(dirs, c, J.tl, J.stamp, J.t0, bc->lens, list1, 1);
   }
 }
 
@@ -626,14 +690,14 @@ __global__ __launch_bounds__(kThreads) void k_repair_p(const BatchDesc* bd, cons
     const uint32_t item = list_in[it];
     const Job& J = jobs[find_job<&Job::t0>(jobs, 0, nj, item)];
     TileCoord c;
-    bool edge;
+    uint32_t dirs;
     if (J.tl.tz == 1)
-      edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
-                                    item - J.t0, c);
+      dirs = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
+                                    bc->relax_iters, sweep, item - J.t0, c);
     else
-      edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
-                                   item - J.t0, c);
-    if (edge) mark_list(true, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
+      dirs = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
+                                   bc->relax_iters, sweep, item - J.t0, c);
+    if (dirs) mark_list(dirs, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
   }
 }
 
@@ -662,10 +726,10 @@ __global__ __launch_bounds__(kThreads) void k_tile0_d(const BatchDesc* bd, const
   const uint32_t it = bd->item0[PH_T][g] + xcd_tile(blockIdx.x, gridDim.x);
   const Job& J = jobs[find_job<&Job::t0>(jobs, (int)bd->job0[g], (int)bd->job0[g + 1], it)];
   TileCoord c;
-  const bool edge = tile0_body<K, TZ, TY, TX>(
+  const uint32_t dirs = tile0_body<K, TZ, TY, TX>(
       (const typename Traits<K>::Raw*)J.x, J.box, J.tl, J.prm, (typename Traits<K>::Bin*)J.bins,
       J.mask, J.sub, &bd->bc->err, bd->bc->relax_iters, it - J.t0, c);
-  mark_list(edge, c, J.tl, J.stamp, J.t0, bd->bc->lens, bd->lists + bd->tiles, 1);
+  mark_list(dirs, c, J.tl, J.stamp, J.t0, bd->bc->lens, bd->lists + bd->tiles, 1);
 }
 
 // One sweep: workgroup b takes entry b of the sweep's work list (the grid
@@ -678,14 +742,14 @@ __global__ __launch_bounds__(kThreads) void k_repair_d(const BatchDesc* bd, cons
   const Job& J = jobs[find_job<&Job::t0>(jobs, 0, (int)bd->job0[kGroups], item)];
   uint32_t* list_out = bd->lists + ((sweep + 1) & 1) * bd->tiles;
   TileCoord c;
-  bool edge;
+  uint32_t dirs;
   if (J.tl.tz == 1)
-    edge = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
-                                  item - J.t0, c);
+    dirs = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
+                                  bc->relax_iters, sweep, item - J.t0, c);
   else
-    edge = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err, bc->relax_iters, sweep,
-                                 item - J.t0, c);
-  if (edge) mark_list(true, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
+    dirs = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
+                                 bc->relax_iters, sweep, item - J.t0, c);
+  if (dirs) mark_list(dirs, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
 }
 
 }  // namespace
