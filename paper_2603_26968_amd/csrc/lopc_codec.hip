@@ -547,10 +547,15 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
   using Word = typename Tr::Word;
   constexpr uint32_t W = kChunkBytes / K;
   constexpr int GPW = (int)(W / 64 / kCW);  // groups per wave
-  // 54,248 bytes of LDS in all: three workgroups fit in the 160 KiB of a CU
+  // LDS: the look-back path keeps the bins part (B) until the end beside
+  // the RZE_K output (X): 54,248 bytes, three workgroups per CU.  The slot
+  // path parks the bins part as soon as it is known and reuses B for X:
+  // about 37.9 KB, four workgroups per CU.
   __shared__ uint64_t U[kMaxUnits];      // bit planes; later the subbin part
-  __shared__ uint64_t B[kMaxUnits];      // bins part
-  __shared__ uint64_t X[kMaxUnits + 2];  // subbins after RZE_K (+16 zero bytes)
+  __shared__ uint64_t B[kMaxUnits + 2];  // bins part (slot path: then X)
+  __shared__ uint64_t Xb[kSlot ? 1 : kMaxUnits + 2];  // subbins after RZE_K (+16 zero bytes)
+  uint64_t* X = kSlot ? B : Xb;
+  __shared__ uint32_t s_btail;  // slot path: bytes of the bins part's partial last word
   __shared__ Scratch sc;
   // the record header and the chunk's offset live in sc.orv, which is free
   // once both block_or calls are done
@@ -592,6 +597,18 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
   __syncthreads();
   int pt_b = 0, pt_s1 = 0, pt_s2 = 0;
   const uint32_t blen = rze_encode<1>(U, L, np * G, (uint8_t*)B, sc, pt_b, sw);
+  const bool last = c == nch - 1;
+  const uint32_t room = last ? S.tail_len : S.len[0] + S.len[1] + S.len[2];
+  if constexpr (kSlot) {
+    // park the whole words of the bins part now (record bytes from 16 on)
+    if (kRecordHeaderBytes + blen <= room)
+      for (uint32_t q = threadIdx.x; q < blen / 4; q += kCT)
+        *slot_word(S, c, last, kRecordHeaderBytes / 4 + q) = ((const uint32_t*)B)[q];
+    if (threadIdx.x == 0)
+      s_btail = (blen & 3u) ? ((const uint32_t*)B)[blen / 4] & ((1u << (8 * (blen & 3u))) - 1u)
+                            : 0u;
+    __syncthreads();  // B is free for the RZE_K output
+  }
 
   // subbins: zero words up to m, BIT_K, RZE_K, RZE_1
   orv = 0;
@@ -624,16 +641,25 @@ __device__ __forceinline__ void encode_body(uint32_t n, const typename Traits<K>
         *(uint32_t*)(stream + kHeaderBytes + 4ull * c) = size;
     }
     __syncthreads();  // hdr
-    const bool last = c == nch - 1;
-    const uint32_t room = last ? S.tail_len : S.len[0] + S.len[1] + S.len[2];
     if (size <= room) {
-      const uint8_t* bp = (const uint8_t*)B;
+      // the header words, then from the bins part's partial word on (its
+      // bytes from s_btail), the subbin part and the padding
+      const uint8_t* bt = (const uint8_t*)&s_btail;
       const uint8_t* sp = (const uint8_t*)U;
-      for (uint32_t q = threadIdx.x; q < size / 4; q += kCT) {
+      const uint32_t nfull = blen / 4, nw = size / 4 - nfull;
+      for (uint32_t e = threadIdx.x; e < nw; e += kCT) {
+        const uint32_t q = e < kRecordHeaderBytes / 4 ? e : e + nfull;
         uint32_t w = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          w |= (uint32_t)record_byte(4 * q + b, hdr, bp, blen, sp, slen) << (8 * b);
+        for (int b = 0; b < 4; ++b) {
+          const uint32_t r = 4 * q + b;
+          uint32_t v;
+          if (r < kRecordHeaderBytes) v = hdr[r];
+          else if (r < kRecordHeaderBytes + blen) v = bt[r - kRecordHeaderBytes - 4 * nfull];
+          else if (r < kRecordHeaderBytes + blen + slen) v = sp[r - kRecordHeaderBytes - blen];
+          else v = 0;
+          w |= v << (8 * b);
+        }
         *slot_word(S, c, last, q) = w;
       }
     } else if (threadIdx.x == 0) {
