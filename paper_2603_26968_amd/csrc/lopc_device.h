@@ -60,10 +60,26 @@ constexpr int8_t kOff[14][3] = {
     {0, 0, 1},  {0, 0, -1},  {0, 1, 0},  {0, -1, 0}, {0, 1, 1},
     {0, -1, -1}, {1, 0, 0},  {-1, 0, 0}, {1, 0, 1},  {-1, 0, -1},
     {1, 1, 0},  {-1, -1, 0}, {1, 1, 1},  {-1, -1, -1}};
-__constant__ int8_t c_off[14][3] = {
-    {0, 0, 1},  {0, 0, -1},  {0, 1, 0},  {0, -1, 0}, {0, 1, 1},
-    {0, -1, -1}, {1, 0, 0},  {-1, 0, 0}, {1, 0, 1},  {-1, 0, -1},
-    {1, 1, 0},  {-1, -1, 0}, {1, 1, 1},  {-1, -1, -1}};
+// The same table as arithmetic, for a j known only at run time (no memory
+// access): offset j is +-(x, y, z bits of (j >> 1) + 1), minus for odd j.
+__device__ __forceinline__ int off_x(int j) {
+  const int e = (j >> 1) + 1;
+  return (j & 1) ? -(e & 1) : (e & 1);
+}
+__device__ __forceinline__ int off_y(int j) {
+  const int e = (j >> 1) + 1;
+  return (j & 1) ? -((e >> 1) & 1) : ((e >> 1) & 1);
+}
+__device__ __forceinline__ int off_z(int j) {
+  const int e = (j >> 1) + 1;
+  return (j & 1) ? -(e >> 2) : (e >> 2);
+}
+// linear offset of stencil offset j in a row-major box of rows hx, planes hxy
+__device__ __forceinline__ int off_lin(int j, int hx, int hxy) {
+  const int e = (j >> 1) + 1;
+  const int o = (e & 1) + ((e >> 1) & 1) * hx + (e >> 2) * hxy;
+  return (j & 1) ? -o : o;
+}
 
 // ------------------------------------------------------------------ scans
 // Exclusive scan of v over a block of NW waves; sh needs NW + 1 slots;

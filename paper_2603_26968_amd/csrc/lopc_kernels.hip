@@ -204,7 +204,7 @@ __device__ __forceinline__ uint32_t out_dirs(int i, uint32_t bits) {
   while (bits) {
     const int j = __builtin_ctz(bits);
     bits &= bits - 1;
-    const int z = iz + c_off[j][0], y = iy + c_off[j][1], x = ix + c_off[j][2];
+    const int z = iz + off_z(j), y = iy + off_y(j), x = ix + off_x(j);
     const int dz = z < 0 ? -1 : (z >= TZ ? 1 : 0), dy = y < 0 ? -1 : (y >= TY ? 1 : 0),
               dx = x < 0 ? -1 : (x >= TX ? 1 : 0);
     if (dz | dy | dx) d |= 1u << ((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
@@ -297,8 +297,7 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
         while (mm) {
           const int j = __builtin_ctz(mm);
           mm &= mm - 1;
-          const uint32_t c = S[li + c_off[j][0] * (G::HY * G::HX) + c_off[j][1] * G::HX +
-                               c_off[j][2]] + ((j & 1) ? 0u : 1u);
+          const uint32_t c = S[li + off_lin(j, G::HX, G::HY * G::HX)] + ((j & 1) ? 0u : 1u);
           best = c > best ? c : best;
         }
       }
