@@ -261,8 +261,9 @@ def lopc_decompress(ctx, d_stream, size, d_field, cap, d_ws, ws_bytes, stream) -
 
 def lopc_decompress_h(ctx, header: bytes, d_stream, size, d_field, cap, d_ws, ws_bytes,
                       stream) -> int:
-    buf = ctypes.create_string_buffer(bytes(header)[:HEADER_BYTES], HEADER_BYTES)
-    return load().lopc_decompress_h(ctx, buf, d_stream, size, d_field, cap, d_ws, ws_bytes,
+    h = header if type(header) is bytes and len(header) == HEADER_BYTES else \
+        ctypes.create_string_buffer(bytes(header)[:HEADER_BYTES], HEADER_BYTES)
+    return load().lopc_decompress_h(ctx, h, d_stream, size, d_field, cap, d_ws, ws_bytes,
                                     stream)
 
 
@@ -351,6 +352,26 @@ def _mode(mode) -> int:
     return int(mode)
 
 
+def _stream_handle(dev: torch.device) -> int:
+    """The current HIP stream of device `dev` as an integer handle."""
+    return torch._C._cuda_getCurrentRawStream(dev.index)
+
+
+_infos = {}
+
+
+def _stream_info_cached(hdr: bytes) -> dict:
+    """lopc_stream_info of a header, remembered per header (headers repeat
+    when the same fields are decompressed again)."""
+    v = _infos.get(hdr)
+    if v is None:
+        v = lopc_stream_info(hdr)
+        if len(_infos) > 4096:
+            _infos.clear()
+        _infos[hdr] = v
+    return v
+
+
 def _check_field(x: torch.Tensor):
     if not x.is_cuda:
         raise ValueError("field must be a device tensor")
@@ -391,7 +412,7 @@ def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = Fals
         out = torch.empty(cap, dtype=torch.uint8, device=dev)
     if workspace is None or workspace.numel() < wsz:
         workspace = torch.empty(wsz, dtype=torch.uint8, device=dev)
-    s = torch.cuda.current_stream(dev).cuda_stream
+    s = _stream_handle(dev)
     st, size, stt = lopc_compress(ctx, x.data_ptr(), code, tuple(x.shape), error_bound,
                                   _mode(mode), out.data_ptr(), out.numel(),
                                   workspace.data_ptr(), workspace.numel(), s, stats)
@@ -415,9 +436,9 @@ def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
         raise ValueError("stream must be a contiguous uint8 device tensor")
     if stream.numel() < HEADER_BYTES:
         raise LopcError(LOPC_E_FORMAT, "lopc_decompress")
-    hdr = bytes(header) if header is not None else \
+    hdr = (header if type(header) is bytes else bytes(header)) if header is not None else \
         stream[:HEADER_BYTES].cpu().numpy().tobytes()
-    info = lopc_stream_info(hdr)
+    info = _stream_info_cached(hdr)
     dev = stream.device
     ctx = context(dev.index) if ctx is None else ctx
     if out is None:
@@ -425,7 +446,7 @@ def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
     wsz = _sizes_for(ctx, info["shape"], info["dtype"])[2]
     if workspace is None or workspace.numel() < wsz:
         workspace = torch.empty(wsz, dtype=torch.uint8, device=dev)
-    s = torch.cuda.current_stream(dev).cuda_stream
+    s = _stream_handle(dev)
     st = lopc_decompress_h(ctx, hdr, stream.data_ptr(), stream.numel(), out.data_ptr(),
                            out.numel() * out.element_size(), workspace.data_ptr(),
                            workspace.numel(), s)
