@@ -33,37 +33,39 @@ LOPC_HD bool finite64(uint64_t u) {
 
 // Quantizer (Sec. IV-A): nearest integer to the exact real y*inv, ties to
 // even, saturated to +-(2^62 + 1).  The rounded product p and the exact
-// residual r = fma(y, inv, -p) give the real product p + r exactly.  The
-// rounding is done on the magnitude a = |p| (residual rr = +-r), where the
-// fraction a - floor(a) is exact; rounding p can only cross a half-integer h
-// if a == h, and then the sign of rr decides.
+// residual r = fma(y, inv, -p) give the real product p + r exactly.  Rounding
+// is monotone and half-integers below 2^52 are representable, so the real
+// product lies on the same side of every half-integer as p, or p is that
+// half-integer: rint(p) (ties to even) is the answer unless p is a
+// half-integer, and then the sign of r decides (r == 0: a true tie, which
+// rint already resolved to even).  From 2^52 on p is an integer and the
+// fraction of the real product is in r.
 LOPC_HD int64_t q_bin(double y, double inv) {
   const double two52 = 4503599627370496.0;
   const double two62 = 4611686018427387904.0;
   const int64_t sat = 4611686018427387905ll;
   double p = y * inv;
   if (!(fabs(p) <= two62)) return p < 0 ? -sat : sat;
+  if (fabs(p) < two52) {
+    double q = rint(p);
+    if (fabs(p - q) == 0.5) {
+      const double r = fma(y, inv, -p);
+      if (r != 0.0) q = r > 0.0 ? p + 0.5 : p - 0.5;
+    }
+    return (int64_t)q;
+  }
   double r = fma(y, inv, -p);
   const bool neg = p < 0.0;
   const double a = fabs(p);
   const double rr = neg ? -r : r;
-  int64_t q;
-  if (a < two52) {
-    double fl = floor(a);
-    double fr = a - fl;
-    q = (int64_t)fl;
-    bool up = fr > 0.5 || (fr == 0.5 && (rr > 0.0 || (rr == 0.0 && (q & 1))));
-    q += up ? 1 : 0;
-  } else {
-    // a is an integer; the fraction of the magnitude is in rr
-    double t = fabs(rr);
-    double ft = floor(t);
-    double frt = t - ft;
-    int64_t cand = rr >= 0.0 ? (int64_t)a + (int64_t)ft : (int64_t)a - (int64_t)ft;
-    int64_t step = rr >= 0.0 ? 1 : -1;
-    if (frt > 0.5 || (frt == 0.5 && (cand & 1))) cand += step;
-    q = cand;
-  }
+  // a is an integer; the fraction of the magnitude is in rr
+  double t = fabs(rr);
+  double ft = floor(t);
+  double frt = t - ft;
+  int64_t cand = rr >= 0.0 ? (int64_t)a + (int64_t)ft : (int64_t)a - (int64_t)ft;
+  int64_t step = rr >= 0.0 ? 1 : -1;
+  if (frt > 0.5 || (frt == 0.5 && (cand & 1))) cand += step;
+  int64_t q = cand;
   if (q > sat) q = sat;
   return neg ? -q : q;
 }
@@ -73,18 +75,14 @@ LOPC_HD int64_t q_bin(double y, double inv) {
 // larger products return +-2^31, which is outside the float32 bin range.
 LOPC_HD int64_t q_bin32(double y, double inv) {
   const double two31 = 2147483648.0;
-  double p = y * inv;
-  const bool neg = p < 0.0;
-  const double a = fabs(p);
-  if (!(a < two31)) return neg ? -(int64_t)two31 : (int64_t)two31;
-  double r = fma(y, inv, -p);
-  const double rr = neg ? -r : r;
-  const double fl = floor(a);
-  const double fr = a - fl;
-  int32_t q = (int32_t)fl;
-  bool up = fr > 0.5 || (fr == 0.5 && (rr > 0.0 || (rr == 0.0 && (q & 1))));
-  int64_t v = (int64_t)q + (up ? 1 : 0);
-  return neg ? -v : v;
+  const double p = y * inv;
+  if (!(fabs(p) < two31)) return p < 0.0 ? -(int64_t)two31 : (int64_t)two31;
+  double q = rint(p);
+  if (fabs(p - q) == 0.5) {
+    const double r = fma(y, inv, -p);
+    if (r != 0.0) q = r > 0.0 ? p + 0.5 : p - 0.5;
+  }
+  return (int64_t)(int32_t)q;
 }
 
 }  // namespace lopc
