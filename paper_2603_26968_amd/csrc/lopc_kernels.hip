@@ -258,52 +258,133 @@ __device__ __forceinline__ unsigned long long* relax_total(uint32_t* counters) {
   return (unsigned long long*)(counters + kRelaxWord);
 }
 
+// Lower neighbours of a point as LDS offsets for the relaxation: up to three
+// 10-bit fields (offset + 512; an unused field holds 512, the point itself),
+// the count in bits 30-31; more than three: kDense (the full mask is used).
+constexpr uint32_t kDense = 0xffffffffu;
+template <int TZ, int TY, int TX>
+__device__ __forceinline__ uint32_t walk_code(uint32_t m) {
+  using G = TileGeom<TZ, TY, TX>;
+  const uint32_t n = (uint32_t)__popc(m);
+  if (n > 3) return kDense;
+  uint32_t code = n << 30 | 512u | 512u << 10 | 512u << 20;
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    if (m) {
+      const int j = __builtin_ctz(m);
+      m &= m - 1;
+      code += (uint32_t)off_lin(j, G::HX, G::HY * G::HX) << (10 * f);
+    }
+  }
+  return code;
+}
+
 // Local fixed point of the tile (masks of the owned points in registers):
 // Gauss-Seidel passes over the owned points until none rises; the halo is
-// fixed.  The neighbour values of a point are loaded unconditionally and
-// combined under its mask, so the loads of a point issue back to back
-// instead of one dependent load per set mask bit.  Adds the pass count to one
-// of 64 statistics slots itot[t % 64].
+// fixed.  Only points with a same-bin lower neighbour can rise; in a 3D
+// tile whose wave holds at most 64 of them over its slots, the wave first
+// gathers them into one lane each (a per-wave list in LDS), so that a pass
+// costs one step per wave instead of one per slot, and each listed point
+// with at most three lower neighbours reads them at precomputed offsets
+// (walk_code: three loads issued back to back).  Otherwise a pass visits the
+// slots and walks the mask bits.  When some lane of the wave has more than
+// three lower neighbours, the wave loads all stencil neighbours and selects
+// under the mask.  Adds the pass count to one of 64 statistics slots
+// itot[t % 64].
 template <int TZ, int TY, int TX>
 __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
                       unsigned long long* itot, uint32_t t) {
   using G = TileGeom<TZ, TY, TX>;
   constexpr int NJ = TZ == 1 ? 6 : 14;  // 2D tiles: the in-plane offsets only
+  static_assert(G::H < 4096, "halo index in 12 bits");
+  __shared__ uint32_t wl_pt[kThreads], wl_cd[kThreads];  // wave w: entries [64w, 64w + 64)
+  // a listed point: rise to the best of its lower neighbours (a positive
+  // offset, even j, reaches a higher index and adds one)
+  auto step = [&](int li, uint32_t m, uint32_t cd) -> bool {
+    const uint32_t cur = S[li];
+    uint32_t best = cur;
+    if (__ballot(cd == kDense)) {
+      uint32_t v[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        v[j] = S[li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2]];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const uint32_t c = v[j] + ((j & 1) ? 0u : 1u);
+        best = ((m >> j) & 1u) && c > best ? c : best;
+      }
+    } else {
+      const int o0 = (int)(cd & 1023u) - 512, o1 = (int)((cd >> 10) & 1023u) - 512,
+                o2 = (int)((cd >> 20) & 1023u) - 512;
+      const uint32_t c0 = S[li + o0] + (o0 > 0), c1 = S[li + o1] + (o1 > 0),
+                     c2 = S[li + o2] + (o2 > 0);
+      best = max(max(best, c0), max(c1, c2));
+    }
+    if (best > cur) {
+      S[li] = best;
+      return true;
+    }
+    return false;
+  };
+  // gather this wave's candidate points (3D tiles; in 2D fields same-bin
+  // neighbours are common and the lists rarely fit)
+  constexpr bool kList = TZ > 1;
+  uint32_t n = kList ? 0u : 65u;  // wave-uniform
+#pragma unroll
+  for (int k = 0; k < (kList ? G::PER : 0); ++k) {
+    const uint64_t act = __ballot(mk[k] != 0);
+    const uint32_t c = (uint32_t)__popcll(act);
+    if (n + c <= 64 && mk[k]) {
+      const uint32_t pos = n + (uint32_t)__popcll(act & ((1ull << lane()) - 1ull));
+      wl_pt[wave() * 64 + pos] =
+          (uint32_t)G::local(threadIdx.x + k * kThreads) | (uint32_t)mk[k] << 12;
+      wl_cd[wave() * 64 + pos] = walk_code<TZ, TY, TX>(mk[k]);
+    }
+    n += c;
+  }
+  const bool listed = n <= 64;
+  uint32_t my_pt = 0, my_cd = 0;
+  __builtin_amdgcn_wave_barrier();
+  if (listed && (uint32_t)lane() < n) {
+    my_pt = wl_pt[wave() * 64 + lane()];
+    my_cd = wl_cd[wave() * 64 + lane()];
+  }
   int iters = 0;
   for (;;) {
     int changed = 0;
+    if (listed) {
+      if (my_pt && step((int)(my_pt & 4095u), my_pt >> 12, my_cd)) changed = 1;
+    } else {
 #pragma unroll 2
-    for (int k = 0; k < G::PER; ++k) {
-      const uint32_t m = mk[k];
-      if (!m) continue;
-      const int li = G::local(threadIdx.x + k * kThreads);
-      const uint32_t cur = S[li];
-      uint32_t best = cur;
-      // even j: the neighbour has the higher index, so it adds one
-      if (__ballot(__popc(m) > 3)) {
-        // some lane of the wave has many lower neighbours: load them all at
-        // once and select under the mask
-        uint32_t v[NJ];
+      for (int k = 0; k < G::PER; ++k) {
+        const uint32_t m = mk[k];
+        if (!m) continue;
+        const int li = G::local(threadIdx.x + k * kThreads);
+        const uint32_t cur = S[li];
+        uint32_t best = cur;
+        if (__ballot(__popc(m) > 3)) {
+          uint32_t v[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-          v[j] = S[li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2]];
+          for (int j = 0; j < NJ; ++j)
+            v[j] = S[li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2]];
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const uint32_t c = v[j] + ((j & 1) ? 0u : 1u);
-          best = ((m >> j) & 1u) && c > best ? c : best;
+          for (int j = 0; j < NJ; ++j) {
+            const uint32_t c = v[j] + ((j & 1) ? 0u : 1u);
+            best = ((m >> j) & 1u) && c > best ? c : best;
+          }
+        } else {
+          uint32_t mm = m;
+          while (mm) {
+            const int j = __builtin_ctz(mm);
+            mm &= mm - 1;
+            const uint32_t c = S[li + off_lin(j, G::HX, G::HY * G::HX)] + ((j & 1) ? 0u : 1u);
+            best = c > best ? c : best;
+          }
         }
-      } else {
-        uint32_t mm = m;
-        while (mm) {
-          const int j = __builtin_ctz(mm);
-          mm &= mm - 1;
-          const uint32_t c = S[li + off_lin(j, G::HX, G::HY * G::HX)] + ((j & 1) ? 0u : 1u);
-          best = c > best ? c : best;
+        if (best > cur) {
+          S[li] = best;
+          changed = 1;
         }
-      }
-      if (best > cur) {
-        S[li] = best;
-        changed = 1;
       }
     }
     if (!__syncthreads_or(changed)) break;
