@@ -80,15 +80,7 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint64_t v) {
   return (uint32_t)((t * 0x0102040810204080ull) >> 56);
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t c) {
-  uint32_t x = c;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, 64);
-    if (lane() >= d) x += y;
-  }
-  return x;
-}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t c) { return wave_scan_u32(c); }
 
 // Turn the per-round totals sc.rpre[0..rounds) into exclusive prefixes and
 // return the grand total.  Call between barriers.
@@ -1052,23 +1044,14 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
       }
       // negabinary -> delta; inclusive prefix within the group of 64 words
       Word d = (g * 64 + lane() < nc) ? (Word)((w ^ Mk) - Mk) : (Word)0;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        Word y = __shfl_up(d, o, 64);
-        if (lane() >= o) d += y;
-      }
+      d = wave_scan<Word>(d);
       wv[i] = d;
       if (lane() == 63 && g < G) gsum[g] = (uint64_t)d;
     }
     __syncthreads();
     if (threadIdx.x < 64) {
       uint64_t v = threadIdx.x < G ? gsum[threadIdx.x] : 0ull;
-      uint64_t x = v;
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        uint64_t y = __shfl_up(x, o, 64);
-        if (lane() >= o) x += y;
-      }
+      const uint64_t x = wave_scan_u64(v);
       if (threadIdx.x < G) gsum[threadIdx.x] = x - v;  // exclusive
     }
     __syncthreads();

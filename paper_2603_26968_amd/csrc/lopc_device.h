@@ -82,16 +82,48 @@ __device__ __forceinline__ int off_lin(int j, int hx, int hxy) {
 }
 
 // ------------------------------------------------------------------ scans
+// Wave-wide inclusive prefix sums through DPP lane moves instead of the LDS
+// crossbar: shifts by 1, 2, 4 and 8 lanes inside each row of 16 (lanes
+// shifted in from outside the row read 0), then the rows are joined by
+// broadcasting lane 15 into rows 1 and 3 and lane 31 into rows 2 and 3.
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, ZERO);
+}
+template <int CTRL, int ROWS, bool ZERO>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+  return (uint64_t)dpp_u32<CTRL, ROWS, ZERO>((uint32_t)x) |
+         (uint64_t)dpp_u32<CTRL, ROWS, ZERO>((uint32_t)(x >> 32)) << 32;
+}
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x) {
+  x += dpp_u32<0x111, 0xf, true>(x);  // row_shr:1
+  x += dpp_u32<0x112, 0xf, true>(x);  // row_shr:2
+  x += dpp_u32<0x114, 0xf, true>(x);  // row_shr:4
+  x += dpp_u32<0x118, 0xf, true>(x);  // row_shr:8
+  x += dpp_u32<0x142, 0xa, false>(x);  // row_bcast:15
+  x += dpp_u32<0x143, 0xc, false>(x);  // row_bcast:31
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_scan_u64(uint64_t x) {
+  x += dpp_u64<0x111, 0xf, true>(x);
+  x += dpp_u64<0x112, 0xf, true>(x);
+  x += dpp_u64<0x114, 0xf, true>(x);
+  x += dpp_u64<0x118, 0xf, true>(x);
+  x += dpp_u64<0x142, 0xa, false>(x);
+  x += dpp_u64<0x143, 0xc, false>(x);
+  return x;
+}
+template <typename V>
+__device__ __forceinline__ V wave_scan(V x) {
+  if constexpr (sizeof(V) == 8) return (V)wave_scan_u64((uint64_t)x);
+  else return (V)wave_scan_u32((uint32_t)x);
+}
+
 // Exclusive scan of v over a block of NW waves; sh needs NW + 1 slots;
 // total receives the block sum.  Every thread of the block must call it.
 template <typename V, int NW = kWaves>
 __device__ V block_excl_scan(V v, V* sh, V& total) {
-  V x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    V y = __shfl_up(x, d, 64);
-    if (lane() >= d) x += y;
-  }
+  V x = wave_scan<V>(v);
   if (lane() == 63) sh[wave()] = x;
   __syncthreads();
   if (threadIdx.x == 0) {
