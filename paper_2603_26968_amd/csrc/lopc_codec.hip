@@ -165,8 +165,9 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
     } else if (W == 4) {
       mi = ((uint32_t)v != 0u) | ((uint32_t)((v >> 32) != 0ull) << 1);
       ci = __popc(mi);
-      uint32_t b = mi | (__shfl_down(mi, 1, 64) << 2) | (__shfl_down(mi, 2, 64) << 4) |
-                   (__shfl_down(mi, 3, 64) << 6);
+      // lanes 4q+1..4q+3 lie in the row of lane 4q: DPP row shifts left
+      uint32_t b = mi | (dpp_u32<0x101, 0xf, true>(mi) << 2) |
+                   (dpp_u32<0x102, 0xf, true>(mi) << 4) | (dpp_u32<0x103, 0xf, true>(mi) << 6);
       if ((lane() & 3) == 0 && u < NU) sc.lv0[u / 4] = (uint8_t)b;
     } else {
       mi = v != 0ull;
@@ -278,7 +279,7 @@ __device__ bool level_decode_w(const uint8_t* par, uint32_t n, const uint8_t* in
     c += (uint32_t)__popc(pb[q]);
   }
   const uint32_t incl = wave_incl_scan(c);
-  const uint32_t tot = __shfl(incl, 63, 64);
+  const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
   if (pos + tot > in_len) return false;
   uint32_t e = incl - c;
 #pragma unroll
@@ -343,7 +344,7 @@ __device__ void rze_decode_head(const uint8_t* in, uint32_t in_len, uint32_t ite
     }
     const uint32_t incl = wave_incl_scan(cnt);
     if ((uint32_t)lane() < rounds) sc.rpre[lane()] = incl - cnt;
-    const uint32_t npay = __shfl(incl, 63, 64);
+    const uint32_t npay = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     ok = pos + npay * W == in_len;
   }
   if (lane() == 0) {
@@ -401,7 +402,7 @@ __device__ __forceinline__ bool rze_decode(const uint8_t* in, uint32_t in_len, u
     if (G && v) pm |= 1ull << (u / G);
   }
   if (G) {
-    for (int d = 32; d > 0; d >>= 1) pm |= __shfl_xor(pm, d, 64);
+    pm = wave_reduce(pm, OpOr{});
     if (lane() == 0) sc.orv[wave()] = pm;
   }
   __syncthreads();
@@ -470,7 +471,7 @@ __device__ void bit_decode(const uint64_t* U, uint32_t G, uint64_t planes,
 
 __device__ __forceinline__ uint64_t block_or(uint64_t v, Scratch& sc) {
   // wave OR by ballots over the set bits is costly; reduce through LDS
-  for (int d = 32; d > 0; d >>= 1) v |= __shfl_xor(v, d, 64);
+  v = wave_reduce(v, OpOr{});
   if (lane() == 0) sc.orv[wave()] = v;
   __syncthreads();
   uint64_t r = 0;
@@ -1119,11 +1120,8 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
       bmax = b > bmax ? b : bmax;
     }
   }
-  for (int d = 32; d > 0; d >>= 1) {
-    int64_t a = __shfl_xor(bmin, d, 64), c2 = __shfl_xor(bmax, d, 64);
-    bmin = a < bmin ? a : bmin;
-    bmax = c2 > bmax ? c2 : bmax;
-  }
+  bmin = wave_reduce(bmin, OpMin{});
+  bmax = wave_reduce(bmax, OpMax{});
   if (lane() == 0) {
     sc.orv[wave()] = (uint64_t)bmin;
     sc.scan64[wave()] = (uint64_t)bmax;

@@ -119,6 +119,53 @@ __device__ __forceinline__ V wave_scan(V x) {
   else return (V)wave_scan_u32((uint32_t)x);
 }
 
+// The same lane moves for an idempotent operation (or, min, max): a lane
+// with no source keeps its own value, and the scan pattern leaves the whole
+// wave's result in lane 63, read back as a wave-uniform value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_keep_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS, typename V>
+__device__ __forceinline__ V dpp_keep(V x) {
+  if constexpr (sizeof(V) == 8) {
+    const uint64_t u = (uint64_t)x;
+    return (V)((uint64_t)dpp_keep_u32<CTRL, ROWS>((uint32_t)u) |
+               (uint64_t)dpp_keep_u32<CTRL, ROWS>((uint32_t)(u >> 32)) << 32);
+  } else {
+    return (V)dpp_keep_u32<CTRL, ROWS>((uint32_t)x);
+  }
+}
+template <typename V, typename Op>
+__device__ __forceinline__ V wave_reduce(V x, Op op) {
+  x = op(x, dpp_keep<0x111, 0xf>(x));
+  x = op(x, dpp_keep<0x112, 0xf>(x));
+  x = op(x, dpp_keep<0x114, 0xf>(x));
+  x = op(x, dpp_keep<0x118, 0xf>(x));
+  x = op(x, dpp_keep<0x142, 0xa>(x));
+  x = op(x, dpp_keep<0x143, 0xc>(x));
+  if constexpr (sizeof(V) == 8) {
+    const uint64_t u = (uint64_t)x;
+    return (V)((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63) |
+               (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63)
+                   << 32);
+  } else {
+    return (V)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  }
+}
+struct OpOr {
+  template <typename V>
+  __device__ V operator()(V a, V b) const { return a | b; }
+};
+struct OpMin {
+  template <typename V>
+  __device__ V operator()(V a, V b) const { return b < a ? b : a; }
+};
+struct OpMax {
+  template <typename V>
+  __device__ V operator()(V a, V b) const { return b > a ? b : a; }
+};
+
 // Exclusive scan of v over a block of NW waves; sh needs NW + 1 slots;
 // total receives the block sum.  Every thread of the block must call it.
 template <typename V, int NW = kWaves>

@@ -53,12 +53,8 @@ __device__ __forceinline__ void minmax_body(const typename Traits<K>::Raw* x, ui
     for (int k = 0; k < V; ++k) take(u[k]);
   }
   for (uint32_t t = nv * V + blk * kThreads + threadIdx.x; t < n; t += stride) take(x[t]);
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) {
-    const int64_t a = __shfl_xor(lo, d, 64), b = __shfl_xor(hi, d, 64);
-    lo = a < lo ? a : lo;
-    hi = b > hi ? b : hi;
-  }
+  lo = wave_reduce(lo, OpMin{});
+  hi = wave_reduce(hi, OpMax{});
   __shared__ int64_t slo[kWaves], shi[kWaves];
   if (lane() == 0) {
     slo[wave()] = lo;
@@ -215,8 +211,7 @@ __device__ __forceinline__ uint32_t out_dirs(int i, uint32_t bits) {
 // OR of v over the workgroup (every thread gets it)
 __device__ __forceinline__ uint32_t block_or32(uint32_t v) {
   __shared__ uint32_t w[kWaves];
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) v |= __shfl_xor(v, d, 64);
+  v = wave_reduce(v, OpOr{});
   if (lane() == 0) w[wave()] = v;
   __syncthreads();
   uint32_t r = 0;
