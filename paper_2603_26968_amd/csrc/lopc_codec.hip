@@ -869,13 +869,43 @@ __device__ __forceinline__ void offsets_body(const uint8_t* stream, uint32_t nch
   if (threadIdx.x == 0 && total != body_bytes) set_status(prm, ST_FORMAT);
 }
 
-// Single field: also starts the decoder's status word (no separate clear).
-__global__ __launch_bounds__(kThreads) void k_offsets(
+// Single field, one 1024-thread block: the same scan, four sizes per thread
+// per pass (one 16-byte read where the table allows; the table starts 4
+// bytes past a 16-byte boundary of the stream only if the stream does), and
+// the start of the decoder's status word (no separate clear).
+constexpr int kOfT = 1024;
+__global__ __launch_bounds__(kOfT) void k_offsets(
     const uint8_t* stream, uint32_t nch, uint64_t body_bytes,
     uint64_t* offsets, Params* prm) {
+  __shared__ uint64_t sh[kOfT / 64 + 1];
   if (threadIdx.x == 0) prm->status = 0;
-  __syncthreads();
-  offsets_body(stream, nch, body_bytes, offsets, prm);
+  const uint32_t* tab = (const uint32_t*)(stream + kHeaderBytes);
+  const bool vec = ((uintptr_t)tab & 15u) == 0;
+  uint64_t carry = 0;
+  for (uint32_t t0 = 0; t0 < nch; t0 += 4 * kOfT) {
+    const uint32_t i = t0 + 4 * threadIdx.x;
+    uint32_t sz[4];
+    if (vec && i + 3 < nch) {
+      const uint4 a = *(const uint4*)(tab + i);
+      sz[0] = a.x;
+      sz[1] = a.y;
+      sz[2] = a.z;
+      sz[3] = a.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sz[k] = i + k < nch ? tab[i + k] : 0u;
+    }
+    const uint64_t sum = (uint64_t)sz[0] + sz[1] + sz[2] + sz[3];
+    uint64_t total;
+    uint64_t off = carry + block_excl_scan<uint64_t, kOfT / 64>(sum, sh, total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i + k < nch) offsets[i + k] = off;
+      off += sz[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0 && carry != body_bytes) set_status(prm, ST_FORMAT);
 }
 
 // Totals of the bins and subbin parts over all chunks (statistics only).
@@ -1370,7 +1400,7 @@ hipError_t launch_sum_parts(const uint32_t* parts, uint32_t nch, Params* prm,
 hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
                           uint64_t body_bytes, uint64_t* offsets, Params* prm,
                           hipStream_t s, Ev ev) {
-  hipExtLaunchKernelGGL(k_offsets, dim3(1), dim3(kThreads), 0, s, ev.a, ev.b, 0, stream, nch,
+  hipExtLaunchKernelGGL(k_offsets, dim3(1), dim3(kOfT), 0, s, ev.a, ev.b, 0, stream, nch,
                         body_bytes, offsets, prm);
   return hipGetLastError();
 }

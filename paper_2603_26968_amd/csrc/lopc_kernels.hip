@@ -88,66 +88,69 @@ __device__ __forceinline__ void params_body(int mode, double eb, const int64_t* 
                             Params* prm, uint8_t* stream, uint64_t cap, int ndim,
                             int64_t d0, int64_t d1, int64_t d2) {
   using Tr = Traits<K>;
-  __shared__ int64_t slo[kThreads], shi[kThreads];
+  __shared__ int64_t slo[kWaves], shi[kWaves];
+  __shared__ uint32_t hw[kHeaderBytes / 4];
   int64_t lo = INT64_MAX, hi = INT64_MIN;
   if (mode == 1)
     for (int b = threadIdx.x; b < nblocks; b += kThreads) {
-      lo = min(lo, part[2 * b]);
-      hi = max(hi, part[2 * b + 1]);
+      const longlong2 p = ((const longlong2*)part)[b];
+      lo = min(lo, (int64_t)p.x);
+      hi = max(hi, (int64_t)p.y);
     }
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
+  lo = wave_reduce(lo, OpMin{});
+  hi = wave_reduce(hi, OpMax{});
+  if (lane() == 0) {
+    slo[wave()] = lo;
+    shi[wave()] = hi;
+  }
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      slo[threadIdx.x] = min(slo[threadIdx.x], slo[threadIdx.x + s]);
-      shi[threadIdx.x] = max(shi[threadIdx.x], shi[threadIdx.x + s]);
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWaves; ++w) {
+      lo = min(lo, slo[w]);
+      hi = max(hi, shi[w]);
     }
-    __syncthreads();
+    double e = eb;
+    if (mode == 1) {
+      // NOA: eps = eb * (max - min), all in binary64 (Sec. IV-A)
+      double vlo = Tr::to_double(Tr::unkey(lo));
+      double vhi = Tr::to_double(Tr::unkey(hi));
+      double range = vhi - vlo;
+      e = eb * range;
+      prm->kmin = lo;
+      prm->kmax = hi;
+    }
+    double v = 1.0 / e;
+    bool ok = (e > 0.0) && finite64((uint64_t)__double_as_longlong(e)) &&
+              finite64((uint64_t)__double_as_longlong(v));
+    if (ok && fma(v, e, -1.0) < 0.0)
+      v = __longlong_as_double(__double_as_longlong(v) + 1);  // next up
+    ok = ok && finite64((uint64_t)__double_as_longlong(v));
+    if (!ok) {
+      set_status(prm, ST_BOUND);
+      e = 1.0;
+      v = 1.0;
+    }
+    prm->eb = eb;
+    prm->eps = e;
+    prm->inv = v;
+    prm->winv = 1.0 / v;
+    // the stream header as 16 little-endian words
+    const uint64_t q[8] = {(uint64_t)kMagic | (uint64_t)(kVersion | (K == 4 ? 0u : 1u) << 16 |
+                                                           (uint32_t)ndim << 24) << 32,
+                           (uint64_t)d0, (uint64_t)d1, (uint64_t)d2,
+                           (uint64_t)(uint32_t)mode | (uint64_t)kChunkBytes << 32,
+                           (uint64_t)__double_as_longlong(eb), (uint64_t)__double_as_longlong(e),
+                           (uint64_t)__double_as_longlong(v)};
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      hw[2 * w] = (uint32_t)q[w];
+      hw[2 * w + 1] = (uint32_t)(q[w] >> 32);
+    }
   }
-  if (threadIdx.x != 0) return;
-  double e = eb;
-  if (mode == 1) {
-    // NOA: eps = eb * (max - min), all in binary64 (Sec. IV-A)
-    double vlo = Tr::to_double(Tr::unkey(slo[0]));
-    double vhi = Tr::to_double(Tr::unkey(shi[0]));
-    double range = vhi - vlo;
-    e = eb * range;
-    prm->kmin = slo[0];
-    prm->kmax = shi[0];
-  }
-  double v = 1.0 / e;
-  bool ok = (e > 0.0) && finite64((uint64_t)__double_as_longlong(e)) &&
-            finite64((uint64_t)__double_as_longlong(v));
-  if (ok && fma(v, e, -1.0) < 0.0)
-    v = __longlong_as_double(__double_as_longlong(v) + 1);  // next up
-  ok = ok && finite64((uint64_t)__double_as_longlong(v));
-  if (!ok) {
-    set_status(prm, ST_BOUND);
-    e = 1.0;
-    v = 1.0;
-  }
-  prm->eb = eb;
-  prm->eps = e;
-  prm->inv = v;
-  prm->winv = 1.0 / v;
-  {
-    uint8_t* h = prm->header;
-    put_bytes(h + 0, kMagic, 4);
-    put_bytes(h + 4, kVersion, 2);
-    h[6] = (uint8_t)(K == 4 ? 0 : 1);
-    h[7] = (uint8_t)ndim;
-    put_bytes(h + 8, (uint64_t)d0, 8);
-    put_bytes(h + 16, (uint64_t)d1, 8);
-    put_bytes(h + 24, (uint64_t)d2, 8);
-    h[32] = (uint8_t)mode;
-    h[33] = h[34] = h[35] = 0;
-    put_bytes(h + 36, kChunkBytes, 4);
-    put_bytes(h + 40, (uint64_t)__double_as_longlong(eb), 8);
-    put_bytes(h + 48, (uint64_t)__double_as_longlong(e), 8);
-    put_bytes(h + 56, (uint64_t)__double_as_longlong(v), 8);
-    if (cap >= kHeaderBytes)
-      for (int i = 0; i < (int)kHeaderBytes; ++i) stream[i] = h[i];
+  __syncthreads();
+  if (threadIdx.x < kHeaderBytes / 4) {
+    ((uint32_t*)prm->header)[threadIdx.x] = hw[threadIdx.x];
+    if (cap >= kHeaderBytes) ((uint32_t*)stream)[threadIdx.x] = hw[threadIdx.x];
   }
 }
 
