@@ -235,24 +235,17 @@ __device__ uint32_t rze_encode(const uint64_t* U, uint32_t len, uint32_t nua,
   return out_len;
 }
 
-// Inverse of rze_encode: in[0, in_len) -> the first `len` bytes of U (units
-// rounded up; bytes past len are zero).  Returns false on malformed input;
-// never reads outside [in, in + in_len).  If G > 0 the units are bit planes
-// of G groups and sc.planes receives the mask of planes holding a nonzero
-// unit.
+// Item bits of unit u (of NU, `items` items in all) taken from its level-0
+// bitmap byte b0.
 template <int W>
-__device__ __forceinline__ uint32_t unit_bits(const Scratch& sc, uint32_t u, uint32_t NU,
-                                              uint32_t items) {
-  if (u >= NU) return 0u;
+__device__ __forceinline__ uint32_t unit_bits(uint32_t b0, uint32_t u, uint32_t items) {
   if (W == 1) {
-    uint32_t mi = sc.lv0[u];
-    uint32_t valid = items - u * 8;
-    if (valid < 8) mi &= (1u << valid) - 1;
-    return mi;
+    const uint32_t valid = items - u * 8;
+    return valid < 8 ? b0 & ((1u << valid) - 1) : b0;
   } else if (W == 4) {
-    return (sc.lv0[u / 4] >> (2 * (u % 4))) & 3u;
+    return (b0 >> (2 * (u % 4))) & 3u;
   } else {
-    return (sc.lv0[u / 8] >> (u % 8)) & 1u;
+    return (b0 >> (u % 8)) & 1u;
   }
 }
 
@@ -307,45 +300,59 @@ __device__ bool level_decode_w(const uint8_t* par, uint32_t n, const uint8_t* in
   return true;
 }
 
-// Front half of an RZE decode, on wave 0 alone: the top bitmap, every level
-// down to the items' bitmap lv0, the payload offset of every round of 64
-// units (sc.rpre, exclusive) and the consistency of the total with in_len.
-// Leaves sc.nkept[0] = ok and sc.nkept[1] = offset of the payload.
+// The payload of one unit: its c kept items at p (c * W bytes, any
+// alignment) placed at the items of mask m, the others zero.  Reads the
+// aligned words covering those bytes only (never past p + c * W rounded up
+// to a word), joins them into the 8 bytes from p with byte-align moves, then
+// for W = 1 spreads the bytes with one byte permute per half: the selector
+// of output byte b is the number of mask bits below b when bit b is set,
+// else 0x0c (the permute's zero byte).
 template <int W>
-__device__ void rze_decode_head(const uint8_t* in, uint32_t in_len, uint32_t items,
-                                uint32_t rounds, Scratch& sc) {
+__device__ __forceinline__ uint64_t unit_payload(const uint8_t* p, uint32_t m, uint32_t c) {
+  if (!m) return 0;
+  const uint32_t mis = (uint32_t)(uintptr_t)p & 3u;
+  const uint32_t* q = (const uint32_t*)(p - mis);
+  const uint32_t nd = (mis + c * W + 3) / 4;  // 1..3 words
+  const uint32_t w0 = q[0];
+  const uint32_t w1 = nd > 1 ? q[1] : 0u;
+  const uint32_t w2 = nd > 2 ? q[2] : 0u;
+  const uint32_t x0 = __builtin_amdgcn_alignbyte(w1, w0, mis);
+  const uint32_t x1 = __builtin_amdgcn_alignbyte(w2, w1, mis);
+  if (W == 8) return (uint64_t)x0 | (uint64_t)x1 << 32;
+  if (W == 4) {
+    const uint32_t lo = (m & 1) ? x0 : 0u;
+    const uint32_t hi = (m & 2) ? ((m & 1) ? x1 : x0) : 0u;
+    return (uint64_t)lo | (uint64_t)hi << 32;
+  }
+  // bit i of each nibble of m to bit 0 of byte i (the four shifted copies
+  // do not overlap, so nothing carries)
+  const uint32_t slo = ((m & 0xfu) * 0x00204081u) & 0x01010101u;
+  const uint32_t shi = (((m >> 4) & 0xfu) * 0x00204081u) & 0x01010101u;
+  // inclusive counts per byte, then exclusive: the selector of a set byte
+  const uint32_t ilo = slo * 0x01010101u;
+  const uint32_t ihi = shi * 0x01010101u + (uint32_t)__popc(m & 0xfu) * 0x01010101u;
+  const uint32_t sel_lo = ((ilo - slo) & (slo * 0xffu)) | ((slo ^ 0x01010101u) * 0x0cu);
+  const uint32_t sel_hi = ((ihi - shi) & (shi * 0xffu)) | ((shi ^ 0x01010101u) * 0x0cu);
+  return (uint64_t)__builtin_amdgcn_perm(x1, x0, sel_lo) |
+         (uint64_t)__builtin_amdgcn_perm(x1, x0, sel_hi) << 32;
+}
+
+// Upper levels of an RZE decode, on wave 0 alone: the top bitmap and every
+// level down to level 1 (the bitmap of the level-0 bitmap) into sc.lv1, zero
+// past its last byte.  Leaves sc.nkept[0] = ok and sc.nkept[1] = offset of
+// the level-0 kept bytes (with a single level: of the payload).
+__device__ void rze_decode_upper(const uint8_t* in, uint32_t in_len, uint32_t items,
+                                 Scratch& sc) {
   const int top = rze_top(items);
   const uint32_t sz_top = lvl_size(items, top);
   bool ok = sz_top <= in_len;
   uint32_t pos = sz_top;
-  if (ok) {
+  if (ok && top >= 1) {
     uint8_t* tb = lvl(sc, top);
     if (lane() < 16) tb[lane()] = (uint32_t)lane() < sz_top ? in[lane()] : (uint8_t)0;
     __builtin_amdgcn_wave_barrier();
-    for (int l = top - 1; l >= 0 && ok; --l)
+    for (int l = top - 1; l >= 1 && ok; --l)
       ok = level_decode_w(lvl(sc, l + 1), lvl_size(items, l), in, pos, in_len, lvl(sc, l));
-  }
-  if (ok) {
-    // items of round r: bits [64r * 8/W, 64(r + 1) * 8/W) of lv0, i.e. 8/W
-    // 64-bit words; bits from `items` on do not count
-    constexpr uint32_t WPR = 8 / W;
-    const uint64_t* lw = (const uint64_t*)sc.lv0;
-    uint32_t cnt = 0;
-    if ((uint32_t)lane() < rounds) {
-#pragma unroll
-      for (uint32_t q = 0; q < WPR; ++q) {
-        const uint32_t w = (uint32_t)lane() * WPR + q;
-        if (64ull * w < items) {
-          const uint64_t valid = items - 64ull * w;
-          const uint64_t m = valid >= 64 ? ~0ull : ((1ull << valid) - 1ull);
-          cnt += (uint32_t)__popcll(lw[w] & m);
-        }
-      }
-    }
-    const uint32_t incl = wave_incl_scan(cnt);
-    if ((uint32_t)lane() < rounds) sc.rpre[lane()] = incl - cnt;
-    const uint32_t npay = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    ok = pos + npay * W == in_len;
   }
   if (lane() == 0) {
     sc.nkept[0] = ok ? 1u : 0u;
@@ -357,47 +364,99 @@ __device__ void rze_decode_head(const uint8_t* in, uint32_t in_len, uint32_t ite
 // rounded up; bytes past len are zero).  Returns false on malformed input;
 // never reads outside [in, in + in_len).  If G > 0 the units are bit planes
 // of G groups and sc.planes receives the mask of planes holding a nonzero
-// unit.  Three block barriers: after the front half (wave 0), after the
-// payload, after the plane mask.
+// unit.  Wave 0 decodes the levels above level 0 (small); then every wave
+// expands the level-0 bitmap bytes of its own rounds of 64 units straight
+// into registers (a byte's position among the kept bytes is a prefix count
+// over level 1) and counts their items; after the per-round counts are
+// exchanged, the same lanes fetch their units' payload.  Block barriers:
+// after the upper levels, after the round counts, after the payload, after
+// the plane mask.
 template <int W>
 __device__ __forceinline__ bool rze_decode(const uint8_t* in, uint32_t in_len, uint32_t len,
                            uint64_t* U, Scratch& sc, uint32_t G) {
+  constexpr int kRPW = (int)(kMaxRounds / kCW);  // rounds per wave at most
   const uint32_t NU = (len + 7) / 8;
   const uint32_t items = len / W;
   const uint32_t rounds = (NU + 63) / 64;
-  if (wave() == 0) rze_decode_head<W>(in, in_len, items, rounds, sc);
+  const int top = rze_top(items);
+  const uint32_t n0 = lvl_size(items, 0);  // level-0 bitmap bytes
+  if (wave() == 0) rze_decode_upper(in, in_len, items, sc);
   __syncthreads();
   if (!sc.nkept[0]) return false;
-  const uint32_t pos = sc.nkept[1];
-  uint64_t pm = 0;
-  for (uint32_t r = wave(); r < rounds; r += kCW) {
+  const uint32_t pos1 = sc.nkept[1];
+  // level 1 as 64-bit words (bit q: level-0 byte q differs from the one
+  // before); bits from n0 on do not count
+  const uint64_t* l1 = (const uint64_t*)sc.lv1;
+  uint32_t wexcl = 0, pos0 = pos1;
+  if (top >= 1) {
+    const uint32_t nw = (n0 + 63) / 64;  // <= 32
+    uint64_t wd = 0;
+    if ((uint32_t)lane() < nw) {
+      wd = l1[lane()];
+      const uint32_t v = n0 - 64u * (uint32_t)lane();
+      if (v < 64) wd &= (1ull << v) - 1ull;
+    }
+    const uint32_t c = (uint32_t)__popcll(wd);
+    const uint32_t inc = wave_scan_u32(c);
+    wexcl = inc - c;
+    pos0 = pos1 + (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    if (pos0 > in_len) return false;
+  }
+  uint32_t mi[kRPW], incl[kRPW];
+#pragma unroll
+  for (int k = 0; k < kRPW; ++k) {
+    const uint32_t r = wave() + kCW * k;
+    mi[k] = 0;
+    incl[k] = 0;
+    if (r >= rounds) continue;
     const uint32_t u = r * 64 + lane();
-    const uint32_t mi = unit_bits<W>(sc, u, NU, items);
-    const uint32_t ci = __popc(mi);
-    if (!__ballot(ci != 0u)) {
+    // the level-1 word holding the bits of this round's level-0 bytes
+    // (r / W: one word per round of 8 / W items a unit) and the kept bytes
+    // before it
+    uint64_t wd = 0;
+    uint32_t wb = 0;
+    if (top >= 1) {
+      const uint32_t wi = r / W;
+      wd = l1[wi];
+      const uint32_t v = n0 - 64u * wi;
+      if (v < 64) wd &= (1ull << v) - 1ull;
+      wb = (uint32_t)__builtin_amdgcn_readlane((int)wexcl, (int)wi);
+    }
+    if (u < NU) {
+      const uint32_t q = W == 1 ? u : (W == 4 ? u / 4 : u / 8);  // its level-0 byte
+      uint32_t b0;
+      if (top == 0) {
+        b0 = in[q];  // the top level is level 0 (q < n0 = its size)
+      } else {
+        const uint32_t e = wb + (uint32_t)__popcll(wd & ((2ull << (q & 63)) - 1ull));
+        b0 = e ? in[pos1 + e - 1] : 0u;
+      }
+      mi[k] = unit_bits<W>(b0, u, items);
+    }
+    incl[k] = wave_incl_scan((uint32_t)__popc(mi[k]));
+    if (lane() == 63) sc.rpre[r] = incl[k];
+  }
+  __syncthreads();
+  // payload offsets of the rounds; the payload must end the input exactly
+  const uint32_t rc = (uint32_t)lane() < rounds ? sc.rpre[lane()] : 0u;
+  const uint32_t rinc = wave_scan_u32(rc);
+  const uint32_t npay = (uint32_t)__builtin_amdgcn_readlane((int)rinc, 63);
+  if (pos0 + npay * W != in_len) return false;
+  uint64_t pm = 0;
+#pragma unroll
+  for (int k = 0; k < kRPW; ++k) {
+    const uint32_t r = wave() + kCW * k;
+    if (r >= rounds) break;
+    const uint32_t u = r * 64 + lane();
+    if (!__ballot(mi[k] != 0u)) {
       if (u < NU) U[u] = 0;
       continue;
     }
-    uint32_t s = pos + W * (sc.rpre[r] + wave_incl_scan(ci) - ci);
+    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)(rinc - rc), (int)r);
+    const uint32_t m = mi[k];
+    const uint32_t c = (uint32_t)__popc(m);
     if (u >= NU) continue;
-    uint64_t v = 0;
-    if (W == 1) {
-#pragma unroll
-      for (int b = 0; b < 8; ++b)
-        if ((mi >> b) & 1) v |= (uint64_t)in[s++] << (8 * b);
-    } else if (W == 4) {
-      if (mi & 1) {
-        v |= (uint64_t)in[s] | ((uint64_t)in[s + 1] << 8) | ((uint64_t)in[s + 2] << 16) |
-             ((uint64_t)in[s + 3] << 24);
-        s += 4;
-      }
-      if (mi & 2)
-        v |= ((uint64_t)in[s] | ((uint64_t)in[s + 1] << 8) | ((uint64_t)in[s + 2] << 16) |
-              ((uint64_t)in[s + 3] << 24)) << 32;
-    } else if (mi) {
-#pragma unroll
-      for (int b = 0; b < 8; ++b) v |= (uint64_t)in[s + b] << (8 * b);
-    }
+    const uint64_t v = unit_payload<W>(in + pos0 + W * (base + incl[k] - c), m, c);
     U[u] = v;
     if (G && v) pm |= 1ull << (u / G);
   }
@@ -447,26 +506,6 @@ __device__ uint64_t nonzero_planes(const uint64_t* U, uint32_t G, Scratch& sc) {
   }
   __syncthreads();
   return sc.planes;
-}
-
-// BIT_K inverse: words[64g + lane] from the units of the nonzero planes.
-template <int K>
-__device__ void bit_decode(const uint64_t* U, uint32_t G, uint64_t planes,
-                           typename Traits<K>::Word* words) {
-  using Word = typename Traits<K>::Word;
-  const uint32_t* U32 = (const uint32_t*)U;
-  const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
-  for (uint32_t g = wave(); g < G; g += kCW) {
-    Word w = 0;
-    uint64_t pm = planes;
-    while (pm) {
-      const uint32_t j = (uint32_t)__builtin_ctzll(pm);
-      pm &= pm - 1;
-      const uint32_t h = U32[2 * (j * G + g) + half];
-      w |= (Word)((h >> sh) & 1u) << j;
-    }
-    words[g * 64 + lane()] = w;
-  }
 }
 
 __device__ __forceinline__ uint64_t block_or(uint64_t v, Scratch& sc) {
@@ -993,6 +1032,7 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
   __shared__ uint64_t Mb[kMaxUnits + 2];
   __shared__ Scratch sc;
   __shared__ uint64_t gsum[64 + 1];  // per-group sums of the bin deltas
+  __shared__ int64_t s_mm[2][kCW];     // per-wave least / greatest bin
   __shared__ int s_bad;
 
   const uint32_t p0 = c * W, nc = min(W, n - p0);
@@ -1057,6 +1097,7 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
     return;
   }
   Word wv[GPW];
+  int64_t bmin = INT64_MAX, bmax = INT64_MIN;
   {
     const uint32_t* P32 = (const uint32_t*)planes;
     const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
@@ -1090,6 +1131,19 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
     for (int i = 0; i < GPW; ++i) {
       const uint32_t g = wave() + kCW * i;
       if (g < G) wv[i] += (Word)gsum[g];
+      const int64_t b = K == 4 ? (int64_t)(int32_t)(uint32_t)wv[i] : (int64_t)(uint64_t)wv[i];
+      if (g * 64 + lane() < nc) {
+        bmin = b < bmin ? b : bmin;
+        bmax = b > bmax ? b : bmax;
+      }
+    }
+    // the chunk's bin range (for the floor table below); the wave results
+    // are read after the next barrier
+    bmin = wave_reduce(bmin, OpMin{});
+    bmax = wave_reduce(bmax, OpMax{});
+    if (lane() == 0) {
+      s_mm[0][wave()] = bmin;
+      s_mm[1][wave()] = bmax;
     }
   }
 
@@ -1114,13 +1168,13 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
   } else {
     ok = rze_decode<1>(sp, slen, smid, Mb, sc, 0);
   }
-  uint64_t* words = Mb;  // subbin words go to the buffer not holding the planes
+  uint64_t* spare = Mb;  // the buffer not holding the subbin planes
   uint64_t spm = 0;
   if (ok) {
     if (sfl & 1) {
       ok = smid == L;
       planes = Mb;
-      words = U;
+      spare = U;
       if (ok) spm = nonzero_planes<K>(planes, G, sc);
     } else {
       ok = rze_decode<K>((const uint8_t*)Mb, smid, L, U, sc, G);
@@ -1132,37 +1186,40 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);
     return;
   }
-  bit_decode<K>(planes, G, spm, (Word*)words);
+  // BIT_K inverse of the subbins into registers, word 64g + lane of group
+  // g = wave + kCW * i in sv[i] (as the bins)
+  Word sv[GPW];
+  {
+    const uint32_t* P32 = (const uint32_t*)planes;
+    const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
+#pragma unroll
+    for (int i = 0; i < GPW; ++i) {
+      const uint32_t g = wave() + kCW * i;
+      Word w = 0;
+      if (g < G) {
+        uint64_t pm = spm;
+        while (pm) {
+          const uint32_t j = (uint32_t)__builtin_ctzll(pm);
+          pm &= pm - 1;
+          w |= (Word)((P32[2 * (j * G + g) + half] >> sh) & 1u) << j;
+        }
+      }
+      sv[i] = w;
+    }
+  }
 
   // reconstruct (Sec. IV-E).  The bin floors of the chunk's bin range go to
-  // a table in the (now free) planes buffer when the range is small enough,
-  // so that each distinct bin is walked once.
+  // a table in the spare buffer when the range is small enough, so that each
+  // distinct bin is walked once.
   using Key = typename Tr::Bin;  // order keys fit the signed bin type
   constexpr uint32_t kTab = kChunkBytes / sizeof(Key);
   constexpr Key kNoKey = (Key)((uint64_t)1 << (8 * sizeof(Key) - 1));  // most negative
-  int64_t bmin = INT64_MAX, bmax = INT64_MIN;
-#pragma unroll
-  for (int i = 0; i < GPW; ++i) {
-    const uint32_t j = (wave() + kCW * i) * 64 + lane();
-    const int64_t b = K == 4 ? (int64_t)(int32_t)(uint32_t)wv[i] : (int64_t)(uint64_t)wv[i];
-    if (j < nc) {
-      bmin = b < bmin ? b : bmin;
-      bmax = b > bmax ? b : bmax;
-    }
-  }
-  bmin = wave_reduce(bmin, OpMin{});
-  bmax = wave_reduce(bmax, OpMax{});
-  if (lane() == 0) {
-    sc.orv[wave()] = (uint64_t)bmin;
-    sc.scan64[wave()] = (uint64_t)bmax;
-  }
-  __syncthreads();
   for (int w = 0; w < kCW; ++w) {
-    bmin = min(bmin, (int64_t)sc.orv[w]);
-    bmax = max(bmax, (int64_t)sc.scan64[w]);
+    bmin = min(bmin, s_mm[0][w]);
+    bmax = max(bmax, s_mm[1][w]);
   }
   const bool table = (uint64_t)bmax - (uint64_t)bmin < kTab;
-  Key* T = (Key*)planes;
+  Key* T = (Key*)spare;
   if (table) {
     const uint32_t R = (uint32_t)((uint64_t)bmax - (uint64_t)bmin) + 1;
     for (uint32_t e = threadIdx.x; e < R; e += kCT) {
@@ -1177,7 +1234,7 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
     const uint32_t j = (wave() + kCW * i) * 64 + lane();
     if (j >= nc) continue;
     const int64_t b = K == 4 ? (int64_t)(int32_t)(uint32_t)wv[i] : (int64_t)(uint64_t)wv[i];
-    const uint64_t s = (uint64_t)((const Word*)words)[j];
+    const uint64_t s = (uint64_t)sv[i];
     int64_t klo;
     bool have;
     if (table) {
