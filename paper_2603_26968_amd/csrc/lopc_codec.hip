@@ -1018,6 +1018,38 @@ __device__ __forceinline__ void stage(uint8_t* dst, const uint8_t* src, uint32_t
   }
 }
 
+// BIT_K inverse of the groups g = wave + kCW * i (i < GPW) of G into w[i]
+// (word 64g + lane): bit j of w[i] is bit `lane` of unit j * G + g, for the
+// planes j of mask pm (the others are zero).  Planes outer, groups inner: the
+// reads of one plane sit at fixed distances from one address, so they pair
+// up into two-address LDS reads.
+template <typename Word, int GPW>
+__device__ __forceinline__ void planes_to_words(const uint64_t* planes, uint32_t G, uint64_t pm,
+                                                Word (&w)[GPW]) {
+  const uint32_t* P32 = (const uint32_t*)planes;
+  const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
+#pragma unroll
+  for (int i = 0; i < GPW; ++i) w[i] = 0;
+  if (wave() + kCW * (GPW - 1) < G) {  // every group of this wave present
+    while (pm) {
+      const uint32_t j = (uint32_t)__builtin_ctzll(pm);
+      pm &= pm - 1;
+      const uint32_t* row = P32 + 2 * (j * G + wave()) + half;
+#pragma unroll
+      for (int i = 0; i < GPW; ++i) w[i] |= (Word)((row[2 * kCW * i] >> sh) & 1u) << j;
+    }
+  } else {
+    while (pm) {
+      const uint32_t j = (uint32_t)__builtin_ctzll(pm);
+      pm &= pm - 1;
+      const uint32_t* row = P32 + 2 * (j * G + wave()) + half;
+#pragma unroll
+      for (int i = 0; i < GPW; ++i)
+        if (wave() + kCW * i < G) w[i] |= (Word)((row[2 * kCW * i] >> sh) & 1u) << j;
+    }
+  }
+}
+
 // Decodes chunk c of a field (Sec. IV-E); a malformed record sets FORMAT.
 template <int K>
 __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, uint32_t n,
@@ -1099,21 +1131,12 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
   Word wv[GPW];
   int64_t bmin = INT64_MAX, bmax = INT64_MIN;
   {
-    const uint32_t* P32 = (const uint32_t*)planes;
-    const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
+    planes_to_words<Word, GPW>(planes, G, pm0, wv);
     const Word Mk = (Word)0xAAAAAAAAAAAAAAAAull;
 #pragma unroll
     for (int i = 0; i < GPW; ++i) {
       const uint32_t g = wave() + kCW * i;
-      Word w = 0;
-      if (g < G) {
-        uint64_t pm = pm0;
-        while (pm) {
-          const uint32_t j = (uint32_t)__builtin_ctzll(pm);
-          pm &= pm - 1;
-          w |= (Word)((P32[2 * (j * G + g) + half] >> sh) & 1u) << j;
-        }
-      }
+      const Word w = wv[i];
       // negabinary -> delta; inclusive prefix within the group of 64 words
       Word d = (g * 64 + lane() < nc) ? (Word)((w ^ Mk) - Mk) : (Word)0;
       d = wave_scan<Word>(d);
@@ -1189,24 +1212,7 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
   // BIT_K inverse of the subbins into registers, word 64g + lane of group
   // g = wave + kCW * i in sv[i] (as the bins)
   Word sv[GPW];
-  {
-    const uint32_t* P32 = (const uint32_t*)planes;
-    const uint32_t half = (uint32_t)lane() >> 5, sh = (uint32_t)lane() & 31;
-#pragma unroll
-    for (int i = 0; i < GPW; ++i) {
-      const uint32_t g = wave() + kCW * i;
-      Word w = 0;
-      if (g < G) {
-        uint64_t pm = spm;
-        while (pm) {
-          const uint32_t j = (uint32_t)__builtin_ctzll(pm);
-          pm &= pm - 1;
-          w |= (Word)((P32[2 * (j * G + g) + half] >> sh) & 1u) << j;
-        }
-      }
-      sv[i] = w;
-    }
-  }
+  planes_to_words<Word, GPW>(planes, G, spm, sv);
 
   // reconstruct (Sec. IV-E).  The bin floors of the chunk's bin range go to
   // a table in the spare buffer when the range is small enough, so that each
