@@ -111,8 +111,8 @@ def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing, want_stats=True):
 
 
 def measured_traffic(phase):
-    """HBM bytes per launch of the kernels of codec phase `phase` ("encode"
-    or "decode") from the committed counter summary of the turb3d workload
+    """HBM bytes per launch of the kernels of phase `phase` ("quant",
+    "encode" or "decode") from the committed counter summary of the turb3d workload
     (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel), or None if it was
     taken on other kernel sources than the current ones."""
     import hashlib
@@ -165,7 +165,9 @@ def bench_single(args, name):
     # phase breakdown and statistics: a few steps before the timed region,
     # every phase timed (a timed dispatch delays the next launch a little)
     _, phase, stats, _ = run_steps(P, lopc, ctx, x, args.eb, min(args.steps, 5), bufs, True)
-    dom = "decode" if phase["decode"] >= phase["encode"] else "encode"
+    # the dominant kernel: the first tile pass (k_tile0, phase "quant"), the
+    # encode phase or the decoder, whichever took longest
+    dom = max(("quant", "encode", "decode"), key=lambda q: phase[q])
     # timed region: K steps; the dominant codec phase is timed by HIP events
     # that the library takes from its kernels' dispatches on their stream
     dt, phase_k, _, s = run_steps(P, lopc, ctx, x, args.eb, args.steps, bufs, (dom,),
@@ -176,21 +178,27 @@ def bench_single(args, name):
     t_d = phase["offsets"] + phase["decode"]
     value = n * k / (dt / args.steps) / 1e9
 
-    # algorithmic bytes of the two codec phases: the decoder reads the
-    # stream and writes the field; the encoder (k_encode, which parks each
-    # record in rows it has consumed, k_record_offsets and k_place, timed
-    # together) reads bins and subbins and writes the stream
-    # (the non-dominant phase's time comes from the breakdown steps)
-    t_ph = {q: (phase_k[q] if q == dom else phase[q]) for q in ("encode", "decode")}
+    # algorithmic bytes of the three largest phases: the first tile pass
+    # reads the field and writes bins, order flags (2 bytes) and first
+    # subbins (4 bytes); the decoder reads the stream and writes the field;
+    # the encoder (k_encode, which parks each record in rows it has
+    # consumed, k_record_offsets and k_place, timed together) reads bins and
+    # subbins and writes the stream (the non-dominant phases' times come
+    # from the breakdown steps)
+    t_ph = {q: (phase_k[q] if q == dom else phase[q]) for q in ("quant", "encode", "decode")}
+    q_bytes = n * k + n * k + n * 2 + n * 4
+    q_gbps = q_bytes / (t_ph["quant"] * 1e-3) / 1e9 if t_ph["quant"] else 0.0
     dec_bytes = S + n * k
     dec_gbps = dec_bytes / (t_ph["decode"] * 1e-3) / 1e9 if t_ph["decode"] else 0.0
     enc_bytes = n * k + n * 4 + S
     enc_gbps = enc_bytes / (t_ph["encode"] * 1e-3) / 1e9 if t_ph["encode"] else 0.0
     kernels = {
+        "quant": {"ms": t_ph["quant"], "bytes": q_bytes, "GBps": q_gbps},
         "decode": {"ms": t_ph["decode"], "bytes": dec_bytes, "GBps": dec_gbps},
         "encode": {"ms": t_ph["encode"], "bytes": enc_bytes, "GBps": enc_gbps},
     }
-    kname = "k_decode" if dom == "decode" else "k_encode+k_record_offsets+k_place"
+    kname = {"quant": "k_tile0", "decode": "k_decode",
+             "encode": "k_encode+k_record_offsets+k_place"}[dom]
     traffic = measured_traffic(dom) if name == "turb3d" and args.eb == 1e-3 else None
     roof = {"bound": "hbm", "kernel": kname,
             "achieved": round(kernels[dom]["GBps"], 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
