@@ -249,51 +249,60 @@ __device__ __forceinline__ uint32_t unit_bits(uint32_t b0, uint32_t u, uint32_t 
   }
 }
 
-// One level of the bitmap recursion undone by one wave (no block barrier):
+// One level of the bitmap recursion undone by one wave (no block barrier),
+// for levels of at most 512 bytes (level 1 and above of a 16 kB input):
 // child byte i = the last kept byte at or before i (0 if none), the kept
-// bytes read from in[pos...); lane l handles parent bytes [P*l, P*l + P).
-// Returns false (wave-uniform) if the kept bytes run past in_len.
+// bytes read from in[pos...); lane l handles parent byte l.  Returns false
+// (wave-uniform) if the kept bytes run past in_len.  The 8 child bytes of a
+// parent byte m (e kept bytes before it) come from one window of kept
+// bytes, read as aligned words and joined by byte-align moves: it starts
+// one byte before the first kept byte of m when m's bit 0 is clear (that
+// byte fills the leading children), at it otherwise; the selector of child
+// b is its inclusive count of set bits minus bit 0 of m, or 0x0c (zero)
+// while no kept byte has been seen at all (e = 0).
 __device__ bool level_decode_w(const uint8_t* par, uint32_t n, const uint8_t* in,
                                uint32_t& pos, uint32_t in_len, uint8_t* child) {
-  const uint32_t np = (n + 7) / 8;    // <= 256
-  const uint32_t P = (np + 63) / 64;  // <= 4
-  uint32_t pb[4];
-  uint32_t c = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t idx = (uint32_t)lane() * P + q;
-    pb[q] = 0;
-    if ((uint32_t)q < P && idx < np) {
-      uint32_t v = par[idx];
-      const uint32_t valid = n - idx * 8;
-      if (valid < 8) v &= (1u << valid) - 1;
-      pb[q] = v;
-    }
-    c += (uint32_t)__popc(pb[q]);
+  const uint32_t np = (n + 7) / 8;  // <= 64
+  const uint32_t idx = (uint32_t)lane();
+  const uint32_t valid = n - idx * 8;
+  uint32_t m = 0;
+  if (idx < np) {
+    m = par[idx];
+    if (valid < 8) m &= (1u << valid) - 1;
   }
-  const uint32_t incl = wave_incl_scan(c);
+  const uint32_t cq = (uint32_t)__popc(m);
+  const uint32_t incl = wave_incl_scan(cq);
   const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
   if (pos + tot > in_len) return false;
-  uint32_t e = incl - c;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const uint32_t idx = (uint32_t)lane() * P + q;
-    if ((uint32_t)q < P && idx < np) {
-      const uint32_t i0 = idx * 8;
-      uint32_t w0 = 0, w1 = 0;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        uint32_t v = 0;
-        if (i0 + b < n) {
-          if ((pb[q] >> b) & 1) ++e;
-          v = e ? in[pos + e - 1] : 0u;
-        }
-        if (b < 4) w0 |= v << (8 * b);
-        else w1 |= v << (8 * (b - 4));
-      }
-      ((uint32_t*)child)[2 * idx] = w0;  // bytes past n are zero
-      ((uint32_t*)child)[2 * idx + 1] = w1;
+  const uint32_t e = incl - cq;
+  if (idx < np) {
+    const uint32_t b0 = m & 1u;
+    // window: from kept byte e - 1 + b0 (in[pos - 1] when e = 0 and b0 = 0,
+    // a byte of the levels above, selected by no child), cq + 1 - b0 bytes
+    const uint8_t* p = in + pos + e + b0 - 1;
+    const uint32_t mis = (uint32_t)(uintptr_t)p & 3u;
+    const uint32_t* wq = (const uint32_t*)(p - mis);
+    const uint32_t nd = (mis + cq + 1 - b0 + 3) / 4;  // 1..3 words
+    const uint32_t w0 = wq[0];
+    const uint32_t w1 = nd > 1 ? wq[1] : 0u;
+    const uint32_t w2 = nd > 2 ? wq[2] : 0u;
+    const uint32_t x0 = __builtin_amdgcn_alignbyte(w1, w0, mis);
+    const uint32_t x1 = __builtin_amdgcn_alignbyte(w2, w1, mis);
+    // inclusive counts of set bits per child byte (as in unit_payload)
+    const uint32_t slo = ((m & 0xfu) * 0x00204081u) & 0x01010101u;
+    const uint32_t shi = (((m >> 4) & 0xfu) * 0x00204081u) & 0x01010101u;
+    const uint32_t ilo = slo * 0x01010101u;
+    const uint32_t ihi = shi * 0x01010101u + (uint32_t)__popc(m & 0xfu) * 0x01010101u;
+    uint32_t sel_lo = ilo - b0 * 0x01010101u, sel_hi = ihi - b0 * 0x01010101u;
+    if (e == 0) {  // children before the first kept byte of the level are 0
+      sel_lo |= ((~(ilo + 0x7f7f7f7fu) & 0x80808080u) >> 7) * 0x0cu;
+      sel_hi |= ((~(ihi + 0x7f7f7f7fu) & 0x80808080u) >> 7) * 0x0cu;
     }
+    uint64_t v = (uint64_t)__builtin_amdgcn_perm(x1, x0, sel_lo) |
+                 (uint64_t)__builtin_amdgcn_perm(x1, x0, sel_hi) << 32;
+    if (valid < 8) v &= (1ull << (8 * valid)) - 1ull;  // bytes past n are zero
+    ((uint32_t*)child)[2 * idx] = (uint32_t)v;
+    ((uint32_t*)child)[2 * idx + 1] = (uint32_t)(v >> 32);
   }
   pos += tot;
   __builtin_amdgcn_wave_barrier();
@@ -347,11 +356,12 @@ __device__ void rze_decode_upper(const uint8_t* in, uint32_t in_len, uint32_t it
   const uint32_t sz_top = lvl_size(items, top);
   bool ok = sz_top <= in_len;
   uint32_t pos = sz_top;
-  if (ok && top >= 1) {
-    uint8_t* tb = lvl(sc, top);
-    if (lane() < 16) tb[lane()] = (uint32_t)lane() < sz_top ? in[lane()] : (uint8_t)0;
-    __builtin_amdgcn_wave_barrier();
-    for (int l = top - 1; l >= 1 && ok; --l)
+  if (ok && top == 1) {
+    if (lane() < 16) sc.lv1[lane()] = (uint32_t)lane() < sz_top ? in[lane()] : (uint8_t)0;
+  } else if (ok && top >= 2) {
+    // the top level is read in place (its sz_top bytes are the parents)
+    ok = level_decode_w(in, lvl_size(items, top - 1), in, pos, in_len, lvl(sc, top - 1));
+    for (int l = top - 2; l >= 1 && ok; --l)
       ok = level_decode_w(lvl(sc, l + 1), lvl_size(items, l), in, pos, in_len, lvl(sc, l));
   }
   if (lane() == 0) {
