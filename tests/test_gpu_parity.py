@@ -203,6 +203,42 @@ def test_corrupt_streams_match_oracle(P, ref):
             assert got is not None and same_bits(got, want), f"flip at {pos}"
 
 
+CORRUPT = [
+    # binary64: items of 8 bytes in the subbin stage, 2048 values a chunk
+    ("turb3d_f64", lambda: synth.turbulence_field((12, 20, 36), seed=9, dtype=np.float64), 1e-3),
+    # a loose bound: long same-bin runs, so most bytes of the stream belong
+    # to the subbin part (RZE_K levels and payload)
+    ("turb3d_f32_loose", lambda: synth.turbulence_field((16, 24, 40), seed=10), 1e-1),
+]
+
+
+@pytest.mark.parametrize("name,gen,eb", CORRUPT, ids=[c[0] for c in CORRUPT])
+def test_corrupt_streams_more_match_oracle(P, ref, name, gen, eb):
+    """Single-bit flips anywhere past the header of binary64 and
+    subbin-heavy streams: the GPU accepts exactly what the oracle accepts
+    and decodes it to the same values."""
+    _say("corrupt", name)
+    s = ref.compress(gen(), eb)
+    rng = np.random.default_rng(1)
+    for t in range(100):
+        c = bytearray(s)
+        pos = int(rng.integers(64, len(c)))
+        c[pos] ^= 1 << int(rng.integers(0, 8))
+        c = bytes(c)
+        try:
+            want = ref.decompress(c)
+        except ref.OracleError:
+            want = None
+        try:
+            got = gpu_decompress(P, c)
+        except Exception:
+            got = None
+        if want is None:
+            assert got is None, f"{name}: flip at {pos}: oracle rejects, GPU accepts"
+        else:
+            assert got is not None and same_bits(got, want), f"{name}: flip at {pos}"
+
+
 @pytest.mark.parametrize("eb", [1e-2, 1e-3, 1e-4])
 def test_turb3d_full_size(P, ref, eb):
     x = synth.turbulence_field()
