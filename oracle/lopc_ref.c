@@ -305,7 +305,10 @@ int lopc_ref_subbins(const void* field, int dtype, int ndim,
 static int bin_floor_key(int64_t b, double inv, int dtype, int64_t* out) {
   if (b > bin_limit(dtype) || b < -bin_limit(dtype)) return LOPC_REF_E_FORMAT;
   /* start near the lower edge (b - 1/2)/inv of the bin, then step to the
-   * first representable value whose bin is b */
+   * first representable value whose bin is b.  The rounded edge lies within
+   * two representable values of that value (one for float32) at every bin
+   * magnitude and bound, so a walk of more than 8 steps means a bin no value
+   * of the dtype can have: the stream is malformed. */
   double c = ((double)b - 0.5) / inv;
   if (dtype == 0) c = (double)(float)c;
   if (!isfinite(c)) return LOPC_REF_E_FORMAT;
@@ -314,12 +317,12 @@ static int bin_floor_key(int64_t b, double inv, int dtype, int64_t* out) {
   int steps = 0;
   while (k > -kmax && q_sat(value_of_key(k - 1, dtype), inv) >= b) {
     --k;
-    if (++steps > 64) return LOPC_REF_E_FORMAT;
+    if (++steps > 8) return LOPC_REF_E_FORMAT;
   }
   while (q_sat(value_of_key(k, dtype), inv) < b) {
     if (k >= kmax) return LOPC_REF_E_FORMAT;
     ++k;
-    if (++steps > 64) return LOPC_REF_E_FORMAT;
+    if (++steps > 8) return LOPC_REF_E_FORMAT;
   }
   if (q_sat(value_of_key(k, dtype), inv) != b) return LOPC_REF_E_FORMAT;
   *out = k;

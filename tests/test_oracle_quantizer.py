@@ -147,3 +147,51 @@ def test_zero_is_one_value(ref):
     assert z == 0.0 and not math.copysign(1.0, z) < 0
     assert ref.reconstruct(0, steps - 1, inv, 1) == -5e-324
     assert ref.reconstruct(0, steps + 1, inv, 1) == 5e-324
+
+
+@pytest.mark.parametrize("dtype_code", [0, 1])
+def test_bin_floor_walk_is_short(ref, dtype_code):
+    """The bin floor of any bin b in range, at any bound: found exactly when
+    some value of the dtype lies in the bin (exact rationals), and equal to
+    the lowest such value.  The search starts at the rounded edge
+    (b - 1/2)/inv and may take at most 8 steps; this pins that a non-empty
+    bin is always within reach (across bin magnitudes up to the limits,
+    bounds from subnormal to huge, so bins both much wider and much narrower
+    than the spacing of representable values)."""
+    rng = np.random.default_rng(40 + dtype_code)
+    ftype = np.float32 if dtype_code == 0 else np.float64
+    lim = 2 ** 31 - 2 if dtype_code == 0 else 2 ** 62
+    lo_e, hi_e = (-40, 30) if dtype_code == 0 else (-300, 30)
+    seen_empty = seen_full = 0
+    for _ in range(1500):
+        eps = float(10.0 ** rng.uniform(lo_e, hi_e))
+        try:
+            _, inv = ref.error_params(np.array([[0.0, 1.0]]), eps, ref.ABS)
+        except ref.OracleError:
+            continue
+        b = int(rng.choice([-1, 1])) * int(10 ** rng.uniform(0, math.log10(lim)))
+        edge = (Fraction(b) - Fraction(1, 2)) / Fraction(inv)
+        with np.errstate(over="ignore"):
+            c = float(ftype(float(edge)))
+        if not math.isfinite(c):
+            continue
+        # the exact floor: walk with exact bins from the edge's neighbourhood
+        y = c
+        while True:
+            p = float(np.nextafter(ftype(y), ftype(-np.inf)))
+            if p == 0.0 and y == 0.0:
+                p = float(np.nextafter(ftype(0.0), ftype(-1.0)))
+            if not math.isfinite(p) or q_exact(p, inv) < b:
+                break
+            y = p
+        while math.isfinite(y) and q_exact(y, inv) < b:
+            y = float(np.nextafter(ftype(y), ftype(np.inf)))
+        nonempty = math.isfinite(y) and q_exact(y, inv) == b
+        if nonempty:
+            seen_full += 1
+            assert ref.bin_floor(b, inv, dtype_code) == y, (b, inv)
+        else:
+            seen_empty += 1
+            with pytest.raises(ref.OracleError):
+                ref.bin_floor(b, inv, dtype_code)
+    assert seen_full > 100 and seen_empty > 100
