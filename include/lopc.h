@@ -28,7 +28,9 @@
  *     compress/decompress calls (scratch lives in the caller's workspace);
  *   - `stream` is a hipStream_t (NULL = default stream); all device work is
  *     ordered on it; the calls below block until their own work on that
- *     stream is done (they return sizes and status codes to the host);
+ *     stream is done (they return sizes and status codes to the host),
+ *     except lopc_compress called with h_stream_size = NULL, which only
+ *     enqueues its work and reports on the device;
  *   - return value: LOPC_OK (0) or a negative lopc_status; arguments are
  *     validated before any launch; on error the output buffers hold
  *     unspecified bytes but nothing outside them is written;
@@ -63,19 +65,23 @@ typedef enum {
   LOPC_E_FORMAT = -6,    /* malformed or corrupt stream                      */
   LOPC_E_HIP = -7,       /* a HIP runtime call failed                        */
   LOPC_E_NOMEM = -8,     /* host allocation failed                           */
-  LOPC_E_INTERNAL = -9   /* internal limit exceeded (e.g. repair sweeps)     */
+  LOPC_E_INTERNAL = -9   /* an internal consistency check failed (a bug)     */
 } lopc_status;
 
 typedef struct lopc_ctx lopc_ctx;
 
-/* Optional per-call figures of a compression. */
+/* Optional per-call figures of a compression.  repair_sweeps counts the
+ * first pass and every sweep that ran; when the repair queue ran, it is at
+ * least 1 + the longest chain of tile runs that listed one another. */
 typedef struct {
   double eps;                  /* absolute bound actually applied           */
   uint64_t repair_sweeps;      /* global sweeps of the repair to fixed point */
-  uint64_t active_tiles_total; /* tiles processed over all sweeps           */
+  uint64_t active_tiles_total; /* tile runs, the first pass included        */
   uint64_t bins_bytes;         /* bytes of all bins parts                   */
   uint64_t subbins_bytes;      /* bytes of all subbin parts                 */
   uint64_t relax_iterations;   /* in-tile relaxation passes, all tiles/sweeps */
+  uint64_t queue_runs;         /* tile runs taken from the repair queue      */
+  uint64_t queue_parks;        /* times a taken tile parked on another one   */
 } lopc_stats;
 
 /* Context for one HIP device: device properties, pinned host slots for the
@@ -95,13 +101,29 @@ int lopc_workspace_size(lopc_ctx* ctx, int dtype, int ndim,
                         const int64_t* dims, int op, size_t* bytes);
 
 /* Compress d_field (dtype, ndim, dims) with error_bound under mode into
- * d_stream (capacity stream_cap bytes).  *h_stream_size receives the stream
- * size -- also when LOPC_E_CAPACITY is returned, so the caller can retry.
+ * d_stream (capacity stream_cap bytes) [Sec. IV-A to IV-C: quantize, order
+ * flags, repair to the least fixed point, lossless stages].
  * d_ws/ws_bytes: workspace of at least lopc_workspace_size(op = 0).
- * h_stats may be NULL. */
+ *
+ * Synchronous (h_stream_size != NULL): returns when the stream is complete;
+ * *h_stream_size receives the stream size -- also when LOPC_E_CAPACITY is
+ * returned, so the caller can retry; h_stats may be NULL.
+ *
+ * Enqueued (h_stream_size == NULL, d_stream_size required, h_stats NULL):
+ * every launch is enqueued on `stream` and the call returns LOPC_OK without
+ * waiting (argument errors are still returned at once).  No host memory is
+ * touched after the call returns, so the sequence can be captured into a HIP
+ * graph; the repair reaches its fixed point on the device (LOPC_E_ARG under
+ * LOPC_REPAIR_SWEEPS).
+ *
+ * In both modes, when given, the device words *d_stream_size (8-byte
+ * aligned) and *d_status (4-byte aligned) receive, in stream order, the
+ * stream size (also on LOPC_E_CAPACITY; 0 after any other failure) and the
+ * call's lopc_status. */
 int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
                   const int64_t* dims, double error_bound, int mode,
                   void* d_stream, size_t stream_cap, size_t* h_stream_size,
+                  uint64_t* d_stream_size, int32_t* d_status,
                   void* d_ws, size_t ws_bytes, void* stream,
                   lopc_stats* h_stats);
 
@@ -218,8 +240,29 @@ int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void
  *   LOPC_OPT_PERSIST_PCT   0 (default): direct grids, one workgroup per
  *                          item; 1..400: persistent grids of that percentage
  *                          of the resident capacity, draining the queues (one
- *                          captured graph then serves every batch shape). */
-enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT = 3 };
+ *                          captured graph then serves every batch shape).
+ *   LOPC_OPT_REPAIR        scheduler of the single-field repair [Alg. 1
+ *                          loop, Sec. IV-B]; every one reaches the same
+ *                          least fixed point:
+ *                          LOPC_REPAIR_AUTO (default): synchronous calls
+ *                          as LOPC_REPAIR_SWEEPS up to 64 sweeps, then the
+ *                          repair restarts from its first pass on the queue
+ *                          (a dependency chain across that many tiles);
+ *                          enqueued calls as LOPC_REPAIR_HYBRID;
+ *                          LOPC_REPAIR_HYBRID: K sweeps over device work
+ *                          lists of the tiles whose halo changed (K learned
+ *                          from the previous call on the context, at most
+ *                          48), then a device work queue drained by one
+ *                          persistent launch for whatever is still listed;
+ *                          LOPC_REPAIR_QUEUE: the work queue alone, from the
+ *                          first pass on;
+ *                          LOPC_REPAIR_SWEEPS: global sweeps over the marked
+ *                          tiles, launched by the host in groups, until no
+ *                          tile is marked (not available to enqueued calls). */
+enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT = 3,
+       LOPC_OPT_REPAIR = 4 };
+enum { LOPC_REPAIR_AUTO = 0, LOPC_REPAIR_HYBRID = 1, LOPC_REPAIR_QUEUE = 2,
+       LOPC_REPAIR_SWEEPS = 3 };
 int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value);
 
 /* ------------------------------------------------------------------ checks

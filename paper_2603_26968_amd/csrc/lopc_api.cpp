@@ -42,12 +42,14 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->device = hip_device;
   c->num_cu = prop.multiProcessorCount;
   void* p = nullptr;
-  if (hipHostMalloc(&p, 4096, hipHostMallocDefault) != hipSuccess) {
+  // pinned host slots: the compress report (Params, counters, queue: under
+  // 4 KiB) and, from 4 KiB on, the verify report
+  if (hipHostMalloc(&p, 8192, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return LOPC_E_HIP;
   }
   c->h_prm = (Params*)p;
-  c->h_cnt = (uint32_t*)((uint8_t*)p + 2048);
+  c->h_cnt = (uint32_t*)((uint8_t*)p + 4096);
   c->timing = 0;
   c->have_header = 0;
   c->hip_error = 0;
@@ -63,6 +65,9 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->sweeps_hint = 16;
   c->persist_pct = 0;
   c->sweep_hint = 4;
+  c->repair_mode = LOPC_REPAIR_AUTO;
+  c->rq_per_cu[0] = c->rq_per_cu[1] = 0;
+  c->sl_per_cu[0] = c->sl_per_cu[1] = 0;
   *out = c;
   return LOPC_OK;
 }
@@ -134,62 +139,30 @@ int lopc_workspace_size(lopc_ctx* ctx, int dtype, int ndim,
   return LOPC_OK;
 }
 
-int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
-                  const int64_t* dims, double error_bound, int mode,
-                  void* d_stream, size_t stream_cap, size_t* h_stream_size,
-                  void* d_ws, size_t ws_bytes, void* stream,
-                  lopc_stats* h_stats) {
-  if (!ctx || !d_field || !d_stream || !h_stream_size || !d_ws)
-    return LOPC_E_ARG;
-  if ((dtype != 0 && dtype != 1) || (mode != 0 && mode != 1)) return LOPC_E_ARG;
-  Shape s;
-  int st = make_shape(ndim, dims, &s);
-  if (st) return st;
-  if (!std::isfinite(error_bound) || !(error_bound > 0)) return LOPC_E_BOUND;
-  if (((uintptr_t)d_field & 15) || ((uintptr_t)d_stream & 3)) return LOPC_E_ARG;
-  CompressLayout L = compress_layout(s, dtype);
-  if (ws_bytes < L.total || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
-  hipStream_t hs = (hipStream_t)stream;
-  HIP_CTX(ctx, hipSetDevice(ctx->device));
-
-  uint8_t* ws = (uint8_t*)d_ws;
-  Params* prm = (Params*)(ws + L.prm);
+// Repair sweeps driven from the host (LOPC_REPAIR_SWEEPS): the first
+// group of K sweeps (K from the previous call on this context) is enqueued
+// with the encoder, which runs only if no tile is marked for sweep K + 1;
+// one read of the status, the counters and Params then ends a typical call.
+// Otherwise sweeps continue in groups (4, 8, 16), one read per group, and
+// the encoder runs after them.  A sweep with no marked tile costs one empty
+// launch.  Every sweep that runs raises a subbin, and a dependency chain
+// crosses at most n tiles, so n + 1 sweeps always reach the fixed point.
+// Past `limit` sweeps it returns kRestartOnQueue (the encoder has not run).
+constexpr int kRestartOnQueue = 1;
+static int repair_by_sweeps(lopc_ctx* ctx, const Shape& s, const CompressLayout& L, int dtype,
+                            uint8_t* ws, void* d_stream, size_t stream_cap, const Tiling& tl,
+                            bool want_parts, hipStream_t hs, uint64_t limit,
+                            uint64_t* sweeps_out, uint64_t* active_out) {
   uint32_t* sub = (uint32_t*)(ws + L.sub);
   uint32_t* stamp = (uint32_t*)(ws + L.stamp);
   uint32_t* counters = (uint32_t*)(ws + L.counters);
   uint64_t* offs = (uint64_t*)(ws + L.offs);
+  Params* prm = (Params*)(ws + L.prm);
   const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
-  const uint64_t nch = (s.n + W - 1) / W;
-  Tiling tl = make_tiling(s.box);
-
-  int nblocks = (int)std::min<uint64_t>(kMinmaxBlocks, (s.n + 2047) / 2048);
-  if (nblocks < 1) nblocks = 1;
-  // the zeroed prefix of the workspace is cleared by the range pass (NOA),
-  // else by a fill kernel
-  if (mode == LOPC_EB_NOA)
-    HIP_CTX(ctx, launch_minmax(dtype, d_field, (uint32_t)s.n, (double*)(ws + L.part),
-                               nblocks, ws, L.zero_end, hs, ev_first(ctx, LOPC_PHASE_RANGE)));
-  else
-    HIP_CTX(ctx, launch_zero_n((uint32_t*)ws, L.zero_end / 4, hs,
-                               ev_first(ctx, LOPC_PHASE_RANGE)));
-  HIP_CTX(ctx, launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
-                             nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
-                             s.d, hs, ev_last(ctx, LOPC_PHASE_RANGE)));
-  // quantize, order flags and first relaxation, fused per tile
-  HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
-                            (uint16_t*)(ws + L.mask), sub, stamp, counters, hs,
-                            ev_only(ctx, LOPC_PHASE_QUANT)));
-
-  // repair sweeps (Alg. 1 loop at tile granularity).  The first group of K
-  // sweeps (K from the previous call on this context) is enqueued together
-  // with the encoder, which runs only if no tile is marked for sweep K + 1;
-  // one read of the status, the counters and Params then ends a typical
-  // call.  Otherwise sweeps continue in groups (4, 8, 16), one read per
-  // group, and the encoder runs after them.  A sweep with no marked tile
-  // costs one empty launch.
-  uint64_t sweeps = 1, active = tl.ntiles, relax_iters = 0;
+  const uint32_t nch = (uint32_t)((s.n + W - 1) / W);
+  uint64_t sweeps = 1, active = tl.ntiles;
   const uint32_t K = (uint32_t)ctx->sweep_hint;
-  const size_t report = L.counters + kCounterWords * 4;  // Params + counters
+  const size_t report = L.queue + sizeof(RepairQueue);
   for (uint32_t t = 1; t <= K; ++t) {
     Ev e = t == 1 ? ev_first(ctx, LOPC_PHASE_REPAIR) : Ev{};
     if (t == K) e.b = ev_last(ctx, LOPC_PHASE_REPAIR).b;
@@ -200,25 +173,16 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
                              ws + L.tail, offs, (uint32_t*)(ws + L.parts), prm,
                              (uint8_t*)d_stream, stream_cap, counters + 1 + ((K + 1) & 63), hs,
                              ev_only(ctx, LOPC_PHASE_ENCODE)));
-  if (h_stats)
-    HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+  if (want_parts)
+    HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), nch, prm, hs));
   HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
   HIP_CTX(ctx, hipStreamSynchronize(hs));
   uint32_t next = 1, batch = K;
   for (;;) {
     const uint32_t* hc = (const uint32_t*)((const uint8_t*)ctx->h_prm + L.counters);
     if (hc[0]) return LOPC_E_INTERNAL;
-    relax_iters = 0;
-    for (int q = 0; q < 64; ++q) {
-      uint64_t v;
-      std::memcpy(&v, hc + kRelaxWord + 2 * q, 8);
-      relax_iters += v;
-    }
-    int code = status_code(ctx->h_prm->status);
-    if (code != LOPC_OK && code != LOPC_E_CAPACITY) {
-      *h_stream_size = 0;
-      return code;
-    }
+    const int code = status_code(ctx->h_prm->status);
+    if (code != LOPC_OK && code != LOPC_E_CAPACITY) return code;
     // marks for sweep t are hc[1 + t % 64]; sweep t ran iff they are nonzero
     bool done = false;
     for (uint32_t t = next; t <= next + batch; ++t) {
@@ -236,10 +200,14 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     // clear the ring slots consumed by this group (marks for sweep
     // next + batch stay: the next group starts with it)
     for (uint32_t t = next; t < next + batch; ++t)
-      HIP_CTX(ctx, hipMemsetAsync(counters + 1 + (t & 63), 0, 4, hs));
+      HIP_CTX(ctx, launch_zero_n(counters + 1 + (t & 63), 1, hs));
     next += batch;
     batch = next == K + 1 ? 4 : std::min<uint32_t>(batch * 2, 16);
-    if (next + batch >= kMaxSweeps) return LOPC_E_INTERNAL;
+    if ((uint64_t)next + batch > limit) {
+      *sweeps_out = sweeps;
+      *active_out = active;
+      return limit >= s.n + 2 ? LOPC_E_INTERNAL : kRestartOnQueue;  // the former unreachable
+    }
     for (uint32_t b = 0; b < batch; ++b)
       HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
                                  counters, next + b, hs,
@@ -255,27 +223,194 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
                                (uint16_t*)(ws + L.mask), ws + L.tail, offs,
                                (uint32_t*)(ws + L.parts), prm, (uint8_t*)d_stream, stream_cap,
                                nullptr, hs, ev_only(ctx, LOPC_PHASE_ENCODE)));
-    if (h_stats)
-      HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+    if (want_parts)
+      HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), nch, prm, hs));
     HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
     HIP_CTX(ctx, hipStreamSynchronize(hs));
   }
+  *sweeps_out = sweeps;
+  *active_out = active;
+  return LOPC_OK;
+}
+
+int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
+                  const int64_t* dims, double error_bound, int mode,
+                  void* d_stream, size_t stream_cap, size_t* h_stream_size,
+                  uint64_t* d_stream_size, int32_t* d_status,
+                  void* d_ws, size_t ws_bytes, void* stream,
+                  lopc_stats* h_stats) {
+  if (!ctx || !d_field || !d_stream || !d_ws) return LOPC_E_ARG;
+  const bool enqueue_only = h_stream_size == nullptr;
+  // enqueued calls report on the device only, through a device-driven repair
+  if (enqueue_only && (!d_stream_size || h_stats || ctx->repair_mode == LOPC_REPAIR_SWEEPS))
+    return LOPC_E_ARG;
+  if ((dtype != 0 && dtype != 1) || (mode != 0 && mode != 1)) return LOPC_E_ARG;
+  Shape s;
+  int st = make_shape(ndim, dims, &s);
+  if (st) return st;
+  if (!std::isfinite(error_bound) || !(error_bound > 0)) return LOPC_E_BOUND;
+  if (((uintptr_t)d_field & 15) || ((uintptr_t)d_stream & 3)) return LOPC_E_ARG;
+  if (((uintptr_t)d_stream_size & 7) || ((uintptr_t)d_status & 3)) return LOPC_E_ARG;
+  CompressLayout L = compress_layout(s, dtype);
+  if (ws_bytes < L.total || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
+  hipStream_t hs = (hipStream_t)stream;
+  HIP_CTX(ctx, hipSetDevice(ctx->device));
+
+  uint8_t* ws = (uint8_t*)d_ws;
+  Params* prm = (Params*)(ws + L.prm);
+  uint32_t* sub = (uint32_t*)(ws + L.sub);
+  uint32_t* stamp = (uint32_t*)(ws + L.stamp);
+  uint32_t* counters = (uint32_t*)(ws + L.counters);
+  uint64_t* offs = (uint64_t*)(ws + L.offs);
+  const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
+  const uint64_t nch = (s.n + W - 1) / W;
+  Tiling tl = make_tiling(s.box);
+  const int rmode = ctx->repair_mode;
+  QueueRef Q{};
+  {
+    Q.q = (RepairQueue*)(ws + L.queue);
+    Q.ring = (unsigned long long*)(ws + L.ring);
+    Q.st = (uint32_t*)(ws + L.qstate);
+    Q.parked = (uint32_t*)(ws + L.parked);
+    Q.blockers = (uint32_t*)(ws + L.blockers);
+    Q.depth = (uint32_t*)(ws + L.depth);
+    Q.cap_log2 = L.cap_log2;
+  }
+
+  int nblocks = (int)std::min<uint64_t>(kMinmaxBlocks, (s.n + 2047) / 2048);
+  if (nblocks < 1) nblocks = 1;
+  // the zeroed prefix of the workspace is cleared by the range pass (NOA),
+  // else by a fill kernel
+  if (mode == LOPC_EB_NOA)
+    HIP_CTX(ctx, launch_minmax(dtype, d_field, (uint32_t)s.n, (double*)(ws + L.part),
+                               nblocks, ws, L.zero_end, hs, ev_first(ctx, LOPC_PHASE_RANGE)));
+  else
+    HIP_CTX(ctx, launch_zero_n((uint32_t*)ws, L.zero_end / 4, hs,
+                               ev_first(ctx, LOPC_PHASE_RANGE)));
+  HIP_CTX(ctx, launch_params(dtype, mode, error_bound, (const double*)(ws + L.part),
+                             nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
+                             s.d, hs, ev_last(ctx, LOPC_PHASE_RANGE)));
+  uint64_t sweeps = 1, active = tl.ntiles, qruns = 0, qparks = 0;
+  const int two_d = tl.tz == 1;
+  // Device-driven repair (Alg. 1 loop at tile granularity, no host read):
+  // the first pass (quantize, order flags, first relaxation, fused per
+  // tile), K sweeps over work lists, the repair queue for whatever is still
+  // listed (nothing, when K sweeps were enough; with K = 0 the first pass
+  // lists its tiles in the queue itself), then the encoder and the report.
+  auto device_repair = [&](uint32_t K) -> int {
+    if (!ctx->rq_per_cu[two_d]) ctx->rq_per_cu[two_d] = repair_q_blocks_per_cu(two_d);
+    if (!ctx->sl_per_cu[two_d]) ctx->sl_per_cu[two_d] = sweep_list_blocks_per_cu(two_d);
+    uint32_t* lists = K ? (uint32_t*)(ws + L.lists) : nullptr;
+    HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
+                              (uint16_t*)(ws + L.mask), sub, stamp, counters, lists,
+                              K ? QueueRef{} : Q, hs, ev_only(ctx, LOPC_PHASE_QUANT)));
+    const int sgrid = (int)std::max<uint64_t>(
+        1, std::min<uint64_t>(tl.ntiles, (uint64_t)ctx->sl_per_cu[two_d] * ctx->num_cu));
+    for (uint32_t t = 1; t <= K; ++t)
+      HIP_CTX(ctx, launch_sweep_list(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
+                                     counters, lists, t, sgrid, hs,
+                                     t == 1 ? ev_first(ctx, LOPC_PHASE_REPAIR) : Ev{}));
+    if (K) HIP_CTX(ctx, launch_seed_queue(counters, lists, tl.ntiles, K + 1, Q, hs));
+    const int grid = (int)std::max<uint64_t>(
+        1, std::min<uint64_t>(tl.ntiles, (uint64_t)ctx->rq_per_cu[two_d] * ctx->num_cu));
+    HIP_CTX(ctx, launch_repair_q(s.box, tl, (const uint16_t*)(ws + L.mask), sub, counters, Q,
+                                 grid, hs,
+                                 K ? ev_last(ctx, LOPC_PHASE_REPAIR)
+                                   : ev_only(ctx, LOPC_PHASE_REPAIR)));
+    HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, (uint16_t*)(ws + L.mask),
+                               ws + L.tail, offs, (uint32_t*)(ws + L.parts), prm,
+                               (uint8_t*)d_stream, stream_cap, nullptr, hs,
+                               ev_only(ctx, LOPC_PHASE_ENCODE)));
+    if (h_stats)
+      HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), (uint32_t)nch, prm, hs));
+    if (d_stream_size || d_status)
+      HIP_CTX(ctx, launch_report(prm, Q.q, d_stream_size, d_status, hs));
+    if (enqueue_only) return LOPC_OK;
+    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, L.queue + sizeof(RepairQueue),
+                                hipMemcpyDeviceToHost, hs));
+    HIP_CTX(ctx, hipStreamSynchronize(hs));
+    const uint32_t* hc = (const uint32_t*)((const uint8_t*)ctx->h_prm + L.counters);
+    const RepairQueue* hq = (const RepairQueue*)((const uint8_t*)ctx->h_prm + L.queue);
+    if (hc[0] || hq->err) return LOPC_E_INTERNAL;
+    for (uint32_t t = 1; t <= K; ++t) {
+      const uint32_t m = hc[1 + (t & 63)];
+      if (!m) break;
+      ++sweeps;
+      active += m;
+    }
+    if (hq->runs) sweeps = std::max<uint64_t>(sweeps, 1 + hq->max_depth);
+    active += hq->runs;
+    qruns = hq->runs;
+    qparks = hq->parks;
+    // the next call sweeps as often as this one needed, plus one
+    if (K)
+      ctx->sweep_hint = (int)std::min<uint64_t>(kMaxListSweeps, std::max<uint64_t>(2, sweeps));
+    return LOPC_OK;
+  };
+
+  int rc;
+  if (rmode == LOPC_REPAIR_QUEUE) {
+    rc = device_repair(0);
+  } else if (rmode == LOPC_REPAIR_HYBRID || (rmode == LOPC_REPAIR_AUTO && enqueue_only)) {
+    rc = device_repair((uint32_t)std::min<int>(std::max(ctx->sweep_hint, 1), (int)kMaxListSweeps));
+  } else {
+    // host-driven sweeps (the fastest schedule when dependencies cross few
+    // tiles); the default gives up after kAutoSweeps sweeps and restarts the
+    // repair from the first pass on the queue, which runs a chain across
+    // many tiles a few times per tile instead of once per sweep
+    HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
+                              (uint16_t*)(ws + L.mask), sub, stamp, counters, nullptr,
+                              QueueRef{}, hs, ev_only(ctx, LOPC_PHASE_QUANT)));
+    const uint64_t limit = rmode == LOPC_REPAIR_AUTO ? kAutoSweeps : s.n + 2;
+    rc = repair_by_sweeps(ctx, s, L, dtype, ws, d_stream, stream_cap, tl, h_stats != nullptr,
+                          hs, limit, &sweeps, &active);
+    if (rc == kRestartOnQueue) {
+      const uint64_t swept = sweeps, runs = active;
+      sweeps = 1;
+      active = tl.ntiles;
+      rc = device_repair(0);
+      sweeps = std::max(sweeps, swept);
+      active += runs;
+    } else if (rc == LOPC_OK && (d_stream_size || d_status)) {
+      HIP_CTX(ctx, launch_report(prm, nullptr, d_stream_size, d_status, hs));
+    }
+  }
+  if (rc == LOPC_E_HIP || rc == LOPC_E_INTERNAL) return rc;
+  if (rc != LOPC_OK) {
+    *h_stream_size = 0;
+    return rc;
+  }
+  if (enqueue_only) return LOPC_OK;
   if (ctx->timing) {
     for (int p = LOPC_PHASE_RANGE; p <= LOPC_PHASE_ENCODE; ++p) ctx->ms[p] = phase_ms(ctx, p);
   }
   const Params& hp = *ctx->h_prm;
+  const int code = status_code(hp.status);
+  if (code != LOPC_OK && code != LOPC_E_CAPACITY) {
+    *h_stream_size = 0;
+    return code;
+  }
   *h_stream_size = (size_t)hp.stream_size;
   std::memcpy(ctx->last_header, hp.header, kHeaderBytes);
-  ctx->have_header = status_code(hp.status) == LOPC_OK;
+  ctx->have_header = code == LOPC_OK;
   if (h_stats) {
+    const uint32_t* hc = (const uint32_t*)((const uint8_t*)ctx->h_prm + L.counters);
+    uint64_t relax_iters = 0;
+    for (int q = 0; q < 64; ++q) {
+      uint64_t v;
+      std::memcpy(&v, hc + kRelaxWord + 2 * q, 8);
+      relax_iters += v;
+    }
     h_stats->eps = hp.eps;
     h_stats->repair_sweeps = sweeps;
     h_stats->active_tiles_total = active;
     h_stats->relax_iterations = relax_iters;
     h_stats->bins_bytes = hp.bins_bytes;
     h_stats->subbins_bytes = hp.sub_bytes;
+    h_stats->queue_runs = qruns;
+    h_stats->queue_parks = qparks;
   }
-  return status_code(hp.status);
+  return code;
 }
 
 int lopc_stream_info(const void* h_header, size_t n, int* dtype, int* ndim,

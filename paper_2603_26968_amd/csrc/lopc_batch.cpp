@@ -581,6 +581,10 @@ int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value) {
       if (value < 0 || value > 400) return LOPC_E_ARG;
       ctx->persist_pct = (int)value;
       return LOPC_OK;
+    case LOPC_OPT_REPAIR:
+      if (value < LOPC_REPAIR_AUTO || value > LOPC_REPAIR_SWEEPS) return LOPC_E_ARG;
+      ctx->repair_mode = (int)value;
+      return LOPC_OK;
     default:
       return LOPC_E_ARG;
   }

@@ -1450,15 +1450,15 @@ hipError_t launch_encode(int dtype, uint32_t n, const void* bins, uint32_t* sub,
   S.tail = tail;
   S.tail_len = kRecordTailBytes;
   if (dtype == 0)
-    hipExtLaunchKernelGGL(k_encode<4>, dim3(nch), dim3(kCT), 0, s, ev.a, nullptr, 0, n,
+    launch_ev(k_encode<4>, dim3(nch), dim3(kCT), s, Ev{ev.a, nullptr}, n,
                           (const int32_t*)bins, (const uint32_t*)sub, parts, prm, stream,
                           (uint64_t)cap, nch, S, gate);
   else
-    hipExtLaunchKernelGGL(k_encode<8>, dim3(nch), dim3(kCT), 0, s, ev.a, nullptr, 0, n,
+    launch_ev(k_encode<8>, dim3(nch), dim3(kCT), s, Ev{ev.a, nullptr}, n,
                           (const int64_t*)bins, (const uint32_t*)sub, parts, prm, stream,
                           (uint64_t)cap, nch, S, gate);
   k_record_offsets<<<1, kOT, 0, s>>>(parts, nch, offs, prm, gate);
-  hipExtLaunchKernelGGL(k_place, dim3(nch), dim3(kThreads), 0, s, nullptr, ev.b, 0,
+  launch_ev(k_place, dim3(nch), dim3(kThreads), s, Ev{nullptr, ev.b},
                         (const uint32_t*)parts, (const uint64_t*)offs, nch, S, prm, stream,
                         (uint64_t)cap, gate);
   return hipGetLastError();
@@ -1473,7 +1473,7 @@ hipError_t launch_sum_parts(const uint32_t* parts, uint32_t nch, Params* prm,
 hipError_t launch_offsets(const uint8_t* stream, uint32_t nch,
                           uint64_t body_bytes, uint64_t* offsets, Params* prm,
                           hipStream_t s, Ev ev) {
-  hipExtLaunchKernelGGL(k_offsets, dim3(1), dim3(kOfT), 0, s, ev.a, ev.b, 0, stream, nch,
+  launch_ev(k_offsets, dim3(1), dim3(kOfT), s, ev, stream, nch,
                         body_bytes, offsets, prm);
   return hipGetLastError();
 }
@@ -1484,10 +1484,10 @@ hipError_t launch_decode(int dtype, const uint8_t* stream, uint32_t n,
   uint32_t W = kChunkBytes / (dtype == 0 ? 4 : 8);
   uint32_t nch = (n + W - 1) / W;
   if (dtype == 0)
-    hipExtLaunchKernelGGL(k_decode<4>, dim3(nch), dim3(kCT), 0, s, ev.a, ev.b, 0, stream, n,
+    launch_ev(k_decode<4>, dim3(nch), dim3(kCT), s, ev, stream, n,
                           offsets, prm, (uint32_t*)field);
   else
-    hipExtLaunchKernelGGL(k_decode<8>, dim3(nch), dim3(kCT), 0, s, ev.a, ev.b, 0, stream, n,
+    launch_ev(k_decode<8>, dim3(nch), dim3(kCT), s, ev, stream, n,
                           offsets, prm, (uint64_t*)field);
   return hipGetLastError();
 }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "lopc_internal.h"
@@ -187,6 +188,17 @@ __device__ V block_excl_scan(V v, V* sh, V& total) {
   total = sh[NW];
   __syncthreads();
   return res;
+}
+
+// Launch k on s; when a timing event is given the dispatch itself records
+// the kernel's start (ev.a) and end (ev.b), else it is an ordinary launch
+// (which stream capture records as a plain kernel node).
+template <typename... P, typename... A>
+inline void launch_ev(void (*k)(P...), dim3 g, dim3 b, hipStream_t s, Ev ev, A... a) {
+  if (ev.a || ev.b)
+    hipExtLaunchKernelGGL(k, g, b, 0, s, ev.a, ev.b, 0, a...);
+  else
+    k<<<g, b, 0, s>>>(a...);
 }
 
 __device__ __forceinline__ void put_bytes(uint8_t* dst, uint64_t v, int nbytes) {

@@ -47,6 +47,9 @@ struct lopc_ctx {
   hipEvent_t ev[2 * LOPC_PHASES];  // per phase: first kernel's start, last kernel's end
   double ms[LOPC_PHASES];
   int sweep_hint;      // single field: repair sweeps enqueued before the first read
+  int repair_mode;     // single field: LOPC_REPAIR_HYBRID, _QUEUE or _SWEEPS
+  int rq_per_cu[2];    // resident repair-queue workgroups per CU (3D, 2D tiles)
+  int sl_per_cu[2];    // resident list-sweep workgroups per CU (3D, 2D tiles)
   // batches
   int use_graph;       // capture batch sequences as graphs
   int graph_sweeps;    // sweeps per graph (0 = adaptive)
@@ -68,10 +71,9 @@ struct lopc_ctx {
 namespace lopc_host {
 using namespace lopc;
 
-constexpr uint32_t kMaxSweeps = 1u << 16;
 constexpr int kMinmaxBlocks = 1024;
 
-inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Shape {
   int ndim;
@@ -120,8 +122,9 @@ inline Tiling make_tiling(const Box& b) {
 }
 
 struct CompressLayout {
-  size_t prm, counters, stamp, zero_end;  // zeroed prefix
-  size_t offs, parts, part, bins, mask, sub, tail, total;
+  size_t prm, counters, queue, stamp, qstate, parked, depth, ring, zero_end;  // zeroed prefix
+  size_t blockers, lists, offs, parts, part, bins, mask, sub, tail, total;
+  uint32_t cap_log2;  // repair queue ring: 2^cap_log2 slots
 };
 
 // repair counters (kCounterWords words): [0] internal error flag,
@@ -135,10 +138,20 @@ inline CompressLayout compress_layout(const Shape& s, int dtype) {
   Tiling t = make_tiling(s.box);
   CompressLayout L;
   size_t o = 0;
+  L.cap_log2 = queue_cap_log2(t.ntiles);
   L.prm = o; o += align256(sizeof(Params));
   L.counters = o; o += align256(kCounterWords * 4);
+  L.queue = o; o += align256(sizeof(RepairQueue));
   L.stamp = o; o += align256((size_t)t.ntiles * 4);
+  L.qstate = o; o += align256((size_t)t.ntiles * 4);
+  L.parked = o; o += align256((size_t)t.ntiles * 4);
+  L.depth = o; o += align256((size_t)t.ntiles * 4);
+  L.ring = o; o += align256((size_t)8 << L.cap_log2);
+  static_assert(align256(sizeof(Params)) + align256(kCounterWords * 4) + sizeof(RepairQueue) <= 4096,
+                "the compress report fits its pinned host slot");
   L.zero_end = o;
+  L.blockers = o; o += align256((size_t)t.ntiles * 4);
+  L.lists = o; o += align256((size_t)t.ntiles * 8);
   L.offs = o; o += align256(nch * 8);
   L.parts = o; o += align256(nch * 8);
   L.part = o; o += align256(16 * kMinmaxBlocks);

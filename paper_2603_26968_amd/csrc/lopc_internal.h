@@ -71,9 +71,73 @@ constexpr uint32_t kMinmaxSpan = 16384;
 // Work-list ring: slot s % 64 holds sweep s.
 constexpr uint32_t kRing = 64;
 // Single-field repair counters: [0] error flag, [1 + s % 64] tiles marked for
-// sweep s, from [kRelaxWord] 64 64-bit slots of relaxation-pass counts.
+// sweep s (the length of its work list), from [kRelaxWord] 64 64-bit slots of
+// relaxation-pass counts, from [kCursorWord] the work-list cursor of sweep s
+// at [kCursorWord + s % 64].
 constexpr uint32_t kRelaxWord = 66;
-constexpr uint32_t kCounterWords = kRelaxWord + 128;
+constexpr uint32_t kCursorWord = kRelaxWord + 128;
+constexpr uint32_t kCounterWords = kCursorWord + 64;
+// Sweeps that the hybrid repair runs over work lists before the queue takes
+// over (the ring of list lengths must not wrap).
+constexpr uint32_t kMaxListSweeps = 48;
+// Host-driven sweeps of the default scheduler before it restarts the repair
+// on the queue (a dependency chain across this many tiles reruns nearly
+// every tile on every sweep).
+constexpr uint32_t kAutoSweeps = 64;
+
+// ------------------------------------------------------------- repair queue
+// Device-driven repair: tiles whose halo changed are listed in a work queue
+// that a persistent grid drains until no tile is listed or running, so the
+// fixed point is reached inside one launch, whatever the number of tiles a
+// dependency chain crosses.  The ring holds 64-bit slots: high word 2L + 1
+// while it holds the item of lap L (low word), 2L when it is free for lap L
+// (so zeroed memory is an empty queue); head and tail are tickets.  A tile
+// is listed at most once at a time (its state word), so a ring of at least
+// as many slots as tiles never overruns.
+//
+// A tile that already ran in this repair and is taken again while a
+// neighbour tile of higher index that it depends on is listed or running
+// would only see values about to change: it parks on that tile instead (bit
+// of its direction in the neighbour's parked word) and is listed again when
+// the neighbour's run ends.  Parking follows strictly increasing tile index,
+// so it never forms a cycle; a chain that crosses T tiles then costs about
+// 2T tile runs instead of up to T^2 / 2.
+// (the words that waiting workers poll sit on cache lines of their own)
+struct alignas(256) RepairQueue {
+  unsigned long long head;  // tickets taken by workers
+  uint8_t pad0[248];
+  unsigned long long tail;  // tickets taken by producers
+  uint8_t pad1[248];
+  int32_t pending;          // tiles listed (queued or parked) or running
+  uint8_t pad2[252];
+  uint32_t err;             // a wait saw no progress of the queue for kQueueStall
+  uint32_t max_depth;       // longest chain of tile runs (first pass = 0)
+  unsigned long long runs;  // tile runs of the repair kernel
+  unsigned long long parks; // times a taken tile parked
+};
+// A wait in the repair queue that sees neither tail nor pending move for
+// this many wall-clock ticks (100 MHz: 20 s) gives up and flags `err`
+// (never expected: it turns a scheduling bug into LOPC_E_INTERNAL instead
+// of a kernel that does not end).
+constexpr unsigned long long kQueueStall = 2000000000ull;
+enum : uint32_t { TS_LISTED = 1u, TS_RUNNING = 2u, TS_RAN = 4u };
+struct QueueRef {
+  RepairQueue* q;
+  unsigned long long* ring;
+  uint32_t* st;        // per tile item: TS_* bits (zeroed)
+  uint32_t* parked;    // per tile item: directions of the tiles parked on it (zeroed)
+  uint32_t* blockers;  // per tile item: higher-index directions it depends on
+                       // (bits 14..26 of the 27-direction set; written by the first pass)
+  uint32_t* depth;     // per tile item: chain depth it was listed at (max; zeroed)
+  uint32_t cap_log2;
+};
+constexpr uint32_t kNoTile = 0xffffffffu;
+// ring slots for `tiles` tile items: the next power of two, at least 64
+inline uint32_t queue_cap_log2(uint64_t tiles) {
+  uint32_t l = 6;
+  while ((1ull << l) < tiles) ++l;
+  return l;
+}
 
 // group of a field: 2 * dtype + (3D)
 constexpr int kGroups = 4;
@@ -173,9 +237,35 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
                          int nblocks, Params* prm, uint8_t* stream,
                          size_t cap, int ndim, const int64_t* dims,
                          hipStream_t s, Ev ev = {});
+// Q.q null: marks tiles for host-driven sweeps (launch_repair); else lists
+// them in the repair queue drained by launch_repair_q.
+// lists (may be null): the marked tiles are also appended to the work list
+// of sweep 1.
 hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
-                        uint32_t* counters, hipStream_t s, Ev ev = {});
+                        uint32_t* counters, uint32_t* lists, const QueueRef& Q, hipStream_t s,
+                        Ev ev = {});
+// One sweep over the work list of sweep `sweep` (lists: two arrays of
+// t.ntiles items, sweep parity), appending the tiles it marks to the list
+// of the next sweep; a persistent grid of `grid` workgroups drains the list.
+hipError_t launch_sweep_list(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
+                             uint32_t* stamp, uint32_t* counters, uint32_t* lists,
+                             uint32_t sweep, int grid, hipStream_t s, Ev ev = {});
+int sweep_list_blocks_per_cu(bool two_d);
+// Lists the tiles of the work list of sweep `sweep` in the repair queue.
+hipError_t launch_seed_queue(const uint32_t* counters, const uint32_t* lists, uint32_t ntiles,
+                             uint32_t sweep, const QueueRef& Q, hipStream_t s);
+// Device-driven repair over the queue filled by launch_tile0 (grid: the
+// resident capacity, repair_q_blocks_per_cu per CU).
+hipError_t launch_repair_q(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
+                           uint32_t* counters, const QueueRef& Q, int grid, hipStream_t s,
+                           Ev ev = {});
+int repair_q_blocks_per_cu(bool two_d);
+// Writes the stream size (0 after a failure other than capacity) and the
+// lopc_status code of a compression to the caller's device words (either
+// may be null); q (may be null): its repair queue.
+hipError_t launch_report(const Params* prm, const RepairQueue* q, uint64_t* d_size,
+                         int32_t* d_status, hipStream_t s);
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask,
                          uint32_t* sub, uint32_t* stamp, uint32_t* counters,
                          uint32_t sweep, hipStream_t s, Ev ev = {});

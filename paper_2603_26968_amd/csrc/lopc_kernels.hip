@@ -224,6 +224,19 @@ __device__ __forceinline__ uint32_t block_or32(uint32_t v) {
   return r;
 }
 
+// OR of v over the workgroup (every thread gets it)
+__device__ __forceinline__ uint64_t block_or64(uint64_t v) {
+  __shared__ uint64_t w[kWaves];
+  v = wave_reduce(v, OpOr{});
+  if (lane() == 0) w[wave()] = v;
+  __syncthreads();
+  uint64_t r = 0;
+#pragma unroll
+  for (int q = 0; q < kWaves; ++q) r |= w[q];
+  __syncthreads();
+  return r;
+}
+
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
 // index.  Give each XCD a contiguous range of tiles instead, so that tiles
 // that share halo data share an L2: workgroup b (of n) takes tile
@@ -419,6 +432,208 @@ __device__ void mark_neighbours(uint32_t dirs, const TileCoord& c, const Tiling&
   }
 }
 
+// mark_neighbours, and also append the newly marked tiles to the work list
+// of sweep `next` (lists: two arrays of tl.ntiles items, sweep parity; each
+// tile is listed at most once per sweep, so a list never overflows)
+__device__ void mark_list1(uint32_t dirs, const TileCoord& c, const Tiling& tl, uint32_t* stamp,
+                           uint32_t* counters, uint32_t* lists, uint32_t next) {
+  if (threadIdx.x >= 64) return;
+  bool newly = false;
+  uint32_t u = 0;
+  if (threadIdx.x < 27 && ((dirs >> threadIdx.x) & 1u)) {
+    const int dz = (int)threadIdx.x / 9 - 1, dy = ((int)threadIdx.x / 3) % 3 - 1,
+              dx = (int)threadIdx.x % 3 - 1;
+    const int nz = c.tz + dz, ny = c.ty + dy, nx = c.tx + dx;
+    if ((dz | dy | dx) != 0 && nz >= 0 && nz < tl.ntz && ny >= 0 && ny < tl.nty && nx >= 0 &&
+        nx < tl.ntx) {
+      u = ((uint32_t)nz * tl.nty + ny) * tl.ntx + nx;
+      newly = atomicMax(&stamp[u], next) < next;
+    }
+  }
+  const uint64_t m = __ballot(newly);
+  if (!m) return;
+  uint32_t pos = 0;
+  if (threadIdx.x == 0) pos = atomicAdd(&counters[1 + (next & 63)], (uint32_t)__popcll(m));
+  pos = __shfl(pos, 0, 64);
+  if (newly) lists[(next & 1) * tl.ntiles + pos + lane_prefix(m)] = u;
+}
+
+// ------------------------------------------------------------- repair queue
+// Tile item of the neighbour in direction bit `d` (27-direction set) of the
+// tile at c, in a field whose tile items start at t0.
+__device__ __forceinline__ uint32_t dir_tile(int d, const TileCoord& c, const Tiling& tl,
+                                             uint32_t t0) {
+  const int nz = c.tz + d / 9 - 1, ny = c.ty + (d / 3) % 3 - 1, nx = c.tx + d % 3 - 1;
+  return t0 + ((uint32_t)nz * tl.nty + ny) * tl.ntx + nx;
+}
+__device__ __forceinline__ bool dir_inside(int d, const TileCoord& c, const Tiling& tl) {
+  const int nz = c.tz + d / 9 - 1, ny = c.ty + (d / 3) % 3 - 1, nx = c.tx + d % 3 - 1;
+  return d != 13 && nz >= 0 && nz < tl.ntz && ny >= 0 && ny < tl.nty && nx >= 0 &&
+         nx < tl.ntx;
+}
+
+// Publish a listed tile item in the ring (any lane): a tail ticket, then
+// wait until the slot's previous item has been taken (never long: at most
+// as many items as tiles are in the ring at once).  Release: what the
+// caller did before (counting the item as pending) is visible to the worker
+// that takes it.
+// Watchdog of a queue wait: true once the queue has shown no progress (tail
+// and pending unchanged) for kQueueStall ticks, or another wait gave up.
+struct QueueWatch {
+  unsigned long long tail = ~0ull, since = 0;
+  int32_t pending = -1;
+  __device__ bool stalled(const QueueRef& Q) {
+    if (__hip_atomic_load(&Q.q->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+    const unsigned long long tl =
+        __hip_atomic_load(&Q.q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t pd = __hip_atomic_load(&Q.q->pending, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long now = wall_clock64();
+    if (tl != tail || pd != pending) {
+      tail = tl;
+      pending = pd;
+      since = now;
+      return false;
+    }
+    if (now - since < kQueueStall) return false;
+    atomicOr(&Q.q->err, 1u);
+    return true;
+  }
+};
+
+__device__ void q_publish(const QueueRef& Q, uint32_t item) {
+  const unsigned long long pos = atomicAdd(&Q.q->tail, 1ull);
+  unsigned long long* slot = Q.ring + (pos & ((1ull << Q.cap_log2) - 1ull));
+  const uint32_t lap2 = (uint32_t)(pos >> Q.cap_log2) * 2u;
+  QueueWatch w;
+  for (uint32_t k = 0;
+       (uint32_t)(__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) !=
+       lap2;
+       ++k) {
+    if ((k & 63u) == 63u && w.stalled(Q)) return;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  __hip_atomic_store(slot, (unsigned long long)(lap2 + 1u) << 32 | item, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// List tile item `item` (any lane): nothing if it is listed already, else
+// count it as pending and publish it.  The caller has released the subbins
+// it wrote (a fence at agent scope) before listing; the worker that runs the
+// item acquires them through its state word.
+__device__ void q_push(const QueueRef& Q, uint32_t item, uint32_t depth) {
+  atomicMax(&Q.depth[item], depth);
+  if (__hip_atomic_fetch_or(&Q.st[item], TS_LISTED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+      TS_LISTED)
+    return;
+  atomicAdd(&Q.q->pending, 1);
+  q_publish(Q, item);
+}
+
+// Take the next item from the ring (one thread of a workgroup): a head
+// ticket, then wait for its slot to be filled; kNoTile once nothing is
+// listed or running (nothing can be listed after that: only running tiles
+// list others).
+__device__ uint32_t q_pop(const QueueRef& Q) {
+  const unsigned long long pos = atomicAdd(&Q.q->head, 1ull);
+  unsigned long long* slot = Q.ring + (pos & ((1ull << Q.cap_log2) - 1ull));
+  const uint32_t full = (uint32_t)(pos >> Q.cap_log2) * 2u + 1u;
+  unsigned long long v;
+  QueueWatch w;
+  // back off while waiting: a thousand idle workers polling at full rate
+  // would crowd the memory channel of the words they poll
+  uint32_t nap = 1;
+  for (uint32_t k = 0;; ++k) {
+    v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(v >> 32) == full) break;
+    if ((k & 3u) == 3u &&
+        __hip_atomic_load(&Q.q->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+      return kNoTile;
+    if ((k & 255u) == 255u && w.stalled(Q)) return kNoTile;
+    for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(8);
+    nap = nap < 16u ? nap * 2u : 16u;
+  }
+  __hip_atomic_store(slot, (unsigned long long)(full + 1u) << 32, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  return (uint32_t)v;
+}
+
+// Decide what to do with a taken item t (one thread): true = run it now.
+// * t is running on another worker (it was listed again during that run):
+//   it parks on itself (direction 13) and is published again when that run
+//   ends, so two runs of one tile never overlap (a slower run could
+//   otherwise store smaller values over a faster one's).
+// * t ran before in this repair: it parks on the first listed or running
+//   neighbour of higher index that it depends on (its blockers, stored by
+//   its first run), and is published again when that neighbour's run ends.
+// * otherwise it runs (`first`: its first run in this repair): it clears
+//   its listed bit, acquiring the subbins released by every worker that
+//   listed it; a change after that lists it again.
+// The parking handshakes (parked bit, then the other tile's state; the
+// other tile at the end of its run: its state, then its parked word) are
+// sequentially consistent, so no wake-up is lost; a parker that finds the
+// other tile idle takes its bit back and publishes itself.
+__device__ bool q_park(const QueueRef& Q, uint32_t t, uint32_t v, uint32_t bit) {
+  __hip_atomic_fetch_or(&Q.parked[v], bit, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+  if (!(__hip_atomic_fetch_or(&Q.st[v], 0u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) &
+        (v == t ? TS_RUNNING : (TS_LISTED | TS_RUNNING)))) {
+    if (__hip_atomic_fetch_and(&Q.parked[v], ~bit, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT) &
+        bit)
+      q_publish(Q, t);
+  }
+  return false;
+}
+
+__device__ bool q_claim(const QueueRef& Q, uint32_t t, const TileCoord& c, const Tiling& tl,
+                        uint32_t t0, unsigned long long& parks, bool& first) {
+  const uint32_t old =
+      __hip_atomic_fetch_or(&Q.st[t], TS_RUNNING, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+  if (old & TS_RUNNING) {
+    ++parks;
+    return q_park(Q, t, t, 1u << 13);
+  }
+  if (old & TS_RAN) {
+    uint32_t bl = __hip_atomic_load(&Q.blockers[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (bl) {
+      const int d = 31 - __builtin_clz(bl);  // the farthest in index first
+      bl &= ~(1u << d);
+      const uint32_t v = dir_tile(d, c, tl, t0);
+      if (!(__hip_atomic_load(&Q.st[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+            (TS_LISTED | TS_RUNNING)))
+        continue;
+      __hip_atomic_fetch_and(&Q.st[t], ~TS_RUNNING, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+      ++parks;
+      return q_park(Q, t, v, 1u << (26 - d));
+    }
+  }
+  first = !(old & TS_RAN);
+  __hip_atomic_fetch_and(&Q.st[t], ~TS_LISTED, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  if (first)
+    __hip_atomic_fetch_or(&Q.st[t], TS_RAN, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+// End of a run of tile t (wave 0 of its block): list the neighbour tiles in
+// `dirs` (27-bit set, see out_dirs) after releasing the block's subbin
+// stores, stop running, publish the tiles parked on t, and stop counting
+// the run as pending.
+__device__ void q_finish(uint32_t dirs, uint32_t t, const TileCoord& c, const Tiling& tl,
+                         const QueueRef& Q, uint32_t t0, uint32_t depth) {
+  if (dirs) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (threadIdx.x < 27 && ((dirs >> threadIdx.x) & 1u) && dir_inside((int)threadIdx.x, c, tl))
+    q_push(Q, dir_tile((int)threadIdx.x, c, tl, t0), depth);
+  uint32_t woke = 0;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_and(&Q.st[t], ~TS_RUNNING, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    woke = __hip_atomic_exchange(&Q.parked[t], 0u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  woke = __shfl(woke, 0, 64);
+  if (threadIdx.x < 27 && ((woke >> threadIdx.x) & 1u))
+    q_publish(Q, dir_tile((int)threadIdx.x, c, tl, t0));
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(&Q.q->pending, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // First pass, fused: build the order flags of the owned points (a2, the
 // flags of Alg. 1) from the bins and values of the tile and its halo, write
 // them, then relax with halo subbins 0 (the first sweep of a3).
@@ -550,17 +765,27 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
   return block_or32(dirs);
 }
 
+// Q.q null: mark the tiles to sweep next (and append them to the work list
+// of sweep 1 when lists is given); else list them in the repair queue (the
+// kernel boundary publishes the subbins).
 template <int K, int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_tile0(
     const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl, Params* prm,
     typename Traits<K>::Bin* __restrict__ bins,
     uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
-    uint32_t* counters) {
+    uint32_t* counters, uint32_t* lists, QueueRef Q) {
   TileCoord c;
   const uint32_t dirs = tile0_body<K, TZ, TY, TX>(x, box, tl, prm, bins, mask, sub, counters,
                                                   relax_total(counters),
                                                   xcd_tile(blockIdx.x, gridDim.x), c);
-  mark_neighbours(dirs, c, tl, stamp, counters, 1);
+  if (Q.q) {
+    if (threadIdx.x < 27 && ((dirs >> threadIdx.x) & 1u) && dir_inside((int)threadIdx.x, c, tl))
+      q_push(Q, dir_tile((int)threadIdx.x, c, tl, 0), 1);
+  } else if (lists) {
+    mark_list1(dirs, c, tl, stamp, counters, lists, 1);
+  } else {
+    mark_neighbours(dirs, c, tl, stamp, counters, 1);
+  }
 }
 
 
@@ -568,18 +793,24 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
 // One sweep of tile t if it is marked for it.  Returns (block-uniform) the
 // neighbour tiles holding a point whose flags name a changed boundary point
 // of this tile as a lower neighbour (0 if the tile did not run).
-template <int TZ, int TY, int TX>
+// QM (queue mode): the tile was taken from the repair queue, and other
+// workgroups change subbins while it runs, so subbins are read and written
+// as relaxed atomics at agent scope (coherent across the XCDs' L2 caches).
+// With `blockers` given, thread 0 stores there the higher-index
+// neighbour tiles holding a same-bin lower neighbour of one of the tile's
+// points (the tiles its run depends on; bits 14..26 of the 27-direction set).
+template <int TZ, int TY, int TX, bool QM = false>
 __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
                             uint32_t* __restrict__ sub, const uint32_t* stamp,
                             uint32_t* counters, unsigned long long* itot, uint32_t sweep,
-                            uint32_t t, TileCoord& c) {
+                            uint32_t t, TileCoord& c, uint32_t* blockers = nullptr) {
   using G = TileGeom<TZ, TY, TX>;
   constexpr int NJ = TZ == 1 ? 6 : 14;
   __shared__ uint32_t S[G::H];
   __shared__ uint16_t M[G::H];  // flags of the halo and the owned points
   // one read decides for the whole block (a neighbour may raise the stamp
   // concurrently)
-  if (!__syncthreads_or(threadIdx.x == 0 && stamp[t] >= sweep)) return 0;
+  if (!QM && !__syncthreads_or(threadIdx.x == 0 && stamp[t] >= sweep)) return 0;
   c = tile_coord<TZ, TY, TX>(t, tl);
   constexpr int HL = (G::H + kThreads - 1) / kThreads;
   {
@@ -595,7 +826,8 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
         int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, x = c.x0 + hx - 1;
         if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx) {
           const int64_t g = ((int64_t)z * box.ny + y) * box.nx + x;
-          hv[q] = sub[g];
+          hv[q] = QM ? __hip_atomic_load(sub + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : sub[g];
           hm[q] = mask[g];
         }
       }
@@ -627,7 +859,9 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
     const uint32_t v = S[li];
     if (v != old[k]) {
       const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
-      sub[((int64_t)(c.z0 + iz) * box.ny + c.y0 + iy) * box.nx + c.x0 + ix] = v;
+      uint32_t* dst = sub + ((int64_t)(c.z0 + iz) * box.ny + c.y0 + iy) * box.nx + c.x0 + ix;
+      if (QM) __hip_atomic_store(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else *dst = v;
       if (G::on_edge(i)) {
         // halo neighbours whose flags name this point (offset j from here is
         // offset j ^ 1 from there)
@@ -644,6 +878,17 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
       }
     }
   }
+  if (QM && blockers) {
+    uint32_t ups = 0;
+#pragma unroll
+    for (int k = 0; k < G::PER; ++k) {
+      const int i = threadIdx.x + k * kThreads;
+      if (mk[k] && G::on_edge(i)) ups |= out_dirs<TZ, TY, TX>(i, mk[k]);
+    }
+    const uint64_t both = block_or64((uint64_t)ups << 32 | dirs);
+    if (threadIdx.x == 0) blockers[t] = (uint32_t)(both >> 32) & ~0x3fffu;
+    return (uint32_t)both;
+  }
   return block_or32(dirs);
 }
 
@@ -659,7 +904,117 @@ __global__ __launch_bounds__(kThreads) void k_repair(
   if (dirs) mark_neighbours(dirs, c, tl, stamp, counters, sweep + 1);
 }
 
+// Device-driven repair of a single field: a persistent grid takes tiles from
+// the repair queue until nothing is listed or running.  A tile run reloads
+// the halo, relaxes, writes what changed, releases it and lists the
+// neighbour tiles that depend on a changed boundary point; then the run
+// stops counting as pending.  Subbins only rise and stay below the least
+// fixed point, so the result does not depend on the order of the runs.
+// One sweep over a work list: a persistent grid takes the listed tiles
+// through a cursor; each reloads its halo, relaxes, writes what changed and
+// lists the neighbour tiles that depend on a changed boundary point for the
+// next sweep.  An empty list costs one atomic per workgroup.  The run is
+// out of line for the reason given at repair_run below.
 
+template <int TZ, int TY, int TX>
+__device__ __noinline__ uint32_t sweep_run(Box box, Tiling tl, const uint16_t* __restrict__ mask,
+                                           uint32_t* __restrict__ sub, const uint32_t* stamp,
+                                           uint32_t* counters, uint32_t sweep, uint32_t t) {
+  TileCoord c;
+  return repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, relax_total(counters),
+                                 sweep, t, c);
+}
+
+template <int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_sweep_list(
+    Box box, Tiling tl, const uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
+    uint32_t* stamp, uint32_t* counters, uint32_t* lists, uint32_t sweep) {
+  __shared__ uint32_t s_it;
+  const uint32_t n = counters[1 + (sweep & 63)];
+  const uint32_t* in = lists + (sweep & 1) * tl.ntiles;
+  for (;;) {
+    if (threadIdx.x == 0) s_it = atomicAdd(&counters[kCursorWord + (sweep & 63)], 1u);
+    __syncthreads();
+    const uint32_t it = s_it;
+    __syncthreads();
+    if (it >= n) break;
+    const uint32_t t = in[it];
+    const uint32_t dirs = sweep_run<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, sweep, t);
+    if (dirs) mark_list1(dirs, tile_coord<TZ, TY, TX>(t, tl), tl, stamp, counters, lists,
+                         sweep + 1);
+  }
+}
+
+// The tiles listed for sweep `sweep` become the first items of the queue.
+__global__ __launch_bounds__(kThreads) void k_seed_queue(const uint32_t* counters,
+                                                         const uint32_t* lists, uint32_t ntiles,
+                                                         uint32_t sweep, QueueRef Q) {
+  const uint32_t n = counters[1 + (sweep & 63)];
+  const uint32_t* in = lists + (sweep & 1) * ntiles;
+  for (uint32_t i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads)
+    q_push(Q, in[i], sweep);
+}
+
+// One queued tile run, kept out of line: inlined into the worker loop, the
+// per-thread halo offsets of the body were hoisted out of the loop and kept
+// live across it (180 VGPRs instead of 67).  Its LDS arrays are its own, so
+// their accesses still compile to ds_* instructions.
+template <int TZ, int TY, int TX>
+__device__ __noinline__ uint32_t repair_run(Box box, Tiling tl, const uint16_t* __restrict__ mask,
+                                            uint32_t* __restrict__ sub, uint32_t* counters,
+                                            uint32_t t, uint32_t* blockers) {
+  TileCoord c;
+  return repair_body<TZ, TY, TX, true>(box, tl, mask, sub, nullptr, counters,
+                                       relax_total(counters), 0, t, c, blockers);
+}
+
+template <int TZ, int TY, int TX>
+__global__ __launch_bounds__(kThreads) void k_repair_q(
+    Box box, Tiling tl, const uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
+    uint32_t* counters, QueueRef Q) {
+  __shared__ uint32_t s_item, s_depth, s_first;
+  unsigned long long runs = 0, parks = 0;
+  uint32_t deepest = 0;
+  // nothing listed (the usual end of the work-list sweeps): leave at once
+  // without taking tickets
+  if (__hip_atomic_load(&Q.q->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      uint32_t it;
+      bool first = false;
+      for (;;) {
+        it = q_pop(Q);
+        if (it == kNoTile) break;
+        const TileCoord c = tile_coord<TZ, TY, TX>(it, tl);
+        if (q_claim(Q, it, c, tl, 0, parks, first)) break;
+      }
+      s_item = it;
+      s_first = first;
+      s_depth = it == kNoTile ? 0u
+                              : __hip_atomic_load(&Q.depth[it], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t t = s_item, d = s_depth;
+    if (t == kNoTile) break;
+    // ends with block barriers: s_item may be rewritten after it
+    const uint32_t dirs = repair_run<TZ, TY, TX>(box, tl, mask, sub, counters, t,
+                                                 s_first ? Q.blockers : nullptr);
+    const TileCoord c = tile_coord<TZ, TY, TX>(t, tl);
+    if (threadIdx.x < 64) {
+      q_finish(dirs, t, c, tl, Q, 0, d + 1);
+      if (threadIdx.x == 0) {
+        ++runs;
+        deepest = d > deepest ? d : deepest;
+      }
+    }
+  }
+  if (threadIdx.x == 0 && runs + parks) {
+    atomicAdd(&Q.q->runs, runs);
+    atomicAdd(&Q.q->parks, parks);
+    atomicMax(&Q.q->max_depth, deepest);
+  }
+}
 
 // ------------------------------------------------------------------ batches
 // Persistent kernels: a fixed grid drains the batch-wide items of one phase.
@@ -837,10 +1192,10 @@ hipError_t launch_minmax(int dtype, const void* x, uint32_t n, double* part,
                          int nblocks, void* zero, size_t zero_bytes, hipStream_t s, Ev ev) {
   const uint32_t nz = (uint32_t)(zero_bytes / 16);
   if (dtype == 0)
-    hipExtLaunchKernelGGL(k_minmax<4>, dim3(nblocks), dim3(kThreads), 0, s, ev.a, ev.b, 0,
+    launch_ev(k_minmax<4>, dim3(nblocks), dim3(kThreads), s, ev,
                           (const uint32_t*)x, n, (int64_t*)part, (uint4*)zero, nz);
   else
-    hipExtLaunchKernelGGL(k_minmax<8>, dim3(nblocks), dim3(kThreads), 0, s, ev.a, ev.b, 0,
+    launch_ev(k_minmax<8>, dim3(nblocks), dim3(kThreads), s, ev,
                           (const uint64_t*)x, n, (int64_t*)part, (uint4*)zero, nz);
   return hipGetLastError();
 }
@@ -850,11 +1205,11 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
                          int ndim, const int64_t* dims, hipStream_t s, Ev ev) {
   int64_t d2 = ndim == 3 ? dims[2] : 1;
   if (dtype == 0)
-    hipExtLaunchKernelGGL(k_params<4>, dim3(1), dim3(kThreads), 0, s, ev.a, ev.b, 0, mode, eb,
+    launch_ev(k_params<4>, dim3(1), dim3(kThreads), s, ev, mode, eb,
                           (const int64_t*)part, nblocks, prm, stream, (uint64_t)cap, ndim,
                           dims[0], dims[1], d2);
   else
-    hipExtLaunchKernelGGL(k_params<8>, dim3(1), dim3(kThreads), 0, s, ev.a, ev.b, 0, mode, eb,
+    launch_ev(k_params<8>, dim3(1), dim3(kThreads), s, ev, mode, eb,
                           (const int64_t*)part, nblocks, prm, stream, (uint64_t)cap, ndim,
                           dims[0], dims[1], d2);
   return hipGetLastError();
@@ -862,24 +1217,96 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
 
 hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
-                        uint32_t* counters, hipStream_t s, Ev ev) {
+                        uint32_t* counters, uint32_t* lists, const QueueRef& Q, hipStream_t s,
+                        Ev ev) {
   const dim3 g(t.ntiles), b(kThreads);
   if (t.tz == 1) {
     if (dtype == 0)
-      hipExtLaunchKernelGGL(k_tile0<4, 1, 32, 64>, g, b, 0, s, ev.a, ev.b, 0, (const uint32_t*)x,
-                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters);
+      launch_ev(k_tile0<4, 1, 32, 64>, g, b, s, ev, (const uint32_t*)x,
+                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters, lists, Q);
     else
-      hipExtLaunchKernelGGL(k_tile0<8, 1, 32, 64>, g, b, 0, s, ev.a, ev.b, 0, (const uint64_t*)x,
-                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters);
+      launch_ev(k_tile0<8, 1, 32, 64>, g, b, s, ev, (const uint64_t*)x,
+                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters, lists, Q);
   } else {
     if (dtype == 0)
-      hipExtLaunchKernelGGL(k_tile0<4, 8, 8, 32>, g, b, 0, s, ev.a, ev.b, 0, (const uint32_t*)x,
-                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters);
+      launch_ev(k_tile0<4, 8, 8, 32>, g, b, s, ev, (const uint32_t*)x,
+                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters, lists, Q);
     else
-      hipExtLaunchKernelGGL(k_tile0<8, 8, 8, 32>, g, b, 0, s, ev.a, ev.b, 0, (const uint64_t*)x,
-                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters);
+      launch_ev(k_tile0<8, 8, 8, 32>, g, b, s, ev, (const uint64_t*)x,
+                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters, lists, Q);
   }
   return hipGetLastError();
+}
+
+namespace {
+// the caller's result words of an enqueued compression: the stream size
+// (also when the buffer was short) and the status code of the ST_* bits
+// (precedence as in the synchronous calls)
+__global__ void k_report(const Params* prm, const RepairQueue* q, uint64_t* d_size,
+                         int32_t* d_status) {
+  const uint32_t st = prm->status | (q && q->err ? ST_INTERNAL : 0u);
+  const int32_t code = (st & ST_NONFINITE) ? -2 : (st & ST_BOUND) ? -3 : (st & ST_RANGE) ? -4
+                       : (st & ST_FORMAT) ? -6 : (st & ST_INTERNAL) ? -9
+                       : (st & ST_CAPACITY) ? -5 : 0;
+  if (d_size) *d_size = (code == 0 || code == -5) ? prm->stream_size : 0ull;
+  if (d_status) *d_status = code;
+}
+}  // namespace
+
+hipError_t launch_report(const Params* prm, const RepairQueue* q, uint64_t* d_size,
+                         int32_t* d_status, hipStream_t s) {
+  k_report<<<1, 1, 0, s>>>(prm, q, d_size, d_status);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_list(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
+                             uint32_t* stamp, uint32_t* counters, uint32_t* lists,
+                             uint32_t sweep, int grid, hipStream_t s, Ev ev) {
+  const dim3 g(grid), b(kThreads);
+  if (t.tz == 1)
+    launch_ev(k_sweep_list<1, 32, 64>, g, b, s, ev, box, t, mask, sub, stamp, counters, lists,
+              sweep);
+  else
+    launch_ev(k_sweep_list<8, 8, 32>, g, b, s, ev, box, t, mask, sub, stamp, counters, lists,
+              sweep);
+  return hipGetLastError();
+}
+
+int sweep_list_blocks_per_cu(bool two_d) {
+  int b = 0;
+  const hipError_t e =
+      two_d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep_list<1, 32, 64>, kThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep_list<8, 8, 32>, kThreads, 0);
+  return e == hipSuccess && b > 0 ? b : 1;
+}
+
+hipError_t launch_seed_queue(const uint32_t* counters, const uint32_t* lists, uint32_t ntiles,
+                             uint32_t sweep, const QueueRef& Q, hipStream_t s) {
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(256, (ntiles + kThreads - 1) / kThreads));
+  k_seed_queue<<<grid, kThreads, 0, s>>>(counters, lists, ntiles, sweep, Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_repair_q(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
+                           uint32_t* counters, const QueueRef& Q, int grid, hipStream_t s,
+                           Ev ev) {
+  const dim3 g(grid), b(kThreads);
+  if (t.tz == 1)
+    launch_ev(k_repair_q<1, 32, 64>, g, b, s, ev, box, t, mask, sub,
+                          counters, Q);
+  else
+    launch_ev(k_repair_q<8, 8, 32>, g, b, s, ev, box, t, mask, sub,
+                          counters, Q);
+  return hipGetLastError();
+}
+
+// resident workgroups per CU of the single-field repair kernel (2D or 3D tiles)
+int repair_q_blocks_per_cu(bool two_d) {
+  int b = 0;
+  const hipError_t e =
+      two_d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_q<1, 32, 64>, kThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_q<8, 8, 32>, kThreads, 0);
+  return e == hipSuccess && b > 0 ? b : 1;
 }
 
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
@@ -887,10 +1314,10 @@ hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
                          hipStream_t s, Ev ev) {
   const dim3 g(t.ntiles), b(kThreads);
   if (t.tz == 1)
-    hipExtLaunchKernelGGL(k_repair<1, 32, 64>, g, b, 0, s, ev.a, ev.b, 0, box, t, mask, sub,
+    launch_ev(k_repair<1, 32, 64>, g, b, s, ev, box, t, mask, sub,
                           stamp, counters, sweep);
   else
-    hipExtLaunchKernelGGL(k_repair<8, 8, 32>, g, b, 0, s, ev.a, ev.b, 0, box, t, mask, sub,
+    launch_ev(k_repair<8, 8, 32>, g, b, s, ev, box, t, mask, sub,
                           stamp, counters, sweep);
   return hipGetLastError();
 }
@@ -903,7 +1330,7 @@ hipError_t launch_zero_p(const BatchDesc* bd, int grid, hipStream_t s) {
 hipError_t launch_zero_n(uint32_t* words, uint64_t nwords, hipStream_t s, Ev ev) {
   if (!nwords) return hipSuccess;
   const uint32_t grid = (uint32_t)std::min<uint64_t>(1024, (nwords + kThreads - 1) / kThreads);
-  hipExtLaunchKernelGGL(k_zero_n, dim3(grid), dim3(kThreads), 0, s, ev.a, ev.b, 0, words, nwords);
+  launch_ev(k_zero_n, dim3(grid), dim3(kThreads), s, ev, words, nwords);
   return hipGetLastError();
 }
 

@@ -34,7 +34,8 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option",
            "lopc_ctx_last_batch_headers", "lopc_batch_autotune", "lopc_verify",
            "lopc_verify_workspace_size")
-LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT = 1, 2, 3
+LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT, LOPC_OPT_REPAIR = 1, 2, 3, 4
+LOPC_REPAIR_AUTO, LOPC_REPAIR_HYBRID, LOPC_REPAIR_QUEUE, LOPC_REPAIR_SWEEPS = 0, 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
 
@@ -50,7 +51,8 @@ class LopcError(RuntimeError):
 class Stats(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("repair_sweeps", ctypes.c_uint64),
                 ("active_tiles_total", ctypes.c_uint64), ("bins_bytes", ctypes.c_uint64),
-                ("subbins_bytes", ctypes.c_uint64), ("relax_iterations", ctypes.c_uint64)]
+                ("subbins_bytes", ctypes.c_uint64), ("relax_iterations", ctypes.c_uint64),
+                ("queue_runs", ctypes.c_uint64), ("queue_parks", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -112,7 +114,7 @@ def load() -> ctypes.CDLL:
     L.lopc_compress_bound.restype = ci
     L.lopc_workspace_size.argtypes = [vp, ci, ci, i64p, ci, szp]
     L.lopc_workspace_size.restype = ci
-    L.lopc_compress.argtypes = [vp, vp, ci, ci, i64p, cd, ci, vp, sz, szp, vp, sz, vp,
+    L.lopc_compress.argtypes = [vp, vp, ci, ci, i64p, cd, ci, vp, sz, szp, vp, vp, vp, sz, vp,
                                 ctypes.POINTER(Stats)]
     L.lopc_compress.restype = ci
     L.lopc_stream_info.argtypes = [vp, sz, ctypes.POINTER(ci), ctypes.POINTER(ci), i64p,
@@ -244,15 +246,18 @@ def lopc_stream_info(header: bytes) -> dict:
 
 
 def lopc_compress(ctx, d_field, dtype_code, shape, error_bound, mode, d_stream, cap,
-                  d_ws, ws_bytes, stream, want_stats: bool = True):
-    """Raw call: returns (status, stream size, Stats or None)."""
+                  d_ws, ws_bytes, stream, want_stats: bool = True, d_size=None, d_status=None,
+                  enqueue_only: bool = False):
+    """Raw call: returns (status, stream size, Stats or None).  enqueue_only:
+    h_stream_size NULL (d_size required); the size is then None."""
     size = ctypes.c_size_t()
-    stats = Stats() if want_stats else None
+    stats = Stats() if want_stats and not enqueue_only else None
     st = load().lopc_compress(ctx, d_field, dtype_code, len(shape), _dims(shape),
-                              float(error_bound), mode, d_stream, cap, ctypes.byref(size),
+                              float(error_bound), mode, d_stream, cap,
+                              None if enqueue_only else ctypes.byref(size), d_size, d_status,
                               d_ws, ws_bytes, stream,
-                              ctypes.byref(stats) if want_stats else None)
-    return st, size.value, stats
+                              ctypes.byref(stats) if stats is not None else None)
+    return st, (None if enqueue_only else size.value), stats
 
 
 def lopc_decompress(ctx, d_stream, size, d_field, cap, d_ws, ws_bytes, stream) -> int:
@@ -424,6 +429,39 @@ def compress(x: torch.Tensor, error_bound: float, mode="noa", stats: bool = Fals
     if header:
         res.append(lopc_ctx_last_header(ctx))
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def compress_enqueue(x: torch.Tensor, error_bound: float, mode="noa",
+                     out: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                     size: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                     ctx: int | None = None):
+    """Enqueue a compression on the current stream without waiting for it
+    (lopc_compress with h_stream_size NULL).  Returns (out, size, status):
+    the stream buffer (capacity: the compress bound), a one-element int64
+    device tensor that receives the stream size and a one-element int32
+    device tensor that receives the status.  The call touches no host memory
+    after it returns, so it can be captured into a CUDA/HIP graph (pass
+    preallocated ``out``, ``workspace``, ``size`` and ``status`` then)."""
+    code = _check_field(x)
+    dev = x.device
+    ctx = context(dev.index) if ctx is None else ctx
+    cap, wsz, _ = _sizes_for(ctx, x.shape, x.dtype)
+    if out is None or out.numel() < cap:
+        out = torch.empty(cap, dtype=torch.uint8, device=dev)
+    if workspace is None or workspace.numel() < wsz:
+        workspace = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    if size is None:
+        size = torch.empty(1, dtype=torch.int64, device=dev)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+    s = _stream_handle(dev)
+    st, _, _ = lopc_compress(ctx, x.data_ptr(), code, tuple(x.shape), error_bound, _mode(mode),
+                             out.data_ptr(), out.numel(), workspace.data_ptr(),
+                             workspace.numel(), s, False, size.data_ptr(), status.data_ptr(),
+                             enqueue_only=True)
+    if st:
+        raise LopcError(st, "lopc_compress", ctx)
+    return out, size, status
 
 
 def decompress(stream: torch.Tensor, out: torch.Tensor | None = None,
