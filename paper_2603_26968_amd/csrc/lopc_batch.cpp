@@ -22,7 +22,6 @@ using namespace lopc_host;
 namespace {
 
 constexpr int kMaxGraphs = 8;
-constexpr uint32_t kMaxBatchSweeps = 1u << 16;
 constexpr int kMaxGraphSweeps = (int)kRing - 2;
 
 // group: dtype and tile shape (a 3D field one point thick uses plane tiles,
@@ -178,6 +177,10 @@ int make_plan(int op, int n, const lopc_job* in, uintptr_t ws, Plan& P, int* bad
     }
   }
   P.total = o;
+  // a field whose repair falls back to its own compression runs it inside
+  // this workspace
+  if (op == 0)
+    for (int i = 0; i < n; ++i) P.total = std::max(P.total, compress_layout(shp[i], in[i].dtype).total);
   D.tiles = (uint32_t)P.tiles;
   D.zero_words = (P.zero_end - P.zero_off) / 4;
   D.zero_base = (uint32_t*)(ws + P.zero_off);
@@ -437,6 +440,7 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
     active += m;
   }
   bool continued = false;
+  std::vector<char> redo(P.jobs.size(), 0);  // plan positions to compress on their own
   if (hc->lens[(K + 1) % kRing]) {
     // the captured sweeps did not reach the fixed point: keep sweeping with
     // direct launches (reading the ring once per group of sweeps), then
@@ -477,7 +481,28 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
       if (done) break;
       next += batch;
       batch = std::min<uint32_t>(batch * 2, 16);
-      if (next + batch >= kMaxBatchSweeps) return LOPC_E_INTERNAL;
+      if (next + batch > kAutoSweeps) {
+        // a dependency chain across many tiles (every sweep reruns nearly
+        // every tile of its field): the fields that still have tiles listed
+        // for sweep `next` are compressed again on their own below, where
+        // the repair restarts on the device queue
+        std::vector<uint32_t> items(hc->lens[next % kRing]);
+        if (!items.empty()) {
+          HIP_CTX(ctx, hipMemcpyAsync(items.data(), P.desc.lists + (next & 1) * P.desc.tiles,
+                                      items.size() * 4, hipMemcpyDeviceToHost, hs));
+          HIP_CTX(ctx, hipStreamSynchronize(hs));
+        }
+        for (uint32_t it : items) {
+          int lo = 0, hi = (int)P.jobs.size() - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (P.jobs[mid].t0 <= it) lo = mid;
+            else hi = mid - 1;
+          }
+          redo[lo] = 1;
+        }
+        break;
+      }
     }
     // encoder state is still clear (the gated encoders did not run)
     for (int d = 0; d < 2; ++d) {
@@ -494,6 +519,30 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
       while (h < (int)sweeps + 1 && h < kMaxGraphSweeps) h *= 2;
       ctx->sweeps_hint = std::min(h, kMaxGraphSweeps);
     }
+  }
+  // fields left to compress on their own: the batch workspace (no longer
+  // needed, and at least as large as any field's own workspace) serves the
+  // single-field call, which writes the field's stream, size and status
+  // words; its results replace the batch's
+  BatchResult* hr = (BatchResult*)host_results(ctx);
+  for (size_t q = 0; q < redo.size(); ++q) {
+    if (!redo[q]) continue;
+    const lopc_job& j = jobs[P.order[q]];
+    const int saved = ctx->repair_mode;
+    ctx->repair_mode = LOPC_REPAIR_AUTO;
+    size_t size = 0;
+    lopc_stats st1;
+    const int rc = lopc_compress(ctx, j.d_in, j.dtype, j.ndim, j.dims, j.error_bound, j.mode,
+                                 j.d_out, j.out_cap, &size, j.d_out_size, j.d_status, d_ws,
+                                 ws_bytes, stream, &st1);
+    ctx->repair_mode = saved;
+    if (rc == LOPC_E_HIP || rc == LOPC_E_ARG) return rc;
+    hr[q].size = size;
+    hr[q].status = rc;
+    std::memset(hr[q].header, 0, kHeaderBytes);
+    if (rc == LOPC_OK) std::memcpy(hr[q].header, ctx->last_header, kHeaderBytes);
+    sweeps = std::max<uint64_t>(sweeps, st1.repair_sweeps);
+    active += st1.active_tiles_total;
   }
   if (h_stats) {
     h_stats->repair_sweeps = sweeps;

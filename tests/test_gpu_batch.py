@@ -310,3 +310,23 @@ def test_uneven_batch_matches_single(P, ref):
         z = P.decompress(t)
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy().view(np.uint8), z.cpu().numpy().view(np.uint8)), i
+
+
+def test_batch_with_a_chain_across_many_tiles(P, ref):
+    """A field whose same-bin chain falls with the index across 4096 tiles
+    (Sec. IV-E worst case) next to ordinary fields: past 64 sweeps the batch
+    compresses that field on its own (the repair restarts on the device
+    queue); every stream still equals the oracle's, and the chain's subbins
+    are n-1, ..., 0."""
+    _say("batch with a long falling chain")
+    n = 1 << 18
+    chain = (np.arange(n, 0, -1, dtype=np.float64) / n).astype(np.float32).reshape(1, n)
+    batch = [(synth.gaussian_bumps((40, 52), seed=3), 1e-3, "noa"),
+             (chain, 10.0, "abs"),
+             (synth.turbulence_field((24, 20, 28), seed=2, dtype=np.float64), 1e-2, "noa")]
+    want = [ref.compress(x, eb, ref.NOA if m == "noa" else ref.ABS) for x, eb, m in batch]
+    got, st = batch_streams(P, batch, stats=True)
+    assert_same_streams(got, want, "batch with chain")
+    assert st["status"] == [0] * len(batch)
+    _, sub = ref.decode_codes(got[1])
+    assert np.array_equal(sub.ravel().astype(np.int64), np.arange(n - 1, -1, -1))
