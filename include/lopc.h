@@ -149,6 +149,22 @@ int lopc_decompress_h(lopc_ctx* ctx, const void* h_header, const void* d_stream,
                       size_t stream_size, void* d_field, size_t field_cap,
                       void* d_ws, size_t ws_bytes, void* stream);
 
+/* lopc_decompress_h for callers that cannot allocate (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): no
+ * workspace argument and no allocation of any kind.  Its scratch (the
+ * decoder's parameter block and one 8-byte record offset per chunk) is a
+ * 4 MiB array held by the library on each GPU until the process ends, so
+ * streams of at most 524,256 chunks are accepted (a float32 field of up to
+ * about 2.1e9 points, float64 1.07e9); a larger stream returns
+ * LOPC_E_CAPACITY before any device work.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other host threads, or
+ * other streams) race and must be serialised by the caller.  The array
+ * keeps the last call's contents; each call clears what must start at zero.
+ * Otherwise as lopc_decompress_h (the same kernels, stream order, checks
+ * and status codes). */
+int lopc_decompress_static(lopc_ctx* ctx, const void* h_header, const void* d_stream,
+                           size_t stream_size, void* d_field, size_t field_cap, void* stream);
+
 /* Copy the 64-byte header of the most recent successful lopc_compress on this
  * context into h_header.  LOPC_E_ARG if there is none. */
 int lopc_ctx_last_header(lopc_ctx* ctx, void* h_header);

@@ -8,8 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblopc.so")
-SOURCES = ["lopc_kernels.hip", "lopc_codec.hip", "lopc_verify.hip", "lopc_api.cpp",
-           "lopc_batch.cpp"]
+SOURCES = ["lopc_kernels.hip", "lopc_codec.hip", "lopc_verify.hip", "lopc_static.hip",
+           "lopc_api.cpp", "lopc_batch.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -50,6 +50,13 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   }
   c->h_prm = (Params*)p;
   c->h_cnt = (uint32_t*)((uint8_t*)p + 4096);
+  // the device address of this device's copy of the library-held scratch
+  // (lopc_decompress_static), looked up with the device current
+  if (static_scratch_address(&c->scratch) != hipSuccess || !c->scratch) {
+    (void)hipHostFree(p);
+    delete c;
+    return LOPC_E_HIP;
+  }
   c->timing = 0;
   c->have_header = 0;
   c->hip_error = 0;
@@ -492,6 +499,24 @@ int lopc_decompress(lopc_ctx* ctx, const void* d_stream, size_t stream_size,
   uint8_t hdr[kHeaderBytes];
   std::memcpy(hdr, hh, kHeaderBytes);
   return decompress_core(ctx, hdr, d_stream, stream_size, d_field, field_cap, d_ws, ws_bytes, hs);
+}
+
+int lopc_decompress_static(lopc_ctx* ctx, const void* h_header, const void* d_stream,
+                           size_t stream_size, void* d_field, size_t field_cap, void* stream) {
+  if (!ctx || !h_header || !d_stream || !d_field) return LOPC_E_ARG;
+  if (stream_size < kHeaderBytes) return LOPC_E_FORMAT;
+  int dtype, ndim;
+  int64_t dims[3];
+  if (int st = lopc_stream_info(h_header, kHeaderBytes, &dtype, &ndim, dims, nullptr, nullptr))
+    return st;
+  Shape s;
+  if (make_shape(ndim, dims, &s) != LOPC_OK) return LOPC_E_ARG;
+  // the scratch holds Params and one offset per chunk: larger streams are
+  // refused before any device work
+  if (decompress_ws(s, dtype) > kStaticScratchBytes) return LOPC_E_CAPACITY;
+  HIP_CTX(ctx, hipSetDevice(ctx->device));
+  return decompress_core(ctx, (const uint8_t*)h_header, d_stream, stream_size, d_field,
+                         field_cap, ctx->scratch, kStaticScratchBytes, (hipStream_t)stream);
 }
 
 int lopc_decompress_h(lopc_ctx* ctx, const void* h_header, const void* d_stream,

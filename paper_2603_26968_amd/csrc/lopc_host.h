@@ -50,6 +50,7 @@ struct lopc_ctx {
   int repair_mode;     // single field: LOPC_REPAIR_HYBRID, _QUEUE or _SWEEPS
   int rq_per_cu[2];    // resident repair-queue workgroups per CU (3D, 2D tiles)
   int sl_per_cu[2];    // resident list-sweep workgroups per CU (3D, 2D tiles)
+  void* scratch;       // device address of the library-held scratch on this device
   // batches
   int use_graph;       // capture batch sequences as graphs
   int graph_sweeps;    // sweeps per graph (0 = adaptive)

@@ -324,6 +324,13 @@ hipError_t launch_encode_d(int dtype, const BatchDesc* bd, const Job* jobs, int 
 hipError_t launch_decode_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,
                            hipStream_t s);
 
+// Library-held scratch of lopc_decompress_static (lopc_static.hip): Params
+// and the record offsets of up to kStaticMaxChunks chunks.  Its address on
+// the current device (the host-side name of the array is not a device
+// address and must never be passed to a kernel).
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+hipError_t static_scratch_address(void** ptr);
+
 // Invariant checker (lopc_verify.hip): adds 14 report words to out.
 hipError_t launch_verify(int dtype, const void* x, const void* y, Box box, double eps,
                          unsigned long long* out, int blocks, hipStream_t s);

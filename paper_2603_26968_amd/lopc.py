@@ -33,7 +33,7 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_ctx_last_header", "lopc_batch_workspace_size", "lopc_compress_batch",
            "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option",
            "lopc_ctx_last_batch_headers", "lopc_batch_autotune", "lopc_verify",
-           "lopc_verify_workspace_size")
+           "lopc_verify_workspace_size", "lopc_decompress_static")
 LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT, LOPC_OPT_REPAIR = 1, 2, 3, 4
 LOPC_REPAIR_AUTO, LOPC_REPAIR_HYBRID, LOPC_REPAIR_QUEUE, LOPC_REPAIR_SWEEPS = 0, 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
@@ -129,6 +129,8 @@ def load() -> ctypes.CDLL:
     L.lopc_ctx_last_timings.argtypes = [vp, ctypes.POINTER(cd), ci]
     L.lopc_ctx_last_timings.restype = ci
     L.lopc_decompress_h.argtypes = [vp, vp, vp, sz, vp, sz, vp, sz, vp]
+    L.lopc_decompress_static.argtypes = [vp, vp, vp, sz, vp, sz, vp]
+    L.lopc_decompress_static.restype = ci
     L.lopc_decompress_h.restype = ci
     L.lopc_ctx_last_header.argtypes = [vp, vp]
     L.lopc_ctx_last_header.restype = ci
@@ -270,6 +272,11 @@ def lopc_decompress_h(ctx, header: bytes, d_stream, size, d_field, cap, d_ws, ws
         ctypes.create_string_buffer(bytes(header)[:HEADER_BYTES], HEADER_BYTES)
     return load().lopc_decompress_h(ctx, h, d_stream, size, d_field, cap, d_ws, ws_bytes,
                                     stream)
+
+
+def lopc_decompress_static(ctx, header: bytes, d_stream, size, d_field, cap, stream) -> int:
+    """Raw call of the allocation-free decompression (library-held scratch)."""
+    return load().lopc_decompress_static(ctx, header, d_stream, size, d_field, cap, stream)
 
 
 def lopc_ctx_last_header(ctx) -> bytes:
