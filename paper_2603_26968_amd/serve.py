@@ -6,9 +6,21 @@ when its HBM footprint fits the budget beside the requests in flight (first
 come, first served: a large request at the head is not overtaken), then runs
 on a free slot.  A slot is a worker thread with its own library context, its
 own HIP stream (default priority) and its own workspace, grown on demand and
-kept; the library calls release the interpreter lock while they wait, so
-requests on different slots overlap on the GPU.  A request's latency runs
-from its arrival to the moment its result is ready.
+kept between requests up to a per-slot limit; the library calls release the
+interpreter lock while they wait, so requests on different slots overlap on
+the GPU.  A request's latency runs from its arrival to the moment its result
+is ready.
+
+Memory: the workspaces the slots keep are a standing reservation taken out
+of the budget up front (slots x keep limit), so the bytes of the requests in
+flight plus the kept workspaces never exceed the budget.
+
+Stream order: submit() records an event on the caller's current stream; the
+slot's stream waits for it before the request runs, so a field or stream
+written by a kernel the caller has not synchronised is read only after that
+kernel.  The result is marked as used by the caller's stream, so the
+allocator does not hand its memory to the slot's stream while the caller's
+work on it may still be pending.
 
 Nothing here computes: every byte of every result comes from the library's
 kernels (``lopc.compress`` / ``lopc.decompress`` with the slot's context).
@@ -37,6 +49,8 @@ class Request:
     keep: bool = True            # False: drop the result once done (timing runs)
     arrival: float = 0.0         # time.perf_counter() at arrival
     # filled in by the server
+    ready: Any = None            # event on the caller's stream at submit (device data)
+    caller_stream: Any = None    # the caller's stream at submit (device data)
     footprint: int = 0
     start: float = 0.0
     end: float = 0.0
@@ -104,16 +118,31 @@ class Server:
     the CPU pass their own."""
 
     def __init__(self, budget: int, slots: int = 4, execute: Callable | None = None,
-                 footprint: Callable | None = None, device: int = 0):
+                 footprint: Callable | None = None, device: int = 0,
+                 keep_limit: int | None = None, kept: Callable | None = None):
         if slots < 1:
             raise ValueError("at least one slot")
+        # workspaces kept between requests: at most keep_limit bytes per
+        # slot (default: a quarter of the budget over all slots for the GPU
+        # executor; none for a caller's executor unless given), reserved from
+        # the budget up front
+        gpu = execute is None or footprint is None
+        if keep_limit is None:
+            keep_limit = budget // (4 * slots) if gpu else 0
+        self.keep_limit = int(keep_limit)
+        if slots * self.keep_limit >= budget:
+            raise ValueError("the kept workspaces would take the whole budget")
         self._gpu = None
-        if execute is None or footprint is None:
-            self._gpu = GpuSlots(slots, device)
+        if gpu:
+            self._gpu = GpuSlots(slots, device, self.keep_limit)
             execute = execute or self._gpu.execute
             footprint = footprint or self._gpu.footprint
+            kept = kept or self._gpu.kept_bytes
         self.execute, self.footprint = execute, footprint
-        self.admission = Admission(budget)
+        self.kept = kept or (lambda: 0)
+        self.budget = int(budget)
+        self.admission = Admission(budget - slots * self.keep_limit)
+        self.peak_total = 0  # largest in-flight + kept bytes seen at a release
         self._pending = queue.Queue()
         self._free = queue.Queue()
         for s in range(slots):
@@ -131,6 +160,8 @@ class Server:
             raise RuntimeError("server closed")
         if not req.arrival:
             req.arrival = time.perf_counter()
+        if self._gpu is not None:
+            self._gpu.mark_ready(req)
         self._pending.put(req)
         return req
 
@@ -168,6 +199,8 @@ class Server:
                 res, err = None, e
             if not req.keep:
                 res = None
+            with self.admission._cv:
+                self.peak_total = max(self.peak_total, self.admission.in_use + self.kept())
             self.admission.release(req.footprint)
             self._free.put(slot)
             self._finish(req, res, err)
@@ -191,9 +224,10 @@ class Server:
 
 class GpuSlots:
     """The GPU executor: per slot a library context, a HIP stream and a
-    workspace tensor kept between requests."""
+    workspace tensor kept between requests while it is at most keep_limit
+    bytes."""
 
-    def __init__(self, slots: int, device: int = 0):
+    def __init__(self, slots: int, device: int = 0, keep_limit: int = 0):
         import torch
 
         from . import lopc
@@ -202,6 +236,19 @@ class GpuSlots:
         self.ctx = [lopc.lopc_ctx_create(device) for _ in range(slots)]
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(slots)]
         self.ws = [None] * slots
+        self.keep_limit = keep_limit
+
+    def kept_bytes(self) -> int:
+        return sum(w.numel() for w in self.ws if w is not None)
+
+    def mark_ready(self, req):
+        """On the caller's thread at submit: an event after the caller's work
+        so far on its current stream (which produced the request's data)."""
+        torch = self.torch
+        if isinstance(req.data, torch.Tensor) and req.data.is_cuda:
+            req.caller_stream = torch.cuda.current_stream(req.data.device)
+            req.ready = torch.cuda.Event()
+            req.ready.record(req.caller_stream)
 
     def _info(self, req):
         if req.header is None:
@@ -229,19 +276,32 @@ class GpuSlots:
     def execute(self, slot, req):
         torch, L = self.torch, self.lopc
         ctx = self.ctx[slot]
-        with torch.cuda.stream(self.streams[slot]):
-            if req.op == "compress":
-                x = req.data
-                _, wsz, _ = L._sizes_for(ctx, x.shape, x.dtype)
-                s = L.compress(x, req.eb, req.mode, ctx=ctx,
-                               workspace=self._workspace(slot, wsz))
-                return s
-            if req.op == "decompress":
-                info = self._info(req)
-                _, _, wsz = L._sizes_for(ctx, info["shape"], info["dtype"])
-                return L.decompress(req.data, header=req.header, ctx=ctx,
-                                    workspace=self._workspace(slot, wsz))
-        raise ValueError(f"unknown op {req.op!r}")
+        st = self.streams[slot]
+        try:
+            with torch.cuda.stream(st):
+                if req.ready is not None:
+                    st.wait_event(req.ready)
+                    req.data.record_stream(st)
+                if req.op == "compress":
+                    x = req.data
+                    _, wsz, _ = L._sizes_for(ctx, x.shape, x.dtype)
+                    out = L.compress(x, req.eb, req.mode, ctx=ctx,
+                                     workspace=self._workspace(slot, wsz))
+                elif req.op == "decompress":
+                    info = self._info(req)
+                    _, _, wsz = L._sizes_for(ctx, info["shape"], info["dtype"])
+                    out = L.decompress(req.data, header=req.header, ctx=ctx,
+                                       workspace=self._workspace(slot, wsz))
+                else:
+                    raise ValueError(f"unknown op {req.op!r}")
+            if req.caller_stream is not None:
+                out.record_stream(req.caller_stream)
+            return out
+        finally:
+            # a workspace above the keep limit is not kept
+            w = self.ws[slot]
+            if w is not None and w.numel() > self.keep_limit:
+                self.ws[slot] = None
 
     def close(self):
         for c in self.ctx:

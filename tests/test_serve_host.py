@@ -103,3 +103,30 @@ def test_poisson_driver_and_stats():
     assert st["requests"] == 50 and st["failed"] == 0
     assert 1.0 <= st["p50_ms"] <= st["p99_ms"]
     assert st["GBps"] > 0
+
+
+def test_kept_workspaces_stay_inside_the_budget():
+    """Slots that keep workspaces between requests: the keep limit per slot
+    is reserved from the budget up front, so the bytes in flight plus the
+    kept bytes never exceed the budget (a stand-in executor keeps a
+    'workspace' of the request's size when it is within the limit)."""
+    budget, slots, limit = 1000, 3, 100
+    kept = [0] * slots
+
+    def execute(slot, req):
+        time.sleep(0.001 * (req.tag % 3))
+        kept[slot] = req.data if req.data <= limit else 0
+        return req.data
+
+    with serve.Server(budget, slots=slots, execute=execute, footprint=lambda r: 2 * r.data,
+                      keep_limit=limit, kept=lambda: sum(kept)) as srv:
+        assert srv.admission.budget == budget - slots * limit
+        rng = np.random.default_rng(3)
+        reqs = [srv.submit(serve.Request("compress", int(rng.integers(1, 350)), tag=i))
+                for i in range(300)]
+        for r in reqs:
+            r.wait(10)
+    assert srv.peak_total <= budget
+    assert srv.admission.in_use == 0
+    with pytest.raises(ValueError):
+        serve.Server(100, slots=2, execute=execute, footprint=lambda r: 1, keep_limit=50)
