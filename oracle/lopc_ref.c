@@ -345,7 +345,8 @@ int lopc_ref_reconstruct(int64_t b, uint64_t s, double inv, int dtype,
   int st = bin_floor_key(b, inv, dtype, &k);
   if (st) return st;
   int64_t kmax = max_finite_key(dtype);
-  if (s > (uint64_t)(kmax - k)) return LOPC_REF_E_FORMAT;
+  /* kmax - k can exceed the int64 range (k near -kmax): take it unsigned */
+  if (s > (uint64_t)kmax - (uint64_t)k) return LOPC_REF_E_FORMAT;
   int64_t kk = k + (int64_t)s;
   double v = value_of_key(kk, dtype);
   /* a valid stream never leaves the bin */

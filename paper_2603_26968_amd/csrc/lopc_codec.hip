@@ -1261,7 +1261,8 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
       have = bin_floor_key<K>(b, inv, winv, klo);
     }
     typename Tr::Raw v = 0;
-    if (!have || s > (uint64_t)(Tr::kMaxKey - klo)) {
+    // the room above klo can exceed the int64 range: unsigned difference
+    if (!have || s > (uint64_t)Tr::kMaxKey - (uint64_t)klo) {
       bad = true;
     } else {
       v = Tr::unkey(klo + (int64_t)s);
