@@ -29,6 +29,8 @@ Other workloads (--workload), one JSON line each:
                single-slot service rate, served on 4 slots under a 64 GiB
                HBM budget: p50 / p99 latency and GB/s per rate
   copy         device-to-device copy of 256 MiB (the achievable HBM rate)
+  repair-study the single-field repair schedulers side by side on the fields
+               above and on long falling chains (repair time, sweeps, tile runs)
 
 Prints one JSON line per run.  Usage:
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lognormal3d]
@@ -72,7 +74,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal3d",
-                    choices=list(SINGLE) + ["batch", "serve", "copy"])
+                    choices=list(SINGLE) + ["batch", "serve", "copy", "repair-study"])
     ap.add_argument("--eb", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -192,6 +194,29 @@ def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing):
     return tc, td, {k: v / max(steps, 1) for k, v in phase.items()}, stats, s
 
 
+def _sweep_parity(P, xh, eb, gpu_stream):
+    """Stream identity with the oracle at one bound of the error-bound sweep:
+    the whole field when it is at most 16M points (gpu_stream: its stream),
+    else the leading slab of about 16M points, compressed by both."""
+    import oracle
+    import torch
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liblopc_ref.so")):
+        oracle.build()
+    if gpu_stream is not None:
+        sl, got = xh, gpu_stream.cpu().numpy().tobytes()
+    else:
+        rows = max(1, (1 << 24) // (xh.size // xh.shape[0]))
+        sl = np.ascontiguousarray(xh[:rows])
+        got = P.compress(torch.from_numpy(sl).cuda(), eb, "noa").cpu().numpy().tobytes()
+    try:
+        want = oracle.compress(sl, eb, oracle.NOA)
+    except oracle.OracleError as e:
+        return {"scope": "whole field" if sl is xh else f"leading slab {list(sl.shape)}",
+                "oracle_error": e.code}
+    return {"scope": "whole field" if sl is xh else f"leading slab {list(sl.shape)}",
+            "stream_identical": got == want}
+
+
 def bench_single(args, name):
     import hashlib
     import tempfile
@@ -294,12 +319,16 @@ def bench_single(args, name):
         extra_sweep = {}
         for e in range(0, 7):
             eb = 10.0 ** (-e)
+            _log("eb sweep", eb)
             try:
                 tce, tde, ph, st, se = run_steps(P, lopc, ctx, x, eb, 3, bufs, True)
             except lopc.LopcError as err:  # e.g. a bin range beyond the integer type
                 extra_sweep[f"1e-{e}"] = {"error": str(err)}
                 continue
             Se = int(se.numel())
+            par = None
+            if not args.no_cpu_baseline:
+                par = _sweep_parity(P, xh, eb, se if sample is xh else None)
             extra_sweep[f"1e-{e}"] = {
                 "CR": round(n * k / Se, 3),
                 "GBps_roundtrip": round(n * k / _pct([a + b for a, b in zip(tce, tde)], 50) / 1e9, 2),
@@ -309,7 +338,8 @@ def bench_single(args, name):
                 "active_tiles_total": int(st["active_tiles_total"]),
                 "relax_iterations": int(st["relax_iterations"]),
                 "bins_share": round(st["bins_bytes"] / Se, 4),
-                "subbins_share": round(st["subbins_bytes"] / Se, 4)}
+                "subbins_share": round(st["subbins_bytes"] / Se, 4),
+                "parity": par}
 
     dtname = "f32" if k == 4 else "f64"
     out = {
@@ -367,6 +397,81 @@ def bench_single(args, name):
     import shutil
     shutil.rmtree(tmp, ignore_errors=True)
     return out
+
+
+# ------------------------------------------------------------------ repair study
+def bench_repair_study(args):
+    """The single-field repair schedulers side by side (LOPC_OPT_REPAIR):
+    for each field and scheduler, the median repair-phase time (library
+    dispatch events), the compress time, sweeps, tile runs, queue runs and
+    parks; the streams of all schedulers of a field must be identical."""
+    import torch
+
+    import paper_2603_26968_amd as P
+    from paper_2603_26968_amd import lopc, synth
+    modes = {"sweeps": lopc.LOPC_REPAIR_SWEEPS, "hybrid": lopc.LOPC_REPAIR_HYBRID,
+             "queue": lopc.LOPC_REPAIR_QUEUE, "auto": lopc.LOPC_REPAIR_AUTO}
+
+    def chain(n):
+        return (np.arange(n, 0, -1, dtype=np.float64) / n).astype(np.float32).reshape(1, n)
+
+    cases = [
+        ("turb3d 256^3 f32 NOA 1e-3", lambda: synth.turbulence_field(), 1e-3, "noa", 5,
+         ("sweeps", "hybrid", "queue", "auto")),
+        ("turb3d 256^3 f32 NOA 1e-2", lambda: synth.turbulence_field(), 1e-2, "noa", 5,
+         ("sweeps", "hybrid", "queue", "auto")),
+        ("turb3d 256^3 f32 NOA 1e0", lambda: synth.turbulence_field(), 1.0, "noa", 3,
+         ("sweeps", "hybrid", "queue", "auto")),
+        ("fronts2d 1800x3600 f32 NOA 1e-3", lambda: synth.fronts_field(), 1e-3, "noa", 5,
+         ("sweeps", "hybrid", "queue", "auto")),
+        ("smooth2d 512^2 f32 NOA 1e-3", lambda: synth.smooth_field(), 1e-3, "noa", 5,
+         ("sweeps", "hybrid", "queue", "auto")),
+        ("lognormal3d 512^3 f64 NOA 1e-3", lambda: synth.lognormal_field(), 1e-3, "noa", 3,
+         ("sweeps", "hybrid", "queue", "auto")),
+        ("falling chain (1, 2^16) f32 ABS 10", lambda: chain(1 << 16), 10.0, "abs", 2,
+         ("sweeps", "queue", "auto")),
+        ("falling chain (1, 2^20) f32 ABS 10", lambda: chain(1 << 20), 10.0, "abs", 1,
+         ("queue", "auto")),
+    ]
+    rows = []
+    for name, gen, eb, mode, reps, which in cases:
+        _log("repair study:", name)
+        t = torch.from_numpy(gen()).cuda()
+        streams = {}
+        for mn in which:
+            ctx = lopc.lopc_ctx_create(0)
+            try:
+                lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_REPAIR, modes[mn])
+                lopc.lopc_ctx_set_timing(ctx, ("repair",))
+                P.compress(t, eb, mode, ctx=ctx)  # learns its sweep count
+                rep_ms, tot_ms = [], []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    s, st = P.compress(t, eb, mode, stats=True, ctx=ctx)
+                    tot_ms.append((time.perf_counter() - t0) * 1e3)
+                    rep_ms.append(lopc.lopc_ctx_last_timings(ctx)["repair"])
+                streams[mn] = s.cpu().numpy().tobytes()
+                rows.append({"field": name, "scheduler": mn,
+                             "repair_ms": round(_pct(rep_ms, 50), 4),
+                             "compress_ms": round(_pct(tot_ms, 50), 4),
+                             "sweeps": int(st["repair_sweeps"]),
+                             "tile_runs": int(st["active_tiles_total"]),
+                             "queue_runs": int(st["queue_runs"]),
+                             "queue_parks": int(st["queue_parks"])})
+                _log(json.dumps(rows[-1]))
+            finally:
+                lopc.lopc_ctx_destroy(ctx)
+        same = len(set(streams.values())) == 1
+        for r in rows:
+            if r["field"] == name:
+                r["streams_identical_across_schedulers"] = same
+        del t
+    return {"metric": "repair-phase time of each scheduler (ms, lower is better)",
+            "value": None, "unit": "ms", "n_gpus": 1, "steps": None, "warmup": 1,
+            "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": "repair-study: schedulers x fields"}, "rows": rows}
 
 
 # ------------------------------------------------------------------ batch
@@ -594,6 +699,8 @@ def main():
         out = bench_serve(args)
     elif args.workload == "copy":
         out = bench_copy(args)
+    elif args.workload == "repair-study":
+        out = bench_repair_study(args)
     else:
         out = bench_single(args, args.workload)
     print(json.dumps(out), flush=True)

@@ -366,8 +366,14 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
     if (listed) {
       if (my_pt && step((int)(my_pt & 4095u), my_pt >> 12, my_cd)) changed = 1;
     } else {
+      // Gauss-Seidel along the thread's slots (one column of points along
+      // z in a 3D tile, one row in four in a 2D tile), in alternating
+      // directions from pass to pass, so a chain along that axis crosses
+      // the tile in a pass or two whichever way it runs
+      const bool rev = iters & 1;
 #pragma unroll 2
-      for (int k = 0; k < G::PER; ++k) {
+      for (int kk = 0; kk < G::PER; ++kk) {
+        const int k = rev ? G::PER - 1 - kk : kk;
         const uint32_t m = mk[k];
         if (!m) continue;
         const int li = G::local(threadIdx.x + k * kThreads);
