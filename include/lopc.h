@@ -240,11 +240,14 @@ int lopc_ctx_last_batch_headers(lopc_ctx* ctx, int n, void* h_headers);
 
 /* Autotuner of the batch path: runs the batch (op 0 = compress, 1 =
  * decompress) with direct grids and with persistent grids of 50, 100 and
- * 200 % of the resident capacity, once untimed and `reps` times timed (host
- * clock around the synchronous call), keeps the fastest in the context (as
- * LOPC_OPT_PERSIST_PCT, 0 = direct) and returns it in *h_pct (may be NULL).
- * The outputs are those of an ordinary call.  Errors as lopc_compress_batch;
- * a per-field failure does not stop the tuning. */
+ * 200 % of the resident capacity and, for compression, with every repair
+ * tile shape (LOPC_OPT_TILE_2D / _3D) of the kinds of field in the batch,
+ * once untimed and `reps` times timed
+ * (host clock around the synchronous call).  It keeps the fastest in the
+ * context (LOPC_OPT_PERSIST_PCT, 0 = direct, and the tile options; read them
+ * back with lopc_ctx_get_option) and returns the grid percentage in *h_pct
+ * (may be NULL).  The outputs are those of an ordinary call.  Errors as
+ * lopc_compress_batch; a per-field failure does not stop the tuning. */
 int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void* d_ws,
                         size_t ws_bytes, void* stream, int reps, int* h_pct);
 
@@ -274,12 +277,23 @@ int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void
  *                          first pass on;
  *                          LOPC_REPAIR_SWEEPS: global sweeps over the marked
  *                          tiles, launched by the host in groups, until no
- *                          tile is marked (not available to enqueued calls). */
+ *                          tile is marked (not available to enqueued calls).
+ *   LOPC_OPT_TILE_3D       tile of the repair of 3D fields (each workgroup
+ *                          holds one tile and a one-point halo in LDS):
+ *                          0 (default) 4 x 8 x 32, 1: 8 x 8 x 32,
+ *                          2: 8 x 16 x 16 points (z, y, x);
+ *   LOPC_OPT_TILE_2D       tile of 2D fields: 0 (default) 32 x 64,
+ *                          1: 16 x 128.
+ *                          Neither the result nor the workspace size
+ *                          (the largest over the shapes) depends on them. */
 enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT = 3,
-       LOPC_OPT_REPAIR = 4 };
+       LOPC_OPT_REPAIR = 4, LOPC_OPT_TILE_3D = 5, LOPC_OPT_TILE_2D = 6 };
 enum { LOPC_REPAIR_AUTO = 0, LOPC_REPAIR_HYBRID = 1, LOPC_REPAIR_QUEUE = 2,
        LOPC_REPAIR_SWEEPS = 3 };
 int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value);
+/* The current value of a context option into *h_value; LOPC_E_ARG for an
+ * unknown option or a NULL argument. */
+int lopc_ctx_get_option(lopc_ctx* ctx, int option, int64_t* h_value);
 
 /* ------------------------------------------------------------------ checks
  * What LOPC guarantees of a reconstruction d_recon of d_orig (same dtype and

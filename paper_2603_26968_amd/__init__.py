@@ -16,10 +16,10 @@ _BINDING = (
     "LOPC_F64", "Stats", "lopc_ctx_set_timing", "lopc_ctx_last_timings",
     "compress_batch", "decompress_batch", "Job", "BatchStats", "lopc_batch_workspace_size",
     "lopc_compress_batch", "lopc_decompress_batch", "lopc_ctx_last_batch",
-    "lopc_ctx_set_option", "LOPC_OPT_BATCH_GRAPH", "LOPC_OPT_GRAPH_SWEEPS",
+    "lopc_ctx_set_option", "lopc_ctx_get_option", "LOPC_OPT_BATCH_GRAPH", "LOPC_OPT_GRAPH_SWEEPS",
     "LOPC_OPT_PERSIST_PCT", "lopc_ctx_last_batch_headers", "lopc_batch_autotune",
     "autotune_compress_batch", "verify", "VerifyReport", "lopc_verify",
-    "compress_enqueue", "LOPC_OPT_REPAIR", "LOPC_REPAIR_QUEUE", "LOPC_REPAIR_SWEEPS", "LOPC_REPAIR_HYBRID", "LOPC_REPAIR_AUTO",
+    "compress_enqueue", "LOPC_OPT_REPAIR", "LOPC_REPAIR_QUEUE", "LOPC_REPAIR_SWEEPS", "LOPC_REPAIR_HYBRID", "LOPC_REPAIR_AUTO", "LOPC_OPT_TILE_3D", "LOPC_OPT_TILE_2D",
 )
 
 

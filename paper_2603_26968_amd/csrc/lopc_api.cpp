@@ -73,8 +73,9 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->persist_pct = 0;
   c->sweep_hint = 4;
   c->repair_mode = LOPC_REPAIR_AUTO;
-  c->rq_per_cu[0] = c->rq_per_cu[1] = 0;
-  c->sl_per_cu[0] = c->sl_per_cu[1] = 0;
+  for (int i = 0; i < kTileShapes; ++i) c->rq_per_cu[i] = c->sl_per_cu[i] = 0;
+  c->tile2 = 0;
+  c->tile3 = 0;
   *out = c;
   return LOPC_OK;
 }
@@ -136,13 +137,21 @@ int lopc_compress_bound(int dtype, int ndim, const int64_t* dims,
 
 int lopc_workspace_size(lopc_ctx* ctx, int dtype, int ndim,
                         const int64_t* dims, int op, size_t* bytes) {
-  (void)ctx;
   if ((dtype != 0 && dtype != 1) || !bytes || (op != 0 && op != 1))
     return LOPC_E_ARG;
   Shape s;
   int st = make_shape(ndim, dims, &s);
   if (st) return st;
-  *bytes = op == 0 ? compress_layout(s, dtype).total : decompress_ws(s, dtype);
+  (void)ctx;
+  // the largest over every tile shape, so that a workspace stays valid when
+  // the context's tile options change
+  size_t b = 0;
+  if (op == 0)
+    for (int t2 = 0; t2 < kTiles2; ++t2)
+      for (int t3 = 0; t3 < kTiles3; ++t3) b = std::max(b, compress_layout(s, dtype, t2, t3).total);
+  else
+    b = decompress_ws(s, dtype);
+  *bytes = b;
   return LOPC_OK;
 }
 
@@ -258,7 +267,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   if (!std::isfinite(error_bound) || !(error_bound > 0)) return LOPC_E_BOUND;
   if (((uintptr_t)d_field & 15) || ((uintptr_t)d_stream & 3)) return LOPC_E_ARG;
   if (((uintptr_t)d_stream_size & 7) || ((uintptr_t)d_status & 3)) return LOPC_E_ARG;
-  CompressLayout L = compress_layout(s, dtype);
+  CompressLayout L = compress_layout(s, dtype, ctx->tile2, ctx->tile3);
   if (ws_bytes < L.total || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
   hipStream_t hs = (hipStream_t)stream;
   HIP_CTX(ctx, hipSetDevice(ctx->device));
@@ -271,7 +280,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   uint64_t* offs = (uint64_t*)(ws + L.offs);
   const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
   const uint64_t nch = (s.n + W - 1) / W;
-  Tiling tl = make_tiling(s.box);
+  Tiling tl = make_tiling(s.box, ctx->tile2, ctx->tile3);
   const int rmode = ctx->repair_mode;
   QueueRef Q{};
   {
@@ -298,28 +307,28 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
                              nblocks, prm, (uint8_t*)d_stream, stream_cap, ndim,
                              s.d, hs, ev_last(ctx, LOPC_PHASE_RANGE)));
   uint64_t sweeps = 1, active = tl.ntiles, qruns = 0, qparks = 0;
-  const int two_d = tl.tz == 1;
+  const int sid = tl.sid;
   // Device-driven repair (Alg. 1 loop at tile granularity, no host read):
   // the first pass (quantize, order flags, first relaxation, fused per
   // tile), K sweeps over work lists, the repair queue for whatever is still
   // listed (nothing, when K sweeps were enough; with K = 0 the first pass
   // lists its tiles in the queue itself), then the encoder and the report.
   auto device_repair = [&](uint32_t K) -> int {
-    if (!ctx->rq_per_cu[two_d]) ctx->rq_per_cu[two_d] = repair_q_blocks_per_cu(two_d);
-    if (!ctx->sl_per_cu[two_d]) ctx->sl_per_cu[two_d] = sweep_list_blocks_per_cu(two_d);
+    if (!ctx->rq_per_cu[sid]) ctx->rq_per_cu[sid] = repair_q_blocks_per_cu(sid);
+    if (!ctx->sl_per_cu[sid]) ctx->sl_per_cu[sid] = sweep_list_blocks_per_cu(sid);
     uint32_t* lists = K ? (uint32_t*)(ws + L.lists) : nullptr;
     HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
                               (uint16_t*)(ws + L.mask), sub, stamp, counters, lists,
                               K ? QueueRef{} : Q, hs, ev_only(ctx, LOPC_PHASE_QUANT)));
     const int sgrid = (int)std::max<uint64_t>(
-        1, std::min<uint64_t>(tl.ntiles, (uint64_t)ctx->sl_per_cu[two_d] * ctx->num_cu));
+        1, std::min<uint64_t>(tl.ntiles, (uint64_t)ctx->sl_per_cu[sid] * ctx->num_cu));
     for (uint32_t t = 1; t <= K; ++t)
       HIP_CTX(ctx, launch_sweep_list(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
                                      counters, lists, t, sgrid, hs,
                                      t == 1 ? ev_first(ctx, LOPC_PHASE_REPAIR) : Ev{}));
     if (K) HIP_CTX(ctx, launch_seed_queue(counters, lists, tl.ntiles, K + 1, Q, hs));
     const int grid = (int)std::max<uint64_t>(
-        1, std::min<uint64_t>(tl.ntiles, (uint64_t)ctx->rq_per_cu[two_d] * ctx->num_cu));
+        1, std::min<uint64_t>(tl.ntiles, (uint64_t)ctx->rq_per_cu[sid] * ctx->num_cu));
     HIP_CTX(ctx, launch_repair_q(s.box, tl, (const uint16_t*)(ws + L.mask), sub, counters, Q,
                                  grid, hs,
                                  K ? ev_last(ctx, LOPC_PHASE_REPAIR)

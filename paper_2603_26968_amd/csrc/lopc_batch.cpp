@@ -43,7 +43,8 @@ struct Plan {
 
 // Validate the jobs and lay the batch out on workspace base `ws` (0 to size
 // it).  On a bad job returns its status and sets *bad to its index.
-int make_plan(int op, int n, const lopc_job* in, uintptr_t ws, Plan& P, int* bad) {
+int make_plan(int op, int n, const lopc_job* in, uintptr_t ws, int t2, int t3, Plan& P,
+              int* bad) {
   *bad = -1;
   if (n < 1 || !in) return LOPC_E_ARG;
   P.order.resize(n);
@@ -90,7 +91,7 @@ int make_plan(int op, int n, const lopc_job* in, uintptr_t ws, Plan& P, int* bad
     Job& J = P.jobs[q];
     const uint64_t k = j.dtype == 0 ? 4 : 8, W = kChunkBytes / k;
     J.box = s.box;
-    J.tl = make_tiling(s.box);
+    J.tl = make_tiling(s.box, t2, t3);
     J.nch = (uint32_t)((s.n + W - 1) / W);
     J.dtype = j.dtype;
     J.mode = op == 0 ? j.mode : 0;
@@ -180,7 +181,7 @@ int make_plan(int op, int n, const lopc_job* in, uintptr_t ws, Plan& P, int* bad
   // a field whose repair falls back to its own compression runs it inside
   // this workspace
   if (op == 0)
-    for (int i = 0; i < n; ++i) P.total = std::max(P.total, compress_layout(shp[i], in[i].dtype).total);
+    for (int i = 0; i < n; ++i) P.total = std::max(P.total, compress_layout(shp[i], in[i].dtype, t2, t3).total);
   D.tiles = (uint32_t)P.tiles;
   D.zero_words = (P.zero_end - P.zero_off) / 4;
   D.zero_base = (uint32_t*)(ws + P.zero_off);
@@ -247,12 +248,14 @@ hipError_t enqueue(lopc_ctx* c, int op, uint8_t* ws, const BatchDesc& D, uint32_
     }
     for (int g = 0; g < kGroups; ++g) {
       if (!(gmask & (1u << g))) continue;
-      if (pers) Q(launch_tile0_p(g, bd, jobs, grid_of(c, PK_TILE0), s));
-      else Q(launch_tile0_d(g, bd, jobs, items(D, PH_T, g, g + 1), s));
+      if (pers) Q(launch_tile0_p(g, c->tile2, c->tile3, bd, jobs, grid_of(c, PK_TILE0), s));
+      else Q(launch_tile0_d(g, c->tile2, c->tile3, bd, jobs, items(D, PH_T, g, g + 1), s));
     }
     for (int t = 1; t <= sweeps; ++t) {
-      if (pers) Q(launch_repair_p(bd, jobs, (uint32_t)t, grid_of(c, PK_REPAIR), s));
-      else Q(launch_repair_d(bd, jobs, (uint32_t)t, D.tiles, s));
+      if (pers)
+        Q(launch_repair_p(c->tile2, c->tile3, bd, jobs, (uint32_t)t, grid_of(c, PK_REPAIR), s));
+      else
+        Q(launch_repair_d(c->tile2, c->tile3, bd, jobs, (uint32_t)t, D.tiles, s));
     }
     for (int d = 0; d < 2; ++d) {
       if (!has[d]) continue;
@@ -277,7 +280,7 @@ hipError_t enqueue(lopc_ctx* c, int op, uint8_t* ws, const BatchDesc& D, uint32_
 bool graph_fits(const BatchGraph& g, lopc_ctx* c, int op, const void* ws, uint32_t gmask,
                 int sweeps, const BatchDesc& D) {
   if (g.op != op || g.ws != ws || g.gmask != gmask || g.sweeps != sweeps ||
-      g.grid_pct != c->persist_pct)
+      g.grid_pct != c->persist_pct || g.tile2 != c->tile2 || g.tile3 != c->tile3)
     return false;
   if (c->persist_pct > 0) return true;
   // direct grids: the batch's shape must match
@@ -320,6 +323,8 @@ int run_sequence(lopc_ctx* c, int op, uint8_t* ws, const BatchDesc& D, uint32_t 
     g.gmask = gmask;
     g.sweeps = sweeps;
     g.grid_pct = c->persist_pct;
+    g.tile2 = c->tile2;
+    g.tile3 = c->tile3;
     std::memcpy(g.job0, D.job0, sizeof(D.job0));
     std::memcpy(g.item0, D.item0, sizeof(D.item0));
     g.tiles = D.tiles;
@@ -391,7 +396,7 @@ int batch_common(lopc_ctx* c, int op, int n, const lopc_job* jobs, void* d_ws,
     return LOPC_E_ARG;
   }
   int bad;
-  int st = make_plan(op, n, jobs, (uintptr_t)d_ws, P, &bad);
+  int st = make_plan(op, n, jobs, (uintptr_t)d_ws, c->tile2, c->tile3, P, &bad);
   if (st) {
     reject(c, n, bad, st);
     return st;
@@ -410,13 +415,19 @@ extern "C" {
 
 int lopc_batch_workspace_size(lopc_ctx* ctx, int op, int n, const lopc_job* jobs,
                               size_t* bytes) {
-  (void)ctx;
   if (!bytes || (op != 0 && op != 1)) return LOPC_E_ARG;
-  Plan P;
-  int bad;
-  int st = make_plan(op, n, jobs, 0, P, &bad);
-  if (st) return st;
-  *bytes = P.total;
+  (void)ctx;
+  // the largest over every tile shape, as lopc_workspace_size
+  size_t b = 0;
+  for (int t2 = 0; t2 < (op == 0 ? kTiles2 : 1); ++t2)
+    for (int t3 = 0; t3 < (op == 0 ? kTiles3 : 1); ++t3) {
+      Plan P;
+      int bad;
+      int st = make_plan(op, n, jobs, 0, t2, t3, P, &bad);
+      if (st) return st;
+      b = std::max(b, (size_t)P.total);
+    }
+  *bytes = b;
   return LOPC_OK;
 }
 
@@ -459,9 +470,11 @@ int lopc_compress_batch(lopc_ctx* ctx, int n, const lopc_job* jobs, void* d_ws,
       }
       for (uint32_t b = 0; b < batch; ++b) {
         if (ctx->persist_pct > 0)
-          HIP_CTX(ctx, launch_repair_p(bd, dj, next + b, grid_of(ctx, PK_REPAIR), hs));
+          HIP_CTX(ctx, launch_repair_p(ctx->tile2, ctx->tile3, bd, dj, next + b,
+                                       grid_of(ctx, PK_REPAIR), hs));
         else
-          HIP_CTX(ctx, launch_repair_d(bd, dj, next + b, P.desc.tiles, hs));
+          HIP_CTX(ctx, launch_repair_d(ctx->tile2, ctx->tile3, bd, dj, next + b, P.desc.tiles,
+                                       hs));
       }
       if (int st = read_back(ctx, P, ws, n, hs)) return st;
       hc = host_counters(ctx);
@@ -579,33 +592,57 @@ int lopc_ctx_last_batch(lopc_ctx* ctx, int n, uint64_t* h_sizes, int32_t* h_stat
 
 int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void* d_ws,
                         size_t ws_bytes, void* stream, int reps, int* h_pct) {
-  if (!ctx || (op != 0 && op != 1) || reps < 1) return LOPC_E_ARG;
+  if (!ctx || (op != 0 && op != 1) || reps < 1 || n < 1 || !jobs) return LOPC_E_ARG;
   static const int kCand[] = {0, 50, 100, 200};
-  const int keep = ctx->persist_pct;
-  int best = keep;
+  // tile shapes matter to compression only, and only for the kinds of field
+  // present; a shape whose workspace exceeds ws_bytes is skipped
+  bool has2 = false, has3 = false;
+  for (int i = 0; i < n; ++i) (group_of(jobs[i]) & 1 ? has3 : has2) = true;
+  const int n2 = op == 0 && has2 ? kTiles2 : 1, n3 = op == 0 && has3 ? kTiles3 : 1;
+  const int keep_pct = ctx->persist_pct, keep2 = ctx->tile2, keep3 = ctx->tile3;
+  int best_pct = keep_pct, best2 = keep2, best3 = keep3;
   double best_t = 1e300;
-  for (int pct : kCand) {
-    ctx->persist_pct = pct;
-    // one call to capture (or warm) this configuration, then the timed ones
-    double t = 0.0;
-    for (int r = 0; r <= reps; ++r) {
-      auto t0 = std::chrono::steady_clock::now();
-      int st = op == 0 ? lopc_compress_batch(ctx, n, jobs, d_ws, ws_bytes, stream, nullptr)
-                       : lopc_decompress_batch(ctx, n, jobs, d_ws, ws_bytes, stream);
-      auto t1 = std::chrono::steady_clock::now();
-      if (st == LOPC_E_ARG || st == LOPC_E_HIP || st == LOPC_E_INTERNAL) {
-        ctx->persist_pct = keep;
-        return st;
+  for (int i2 = 0; i2 < n2; ++i2) {
+    for (int i3 = 0; i3 < n3; ++i3) {
+      const int t2 = n2 > 1 ? i2 : keep2, t3 = n3 > 1 ? i3 : keep3;
+      if (op == 0) {
+        Plan P;
+        int bad;
+        if (make_plan(op, n, jobs, 0, t2, t3, P, &bad) != LOPC_OK || P.total > ws_bytes)
+          continue;
       }
-      if (r) t += std::chrono::duration<double>(t1 - t0).count();
-    }
-    if (t < best_t) {
-      best_t = t;
-      best = pct;
+      ctx->tile2 = t2;
+      ctx->tile3 = t3;
+      for (int pct : kCand) {
+        ctx->persist_pct = pct;
+        // one call to capture (or warm) this configuration, then the timed ones
+        double t = 0.0;
+        for (int r = 0; r <= reps; ++r) {
+          auto t0 = std::chrono::steady_clock::now();
+          int st = op == 0 ? lopc_compress_batch(ctx, n, jobs, d_ws, ws_bytes, stream, nullptr)
+                           : lopc_decompress_batch(ctx, n, jobs, d_ws, ws_bytes, stream);
+          auto t1 = std::chrono::steady_clock::now();
+          if (st == LOPC_E_ARG || st == LOPC_E_HIP || st == LOPC_E_INTERNAL) {
+            ctx->persist_pct = keep_pct;
+            ctx->tile2 = keep2;
+            ctx->tile3 = keep3;
+            return st;
+          }
+          if (r) t += std::chrono::duration<double>(t1 - t0).count();
+        }
+        if (t < best_t) {
+          best_t = t;
+          best_pct = pct;
+          best2 = t2;
+          best3 = t3;
+        }
+      }
     }
   }
-  ctx->persist_pct = best;
-  if (h_pct) *h_pct = best;
+  ctx->persist_pct = best_pct;
+  ctx->tile2 = best2;
+  ctx->tile3 = best3;
+  if (h_pct) *h_pct = best_pct;
   return LOPC_OK;
 }
 
@@ -630,12 +667,33 @@ int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value) {
       if (value < 0 || value > 400) return LOPC_E_ARG;
       ctx->persist_pct = (int)value;
       return LOPC_OK;
+    case LOPC_OPT_TILE_2D:
+      if (value < 0 || value >= kTiles2) return LOPC_E_ARG;
+      ctx->tile2 = (int)value;
+      return LOPC_OK;
+    case LOPC_OPT_TILE_3D:
+      if (value < 0 || value >= kTiles3) return LOPC_E_ARG;
+      ctx->tile3 = (int)value;
+      return LOPC_OK;
     case LOPC_OPT_REPAIR:
       if (value < LOPC_REPAIR_AUTO || value > LOPC_REPAIR_SWEEPS) return LOPC_E_ARG;
       ctx->repair_mode = (int)value;
       return LOPC_OK;
     default:
       return LOPC_E_ARG;
+  }
+}
+
+int lopc_ctx_get_option(lopc_ctx* ctx, int option, int64_t* h_value) {
+  if (!ctx || !h_value) return LOPC_E_ARG;
+  switch (option) {
+    case LOPC_OPT_BATCH_GRAPH: *h_value = ctx->use_graph; return LOPC_OK;
+    case LOPC_OPT_GRAPH_SWEEPS: *h_value = ctx->graph_sweeps; return LOPC_OK;
+    case LOPC_OPT_PERSIST_PCT: *h_value = ctx->persist_pct; return LOPC_OK;
+    case LOPC_OPT_TILE_2D: *h_value = ctx->tile2; return LOPC_OK;
+    case LOPC_OPT_TILE_3D: *h_value = ctx->tile3; return LOPC_OK;
+    case LOPC_OPT_REPAIR: *h_value = ctx->repair_mode; return LOPC_OK;
+    default: return LOPC_E_ARG;
   }
 }
 

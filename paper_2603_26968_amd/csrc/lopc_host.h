@@ -22,6 +22,7 @@ struct BatchGraph {
   uint32_t gmask;      // groups present
   int sweeps;          // repair sweeps captured (compress)
   int grid_pct;        // persistent grid size it was captured with (0: direct)
+  int tile2, tile3;    // tile shapes it was captured with
   uint32_t job0[lopc::kGroups + 1];             // direct grids: the batch shape
   uint32_t item0[lopc::PH_N][lopc::kGroups + 1];
   uint32_t tiles;
@@ -48,8 +49,9 @@ struct lopc_ctx {
   double ms[LOPC_PHASES];
   int sweep_hint;      // single field: repair sweeps enqueued before the first read
   int repair_mode;     // single field: LOPC_REPAIR_HYBRID, _QUEUE or _SWEEPS
-  int rq_per_cu[2];    // resident repair-queue workgroups per CU (3D, 2D tiles)
-  int sl_per_cu[2];    // resident list-sweep workgroups per CU (3D, 2D tiles)
+  int rq_per_cu[lopc::kTileShapes];  // resident repair-queue workgroups per CU, per tile shape
+  int sl_per_cu[lopc::kTileShapes];  // resident list-sweep workgroups per CU, per tile shape
+  int tile2, tile3;    // tile shape indices (kTile2 / kTile3)
   void* scratch;       // device address of the library-held scratch on this device
   // batches
   int use_graph;       // capture batch sequences as graphs
@@ -108,13 +110,12 @@ inline int make_shape(int ndim, const int64_t* dims, Shape* s) {
   return LOPC_OK;
 }
 
-inline Tiling make_tiling(const Box& b) {
+// t2 / t3: the 2D and 3D tile shape indices (kTile2 / kTile3)
+inline Tiling make_tiling(const Box& b, int t2, int t3) {
   Tiling t;
-  if (b.nz == 1) {
-    t.tz = 1; t.ty = 32; t.tx = 64;
-  } else {
-    t.tz = 8; t.ty = 8; t.tx = 32;
-  }
+  const int* e = b.nz == 1 ? kTile2[t2] : kTile3[t3];
+  t.tz = e[0]; t.ty = e[1]; t.tx = e[2];
+  t.sid = b.nz == 1 ? t2 : kTiles2 + t3;
   t.ntz = (b.nz + t.tz - 1) / t.tz;
   t.nty = (b.ny + t.ty - 1) / t.ty;
   t.ntx = (b.nx + t.tx - 1) / t.tx;
@@ -132,11 +133,11 @@ struct CompressLayout {
 // [1 + s % 64] tiles marked for sweep s (a ring the host clears after
 // reading), [kRelaxWord] 64-bit relaxation iteration total
 
-inline CompressLayout compress_layout(const Shape& s, int dtype) {
+inline CompressLayout compress_layout(const Shape& s, int dtype, int t2, int t3) {
   const size_t k = dtype == 0 ? 4 : 8;
   const uint64_t W = kChunkBytes / k;
   const uint64_t nch = (s.n + W - 1) / W;
-  Tiling t = make_tiling(s.box);
+  Tiling t = make_tiling(s.box, t2, t3);
   CompressLayout L;
   size_t o = 0;
   L.cap_log2 = queue_cap_log2(t.ntiles);

@@ -52,12 +52,33 @@ struct Box {
   uint32_t n;  // points
 };
 
+// Tile shapes of the repair compiled into the library, chosen per context
+// (LOPC_OPT_TILE_2D / LOPC_OPT_TILE_3D): index 0 of each is the default.
+// A shape id numbers all of them: 2D shapes 0..1, 3D shapes 2..4.
+constexpr int kTiles2 = 2, kTiles3 = 3, kTileShapes = kTiles2 + kTiles3;
+constexpr int kTile2[kTiles2][3] = {{1, 32, 64}, {1, 16, 128}};
+constexpr int kTile3[kTiles3][3] = {{4, 8, 32}, {8, 8, 32}, {8, 16, 16}};
+
 // Repair tiling.
 struct Tiling {
   int32_t tz, ty, tx;     // tile extent
   int32_t ntz, nty, ntx;  // tiles per axis
   uint32_t ntiles;
+  int32_t sid;            // shape id (see kTile2 / kTile3)
 };
+
+// Run the statements after t with TZ, TY, TX the compile-time extents of
+// tiling t's shape.
+#define LOPC_WITH_TILE(t, ...)                                                  \
+  do {                                                                          \
+    switch ((t).sid) {                                                          \
+      case 0: { constexpr int TZ = 1, TY = 32, TX = 64; __VA_ARGS__; } break;   \
+      case 1: { constexpr int TZ = 1, TY = 16, TX = 128; __VA_ARGS__; } break;  \
+      case 2: { constexpr int TZ = 4, TY = 8, TX = 32; __VA_ARGS__; } break;    \
+      case 3: { constexpr int TZ = 8, TY = 8, TX = 32; __VA_ARGS__; } break;    \
+      default: { constexpr int TZ = 8, TY = 16, TX = 16; __VA_ARGS__; } break;  \
+    }                                                                           \
+  } while (0)
 
 // ------------------------------------------------------------------ batches
 // A batch runs every phase as one persistent launch per (dtype, tile shape)
@@ -251,7 +272,7 @@ hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm
 hipError_t launch_sweep_list(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
                              uint32_t* stamp, uint32_t* counters, uint32_t* lists,
                              uint32_t sweep, int grid, hipStream_t s, Ev ev = {});
-int sweep_list_blocks_per_cu(bool two_d);
+int sweep_list_blocks_per_cu(int sid);
 // Lists the tiles of the work list of sweep `sweep` in the repair queue.
 hipError_t launch_seed_queue(const uint32_t* counters, const uint32_t* lists, uint32_t ntiles,
                              uint32_t sweep, const QueueRef& Q, hipStream_t s);
@@ -260,7 +281,7 @@ hipError_t launch_seed_queue(const uint32_t* counters, const uint32_t* lists, ui
 hipError_t launch_repair_q(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
                            uint32_t* counters, const QueueRef& Q, int grid, hipStream_t s,
                            Ev ev = {});
-int repair_q_blocks_per_cu(bool two_d);
+int repair_q_blocks_per_cu(int sid);
 // Writes the stream size (0 after a failure other than capacity) and the
 // lopc_status code of a compression to the caller's device words (either
 // may be null); q (may be null): its repair queue.
@@ -296,10 +317,11 @@ hipError_t launch_minmax_p(int dtype, const BatchDesc* bd, const Job* jobs, int 
                            hipStream_t s);
 hipError_t launch_params_p(int dtype, const BatchDesc* bd, const Job* jobs, int grid,
                            hipStream_t s);
-hipError_t launch_tile0_p(int group, const BatchDesc* bd, const Job* jobs, int grid,
-                          hipStream_t s);
-hipError_t launch_repair_p(const BatchDesc* bd, const Job* jobs, uint32_t sweep, int grid,
-                           hipStream_t s);
+// t2 / t3: the batch's 2D and 3D tile shape indices (kTile2 / kTile3)
+hipError_t launch_tile0_p(int group, int t2, int t3, const BatchDesc* bd, const Job* jobs,
+                          int grid, hipStream_t s);
+hipError_t launch_repair_p(int t2, int t3, const BatchDesc* bd, const Job* jobs, uint32_t sweep,
+                           int grid, hipStream_t s);
 hipError_t launch_encode_p(int dtype, const BatchDesc* bd, const Job* jobs, int gate_sweep,
                            int grid, hipStream_t s);
 hipError_t launch_finalize_c(const BatchDesc* bd, const Job* jobs, int gate_sweep,
@@ -315,10 +337,10 @@ hipError_t launch_minmax_d(int dtype, const BatchDesc* bd, const Job* jobs, uint
                            hipStream_t s);
 hipError_t launch_params_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t njobs,
                            hipStream_t s);
-hipError_t launch_tile0_d(int group, const BatchDesc* bd, const Job* jobs, uint32_t items,
-                          hipStream_t s);
-hipError_t launch_repair_d(const BatchDesc* bd, const Job* jobs, uint32_t sweep, uint32_t tiles,
-                           hipStream_t s);
+hipError_t launch_tile0_d(int group, int t2, int t3, const BatchDesc* bd, const Job* jobs,
+                          uint32_t items, hipStream_t s);
+hipError_t launch_repair_d(int t2, int t3, const BatchDesc* bd, const Job* jobs, uint32_t sweep,
+                           uint32_t tiles, hipStream_t s);
 hipError_t launch_encode_d(int dtype, const BatchDesc* bd, const Job* jobs, int gate_sweep,
                            uint32_t items, hipStream_t s);
 hipError_t launch_decode_d(int dtype, const BatchDesc* bd, const Job* jobs, uint32_t items,

@@ -1111,7 +1111,21 @@ __global__ __launch_bounds__(kThreads) void k_tile0_p(const BatchDesc* bd, const
   }
 }
 
+// One run of batch tile `t` of job J: the batch's 2D shape S2 or 3D shape S3.
+template <int S2, int S3>
+__device__ __forceinline__ uint32_t batch_repair_run(const Job& J, uint32_t* err,
+                                                     unsigned long long* itot, uint32_t sweep,
+                                                     uint32_t t, TileCoord& c) {
+  if (J.tl.tz == 1)
+    return repair_body<1, kTile2[S2][1], kTile2[S2][2]>(J.box, J.tl, J.mask, J.sub, J.stamp, err,
+                                                        itot, sweep, t, c);
+  return repair_body<kTile3[S3][0], kTile3[S3][1], kTile3[S3][2]>(J.box, J.tl, J.mask, J.sub,
+                                                                  J.stamp, err, itot, sweep, t,
+                                                                  c);
+}
+
 // One sweep over the tiles listed for it, of fields of both tile shapes.
+template <int S2, int S3>
 __global__ __launch_bounds__(kThreads) void k_repair_p(const BatchDesc* bd, const Job* jobs,
                                                        uint32_t sweep) {
   __shared__ uint32_t s_it;
@@ -1129,13 +1143,8 @@ __global__ __launch_bounds__(kThreads) void k_repair_p(const BatchDesc* bd, cons
     const uint32_t item = list_in[it];
     const Job& J = jobs[find_job<&Job::t0>(jobs, 0, nj, item)];
     TileCoord c;
-    uint32_t dirs;
-    if (J.tl.tz == 1)
-      dirs = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
-                                    bc->relax_iters, sweep, item - J.t0, c);
-    else
-      dirs = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
-                                   bc->relax_iters, sweep, item - J.t0, c);
+    const uint32_t dirs = batch_repair_run<S2, S3>(J, &bc->err, bc->relax_iters, sweep,
+                                                   item - J.t0, c);
     if (dirs) mark_list(dirs, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
   }
 }
@@ -1173,6 +1182,7 @@ __global__ __launch_bounds__(kThreads) void k_tile0_d(const BatchDesc* bd, const
 
 // One sweep: workgroup b takes entry b of the sweep's work list (the grid
 // is the list's capacity; workgroups past its length exit at once).
+template <int S2, int S3>
 __global__ __launch_bounds__(kThreads) void k_repair_d(const BatchDesc* bd, const Job* jobs,
                                                        uint32_t sweep) {
   BatchCounters* bc = bd->bc;
@@ -1181,13 +1191,8 @@ __global__ __launch_bounds__(kThreads) void k_repair_d(const BatchDesc* bd, cons
   const Job& J = jobs[find_job<&Job::t0>(jobs, 0, (int)bd->job0[kGroups], item)];
   uint32_t* list_out = bd->lists + ((sweep + 1) & 1) * bd->tiles;
   TileCoord c;
-  uint32_t dirs;
-  if (J.tl.tz == 1)
-    dirs = repair_body<1, 32, 64>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
-                                  bc->relax_iters, sweep, item - J.t0, c);
-  else
-    dirs = repair_body<8, 8, 32>(J.box, J.tl, J.mask, J.sub, J.stamp, &bc->err,
-                                 bc->relax_iters, sweep, item - J.t0, c);
+  const uint32_t dirs = batch_repair_run<S2, S3>(J, &bc->err, bc->relax_iters, sweep,
+                                                 item - J.t0, c);
   if (dirs) mark_list(dirs, c, J.tl, J.stamp, J.t0, bc->lens, list_out, sweep + 1);
 }
 
@@ -1226,21 +1231,14 @@ hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm
                         uint32_t* counters, uint32_t* lists, const QueueRef& Q, hipStream_t s,
                         Ev ev) {
   const dim3 g(t.ntiles), b(kThreads);
-  if (t.tz == 1) {
+  LOPC_WITH_TILE(t, {
     if (dtype == 0)
-      launch_ev(k_tile0<4, 1, 32, 64>, g, b, s, ev, (const uint32_t*)x,
-                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters, lists, Q);
+      launch_ev(k_tile0<4, TZ, TY, TX>, g, b, s, ev, (const uint32_t*)x, box, t, prm,
+                (int32_t*)bins, mask, sub, stamp, counters, lists, Q);
     else
-      launch_ev(k_tile0<8, 1, 32, 64>, g, b, s, ev, (const uint64_t*)x,
-                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters, lists, Q);
-  } else {
-    if (dtype == 0)
-      launch_ev(k_tile0<4, 8, 8, 32>, g, b, s, ev, (const uint32_t*)x,
-                            box, t, prm, (int32_t*)bins, mask, sub, stamp, counters, lists, Q);
-    else
-      launch_ev(k_tile0<8, 8, 8, 32>, g, b, s, ev, (const uint64_t*)x,
-                            box, t, prm, (int64_t*)bins, mask, sub, stamp, counters, lists, Q);
-  }
+      launch_ev(k_tile0<8, TZ, TY, TX>, g, b, s, ev, (const uint64_t*)x, box, t, prm,
+                (int64_t*)bins, mask, sub, stamp, counters, lists, Q);
+  });
   return hipGetLastError();
 }
 
@@ -1269,20 +1267,18 @@ hipError_t launch_sweep_list(Box box, Tiling t, const uint16_t* mask, uint32_t* 
                              uint32_t* stamp, uint32_t* counters, uint32_t* lists,
                              uint32_t sweep, int grid, hipStream_t s, Ev ev) {
   const dim3 g(grid), b(kThreads);
-  if (t.tz == 1)
-    launch_ev(k_sweep_list<1, 32, 64>, g, b, s, ev, box, t, mask, sub, stamp, counters, lists,
-              sweep);
-  else
-    launch_ev(k_sweep_list<8, 8, 32>, g, b, s, ev, box, t, mask, sub, stamp, counters, lists,
-              sweep);
+  LOPC_WITH_TILE(t, launch_ev(k_sweep_list<TZ, TY, TX>, g, b, s, ev, box, t, mask, sub, stamp,
+                              counters, lists, sweep));
   return hipGetLastError();
 }
 
-int sweep_list_blocks_per_cu(bool two_d) {
+int sweep_list_blocks_per_cu(int sid) {
   int b = 0;
-  const hipError_t e =
-      two_d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep_list<1, 32, 64>, kThreads, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sweep_list<8, 8, 32>, kThreads, 0);
+  Tiling t{};
+  t.sid = sid;
+  hipError_t e = hipErrorInvalidValue;
+  LOPC_WITH_TILE(t, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &b, k_sweep_list<TZ, TY, TX>, kThreads, 0));
   return e == hipSuccess && b > 0 ? b : 1;
 }
 
@@ -1297,21 +1293,19 @@ hipError_t launch_repair_q(Box box, Tiling t, const uint16_t* mask, uint32_t* su
                            uint32_t* counters, const QueueRef& Q, int grid, hipStream_t s,
                            Ev ev) {
   const dim3 g(grid), b(kThreads);
-  if (t.tz == 1)
-    launch_ev(k_repair_q<1, 32, 64>, g, b, s, ev, box, t, mask, sub,
-                          counters, Q);
-  else
-    launch_ev(k_repair_q<8, 8, 32>, g, b, s, ev, box, t, mask, sub,
-                          counters, Q);
+  LOPC_WITH_TILE(t, launch_ev(k_repair_q<TZ, TY, TX>, g, b, s, ev, box, t, mask, sub, counters,
+                              Q));
   return hipGetLastError();
 }
 
-// resident workgroups per CU of the single-field repair kernel (2D or 3D tiles)
-int repair_q_blocks_per_cu(bool two_d) {
+// resident workgroups per CU of the single-field repair-queue kernel
+int repair_q_blocks_per_cu(int sid) {
   int b = 0;
-  const hipError_t e =
-      two_d ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_q<1, 32, 64>, kThreads, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_q<8, 8, 32>, kThreads, 0);
+  Tiling t{};
+  t.sid = sid;
+  hipError_t e = hipErrorInvalidValue;
+  LOPC_WITH_TILE(t, e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &b, k_repair_q<TZ, TY, TX>, kThreads, 0));
   return e == hipSuccess && b > 0 ? b : 1;
 }
 
@@ -1319,12 +1313,8 @@ hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
                          uint32_t* stamp, uint32_t* counters, uint32_t sweep,
                          hipStream_t s, Ev ev) {
   const dim3 g(t.ntiles), b(kThreads);
-  if (t.tz == 1)
-    launch_ev(k_repair<1, 32, 64>, g, b, s, ev, box, t, mask, sub,
-                          stamp, counters, sweep);
-  else
-    launch_ev(k_repair<8, 8, 32>, g, b, s, ev, box, t, mask, sub,
-                          stamp, counters, sweep);
+  LOPC_WITH_TILE(t, launch_ev(k_repair<TZ, TY, TX>, g, b, s, ev, box, t, mask, sub, stamp,
+                              counters, sweep));
   return hipGetLastError();
 }
 
@@ -1354,20 +1344,41 @@ hipError_t launch_params_p(int dtype, const BatchDesc* bd, const Job* jobs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_tile0_p(int group, const BatchDesc* bd, const Job* jobs, int grid,
-                          hipStream_t s) {
-  switch (group) {
-    case 0: k_tile0_p<4, 1, 32, 64><<<grid, kThreads, 0, s>>>(bd, jobs, 0); break;
-    case 1: k_tile0_p<4, 8, 8, 32><<<grid, kThreads, 0, s>>>(bd, jobs, 1); break;
-    case 2: k_tile0_p<8, 1, 32, 64><<<grid, kThreads, 0, s>>>(bd, jobs, 2); break;
-    default: k_tile0_p<8, 8, 8, 32><<<grid, kThreads, 0, s>>>(bd, jobs, 3); break;
-  }
+// the tile extents of a batch group (2D groups: shape t2, 3D groups: t3)
+static Tiling group_tiling(int group, int t2, int t3) {
+  Tiling t{};
+  t.sid = (group & 1) ? kTiles2 + t3 : t2;
+  return t;
+}
+
+hipError_t launch_tile0_p(int group, int t2, int t3, const BatchDesc* bd, const Job* jobs,
+                          int grid, hipStream_t s) {
+  const Tiling t = group_tiling(group, t2, t3);
+  LOPC_WITH_TILE(t, {
+    if (group < 2) k_tile0_p<4, TZ, TY, TX><<<grid, kThreads, 0, s>>>(bd, jobs, group);
+    else k_tile0_p<8, TZ, TY, TX><<<grid, kThreads, 0, s>>>(bd, jobs, group);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_repair_p(const BatchDesc* bd, const Job* jobs, uint32_t sweep, int grid,
-                           hipStream_t s) {
-  k_repair_p<<<grid, kThreads, 0, s>>>(bd, jobs, sweep);
+// the repair kernels of the batch for shape pair (t2, t3)
+#define LOPC_WITH_PAIR(t2, t3, ...)                                          \
+  do {                                                                       \
+    const int pair_ = (t2) * kTiles3 + (t3);                                 \
+    switch (pair_) {                                                         \
+      case 0: { constexpr int S2 = 0, S3 = 0; __VA_ARGS__; } break;          \
+      case 1: { constexpr int S2 = 0, S3 = 1; __VA_ARGS__; } break;          \
+      case 2: { constexpr int S2 = 0, S3 = 2; __VA_ARGS__; } break;          \
+      case 3: { constexpr int S2 = 1, S3 = 0; __VA_ARGS__; } break;          \
+      case 4: { constexpr int S2 = 1, S3 = 1; __VA_ARGS__; } break;          \
+      default: { constexpr int S2 = 1, S3 = 2; __VA_ARGS__; } break;         \
+    }                                                                        \
+  } while (0)
+static_assert(kTiles2 == 2 && kTiles3 == 3, "LOPC_WITH_PAIR lists every shape pair");
+
+hipError_t launch_repair_p(int t2, int t3, const BatchDesc* bd, const Job* jobs, uint32_t sweep,
+                           int grid, hipStream_t s) {
+  LOPC_WITH_PAIR(t2, t3, (k_repair_p<S2, S3><<<grid, kThreads, 0, s>>>(bd, jobs, sweep)));
   return hipGetLastError();
 }
 
@@ -1387,22 +1398,21 @@ hipError_t launch_params_d(int dtype, const BatchDesc* bd, const Job* jobs, uint
   return hipGetLastError();
 }
 
-hipError_t launch_tile0_d(int group, const BatchDesc* bd, const Job* jobs, uint32_t items,
-                          hipStream_t s) {
+hipError_t launch_tile0_d(int group, int t2, int t3, const BatchDesc* bd, const Job* jobs,
+                          uint32_t items, hipStream_t s) {
   if (!items) return hipSuccess;
-  switch (group) {
-    case 0: k_tile0_d<4, 1, 32, 64><<<items, kThreads, 0, s>>>(bd, jobs, 0); break;
-    case 1: k_tile0_d<4, 8, 8, 32><<<items, kThreads, 0, s>>>(bd, jobs, 1); break;
-    case 2: k_tile0_d<8, 1, 32, 64><<<items, kThreads, 0, s>>>(bd, jobs, 2); break;
-    default: k_tile0_d<8, 8, 8, 32><<<items, kThreads, 0, s>>>(bd, jobs, 3); break;
-  }
+  const Tiling t = group_tiling(group, t2, t3);
+  LOPC_WITH_TILE(t, {
+    if (group < 2) k_tile0_d<4, TZ, TY, TX><<<items, kThreads, 0, s>>>(bd, jobs, group);
+    else k_tile0_d<8, TZ, TY, TX><<<items, kThreads, 0, s>>>(bd, jobs, group);
+  });
   return hipGetLastError();
 }
 
-hipError_t launch_repair_d(const BatchDesc* bd, const Job* jobs, uint32_t sweep, uint32_t tiles,
-                           hipStream_t s) {
+hipError_t launch_repair_d(int t2, int t3, const BatchDesc* bd, const Job* jobs, uint32_t sweep,
+                           uint32_t tiles, hipStream_t s) {
   if (!tiles) return hipSuccess;
-  k_repair_d<<<tiles, kThreads, 0, s>>>(bd, jobs, sweep);
+  LOPC_WITH_PAIR(t2, t3, (k_repair_d<S2, S3><<<tiles, kThreads, 0, s>>>(bd, jobs, sweep)));
   return hipGetLastError();
 }
 
@@ -1415,7 +1425,7 @@ int batch_blocks_per_cu(int kernel) {
     case PK_MINMAX: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_minmax_p<8>, kThreads, 0); break;
     case PK_PARAMS: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_params_p<8>, kThreads, 0); break;
     case PK_TILE0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_tile0_p<8, 8, 8, 32>, kThreads, 0); break;
-    case PK_REPAIR: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_p, kThreads, 0); break;
+    case PK_REPAIR: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_repair_p<0, 1>, kThreads, 0); break;
     default: break;
   }
   return e == hipSuccess && b > 0 ? b : 1;

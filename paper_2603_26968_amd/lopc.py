@@ -31,10 +31,11 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_decompress", "lopc_strerror", "lopc_ctx_set_timing",
            "lopc_ctx_last_timings", "lopc_ctx_last_hip_error", "lopc_decompress_h",
            "lopc_ctx_last_header", "lopc_batch_workspace_size", "lopc_compress_batch",
-           "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option",
+           "lopc_decompress_batch", "lopc_ctx_last_batch", "lopc_ctx_set_option", "lopc_ctx_get_option",
            "lopc_ctx_last_batch_headers", "lopc_batch_autotune", "lopc_verify",
            "lopc_verify_workspace_size", "lopc_decompress_static")
 LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT, LOPC_OPT_REPAIR = 1, 2, 3, 4
+LOPC_OPT_TILE_3D, LOPC_OPT_TILE_2D = 5, 6
 LOPC_REPAIR_AUTO, LOPC_REPAIR_HYBRID, LOPC_REPAIR_QUEUE, LOPC_REPAIR_SWEEPS = 0, 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
@@ -157,6 +158,8 @@ def load() -> ctypes.CDLL:
     L.lopc_ctx_last_batch_headers.restype = ci
     L.lopc_ctx_set_option.argtypes = [vp, ci, ctypes.c_int64]
     L.lopc_ctx_set_option.restype = ci
+    L.lopc_ctx_get_option.argtypes = [vp, ci, ctypes.POINTER(ctypes.c_int64)]
+    L.lopc_ctx_get_option.restype = ci
     _lib = L
     return L
 
@@ -291,6 +294,14 @@ def lopc_ctx_set_option(ctx: int, option: int, value: int) -> None:
     st = load().lopc_ctx_set_option(ctx, option, int(value))
     if st:
         raise LopcError(st, "lopc_ctx_set_option")
+
+
+def lopc_ctx_get_option(ctx: int, option: int) -> int:
+    v = ctypes.c_int64()
+    st = load().lopc_ctx_get_option(ctx, option, ctypes.byref(v))
+    if st:
+        raise LopcError(st, "lopc_ctx_get_option")
+    return v.value
 
 
 def lopc_batch_workspace_size(ctx: int, op: int, jobs) -> int:
@@ -609,8 +620,9 @@ def compress_batch(fields, error_bounds, modes="noa", out: torch.Tensor | None =
 
 def autotune_compress_batch(fields, error_bounds, modes="noa", out=None, workspace=None,
                             ctx=None, reps: int = 2) -> int:
-    """Tune the persistent grid size of the batch path on this batch (kept in
-    the context); returns the chosen percentage."""
+    """Tune the persistent grid size and the repair tile shapes of the batch
+    path on this batch (kept in the context); returns the chosen grid
+    percentage."""
     jobs, out, offs, ctx, dev = _compress_jobs(fields, error_bounds, modes, out, ctx)
     wsz = lopc_batch_workspace_size(ctx, 0, jobs)
     ws = _workspace(ctx, wsz, dev, workspace)

@@ -177,10 +177,37 @@ def test_autotuner_keeps_results(P):
         pct = P.autotune_compress_batch(xs, [eb for _, eb, _ in batch],
                                         [m for _, _, m in batch], reps=1)
         assert pct in (0, 50, 100, 200)
+        assert P.lopc_ctx_get_option(ctx, P.LOPC_OPT_PERSIST_PCT) == pct
+        t2 = P.lopc_ctx_get_option(ctx, P.LOPC_OPT_TILE_2D)
+        t3 = P.lopc_ctx_get_option(ctx, P.LOPC_OPT_TILE_3D)
+        assert 0 <= t2 < 2 and 0 <= t3 < 3
         got, _ = batch_streams(P, batch)
-        assert_same_streams(got, want, f"tuned {pct}")
+        assert_same_streams(got, want, f"tuned {pct}% tiles {t2} {t3}")
     finally:
         P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, 0)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_TILE_2D, 0)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_TILE_3D, 0)
+
+
+@pytest.mark.parametrize("t2,t3", [(0, 1), (1, 2), (1, 0)])
+@pytest.mark.parametrize("pct", [0, 100])
+def test_tile_shapes_give_the_same_batch_streams(P, t2, t3, pct):
+    """The repair tile shape changes the schedule, not the fixed point: the
+    batch streams under every shape equal the default single-field ones."""
+    batch = mixed_batch()
+    want = single_streams(P, batch)
+    ctx = P.context(0)
+    try:
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_TILE_2D, t2)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_TILE_3D, t3)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, pct)
+        _say("batch tiles", t2, t3, "grid", pct)
+        got, _ = batch_streams(P, batch)
+        assert_same_streams(got, want, f"tiles {t2} {t3} grid {pct}")
+    finally:
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_PERSIST_PCT, 0)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_TILE_2D, 0)
+        P.lopc_ctx_set_option(ctx, P.LOPC_OPT_TILE_3D, 0)
 
 
 @pytest.mark.parametrize("pct", [1, 25, 100, 300])

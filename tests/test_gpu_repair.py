@@ -90,6 +90,41 @@ def test_schedulers_agree(P, ref, name, gen, eb):
         lopc.lopc_ctx_destroy(ctx)
 
 
+TILES = [(0, 0), (0, 1), (0, 2), (1, 0)]
+
+
+@pytest.mark.parametrize("t2,t3", TILES, ids=[f"t2_{a}-t3_{b}" for a, b in TILES])
+def test_tile_shapes_agree(P, ref, t2, t3):
+    """Every repair tile shape, under every scheduler, gives the oracle's
+    bytes (ragged tiles on every side, both dtypes, 2D and 3D), and so does
+    a falling chain along z, which crosses every tile plane."""
+    from paper_2603_26968_amd import lopc
+    cases = [(synth.turbulence_field((37, 45, 70), seed=8), 1e-2, "noa"),
+             (synth.lognormal_field((20, 33, 100), seed=9), 1e-3, "noa"),
+             (synth.fronts_field((150, 290), seed=10), 1e-3, "noa"),
+             (synth.gaussian_bumps((90, 260), seed=11).astype(np.float64), 1e-2, "noa"),
+             (_falling((96, 3, 5), np.float32), 10.0, "abs")]
+    ctx = lopc.lopc_ctx_create(0)
+    try:
+        lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_TILE_2D, t2)
+        lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_TILE_3D, t3)
+        for x, eb, mode in cases:
+            _say("tiles", t2, t3, x.shape, x.dtype)
+            want = ref.compress(x, eb, ref.NOA if mode == "noa" else ref.ABS)
+            t = torch.from_numpy(x).cuda()
+            for m in (lopc.LOPC_REPAIR_AUTO, lopc.LOPC_REPAIR_QUEUE, lopc.LOPC_REPAIR_HYBRID,
+                      lopc.LOPC_REPAIR_SWEEPS):
+                lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_REPAIR, m)
+                s = P.compress(t, eb, mode, ctx=ctx)
+                assert s.cpu().numpy().tobytes() == want, (x.shape, m)
+            lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_REPAIR, lopc.LOPC_REPAIR_AUTO)
+            out, size, status = P.compress_enqueue(t, eb, mode, ctx=ctx)
+            torch.cuda.synchronize()
+            assert status.item() == 0 and out[:size.item()].cpu().numpy().tobytes() == want
+    finally:
+        lopc.lopc_ctx_destroy(ctx)
+
+
 def test_enqueued_compress_reports_on_device(P, ref):
     """Enqueued calls: size and status words against the synchronous call
     and the oracle, also for the failure cases."""
