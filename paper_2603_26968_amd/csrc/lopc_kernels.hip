@@ -180,6 +180,12 @@ struct TileGeom {
   static constexpr int NPT = TZ * TY * TX;
   static constexpr int PER = NPT / kThreads;
   static_assert(NPT % kThreads == 0, "tile must be a multiple of the block");
+  // owned point tid + k * kThreads (slot k of thread tid) lies kSlot LDS
+  // words after slot 0: the block covers whole planes of a 3D tile, or whole
+  // rows of a 2D one
+  static_assert((TZ > 1 && TY * TX == kThreads) || (TZ == 1 && kThreads % TX == 0),
+                "slots of a thread are evenly spaced in LDS");
+  static constexpr int kSlot = TZ > 1 ? HY * HX : (kThreads / TX) * HX;
   // halo-local index of interior point i
   __device__ static int local(int i) {
     int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
@@ -290,6 +296,38 @@ __device__ __forceinline__ uint32_t walk_code(uint32_t m) {
   return code;
 }
 
+// The best raise of the point at LDS index li from all its stencil
+// neighbours, selected by its lower-neighbour mask m without branches or
+// compares: bit j of m widened to an all-ones / zero word masks the
+// neighbour's subbin, and for an even j (a neighbour of higher index, weight
+// 1) subtracting the widened bit adds the weight only where the bit is set.
+// The maxima fold three at a time.
+template <int NJ, int HX, int HXY>
+__device__ __forceinline__ uint32_t dense_best(const uint32_t* S, int li, uint32_t m,
+                                               uint32_t cur) {
+  uint32_t c[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const uint32_t v = S[li + kOff[j][0] * HXY + kOff[j][1] * HX + kOff[j][2]];
+    const uint32_t w = (uint32_t)((int32_t)(m << (31 - j)) >> 31);
+    // one AND (kept as written: the compiler would otherwise turn the masked
+    // maximum back into a compare and a select)
+    uint32_t vw;
+    asm("v_and_b32 %0, %1, %2" : "=v"(vw) : "v"(v), "v"(w));
+    c[j] = (j & 1) ? vw : vw - w;
+  }
+  uint32_t a = max(max(cur, c[0]), c[1]);
+  uint32_t b = max(max(c[2], c[3]), c[4]);
+  uint32_t r = max(max(a, b), c[5]);
+  if constexpr (NJ > 6) {
+    const uint32_t d = max(max(c[6], c[7]), c[8]);
+    const uint32_t e = max(max(c[9], c[10]), c[11]);
+    const uint32_t f = max(max(c[12], c[13]), d);
+    r = max(max(r, e), f);
+  }
+  return r;
+}
+
 // Local fixed point of the tile (masks of the owned points in registers):
 // Gauss-Seidel passes over the owned points until none rises; the halo is
 // fixed.  Only points with a same-bin lower neighbour can rise; in a 3D
@@ -315,15 +353,7 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
     const uint32_t cur = S[li];
     uint32_t best = cur;
     if (__ballot(cd == kDense)) {
-      uint32_t v[NJ];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        v[j] = S[li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2]];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const uint32_t c = v[j] + ((j & 1) ? 0u : 1u);
-        best = ((m >> j) & 1u) && c > best ? c : best;
-      }
+      best = dense_best<NJ, G::HX, G::HY * G::HX>(S, li, m, cur);
     } else {
       const int o0 = (int)(cd & 1023u) - 512, o1 = (int)((cd >> 10) & 1023u) - 512,
                 o2 = (int)((cd >> 20) & 1023u) - 512;
@@ -360,6 +390,9 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
     my_pt = wl_pt[wave() * 64 + lane()];
     my_cd = wl_cd[wave() * 64 + lane()];
   }
+  // slots: neighbour code of each owned point, fixed for the call (unused
+  // when the wave is listed); slot k lies kSlot LDS words after slot 0
+  const int li0 = G::local(threadIdx.x);
   int iters = 0;
   for (;;) {
     int changed = 0;
@@ -376,19 +409,11 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
         const int k = rev ? G::PER - 1 - kk : kk;
         const uint32_t m = mk[k];
         if (!m) continue;
-        const int li = G::local(threadIdx.x + k * kThreads);
+        const int li = li0 + k * G::kSlot;
         const uint32_t cur = S[li];
         uint32_t best = cur;
         if (__ballot(__popc(m) > 3)) {
-          uint32_t v[NJ];
-#pragma unroll
-          for (int j = 0; j < NJ; ++j)
-            v[j] = S[li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2]];
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            const uint32_t c = v[j] + ((j & 1) ? 0u : 1u);
-            best = ((m >> j) & 1u) && c > best ? c : best;
-          }
+          best = dense_best<NJ, G::HX, G::HY * G::HX>(S, li, m, cur);
         } else {
           uint32_t mm = m;
           while (mm) {
