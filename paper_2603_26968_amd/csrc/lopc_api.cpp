@@ -281,6 +281,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
   const uint64_t nch = (s.n + W - 1) / W;
   Tiling tl = make_tiling(s.box, ctx->tile2, ctx->tile3);
+  if (s.box.nz == 1) tl.lev = ws + L.lev;
   const int rmode = ctx->repair_mode;
   QueueRef Q{};
   {

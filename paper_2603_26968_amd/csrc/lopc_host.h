@@ -120,12 +120,13 @@ inline Tiling make_tiling(const Box& b, int t2, int t3) {
   t.nty = (b.ny + t.ty - 1) / t.ty;
   t.ntx = (b.nx + t.tx - 1) / t.tx;
   t.ntiles = (uint32_t)t.ntz * t.nty * t.ntx;
+  t.lev = nullptr;
   return t;
 }
 
 struct CompressLayout {
   size_t prm, counters, queue, stamp, qstate, parked, depth, ring, zero_end;  // zeroed prefix
-  size_t blockers, lists, offs, parts, part, bins, mask, sub, tail, total;
+  size_t blockers, lists, offs, parts, part, bins, mask, sub, lev, tail, total;
   uint32_t cap_log2;  // repair queue ring: 2^cap_log2 slots
 };
 
@@ -160,6 +161,7 @@ inline CompressLayout compress_layout(const Shape& s, int dtype, int t2, int t3)
   L.bins = o; o += align256(s.n * k);
   L.mask = o; o += align256(s.n * 2);
   L.sub = o; o += align256(s.n * 4);
+  L.lev = o; o += align256(s.box.nz == 1 ? s.n : 0);
   L.tail = o; o += align256(kRecordTailBytes);
   L.total = o;
   return L;

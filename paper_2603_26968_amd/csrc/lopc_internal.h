@@ -65,6 +65,9 @@ struct Tiling {
   int32_t ntz, nty, ntx;  // tiles per axis
   uint32_t ntiles;
   int32_t sid;            // shape id (see kTile2 / kTile3)
+  uint8_t* lev;           // per point of a 2D field: its level inside its
+                          // tile (255: unknown), kept by the first pass;
+                          // null: not kept
 };
 
 // Run the statements after t with TZ, TY, TX the compile-time extents of

@@ -438,6 +438,228 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
   if (threadIdx.x == 0) atomicAdd(&itot[t % 64], (unsigned long long)(iters + 1));
 }
 
+// ------------------------------------------------------------------ levels
+// 2D tiles.  The level of an owned point is the length of the longest path
+// of same-bin lower neighbours inside the tile that ends at it (0: no lower
+// neighbour inside).  Taking the points level by level, each after every
+// level below it, visits every point once with all its lower neighbours
+// already final: one pass in a topological order of the tile's part of the
+// order graph reaches the tile's fixed point for a fixed halo (the raising
+// rule of Alg. 2).  The first pass finds the levels by peeling (Kahn's
+// order: a point is ready once all its lower neighbours inside the tile are
+// done) and keeps them, one byte per point, saturating at 255; later runs
+// of the tile sort their points by the kept levels.  A 2D tile holds eight
+// slots per thread, so a relaxation pass costs eight visits per wave, while
+// a level costs one visit of the waves its points fall to: levels pay off
+// there.  3D tiles (four slots per thread, and more levels per tile) keep
+// the relaxation passes.
+
+// stencil offsets j of owned point i whose neighbour lies inside the tile
+template <int TZ, int TY, int TX>
+__device__ __forceinline__ uint32_t inside_bits(int i) {
+  constexpr int NJ = TZ == 1 ? 6 : 14;
+  const int iz = i / (TY * TX), iy = (i / TX) % TY, ix = i % TX;
+  uint32_t b = 0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int z = iz + kOff[j][0], y = iy + kOff[j][1], x = ix + kOff[j][2];
+    if (z >= 0 && z < TZ && y >= 0 && y < TY && x >= 0 && x < TX) b |= 1u << j;
+  }
+  return b;
+}
+
+// owned-index offset of stencil offset j (known only at run time)
+template <int TZ, int TY, int TX>
+__device__ __forceinline__ int own_off(int j) {
+  return off_z(j) * (TY * TX) + off_y(j) * TX + off_x(j);
+}
+
+// the best raise of the point at LDS index li (lower-neighbour mask m)
+template <int TZ, int TY, int TX>
+__device__ __forceinline__ uint32_t raise_of(const uint32_t* S, int li, uint32_t m, uint32_t cur) {
+  using G = TileGeom<TZ, TY, TX>;
+  constexpr int NJ = TZ == 1 ? 6 : 14;
+  if (__ballot(__popc(m) > 3)) return dense_best<NJ, G::HX, G::HY * G::HX>(S, li, m, cur);
+  uint32_t best = cur;
+  while (m) {
+    const int j = __builtin_ctz(m);
+    m &= m - 1;
+    const uint32_t c = S[li + off_lin(j, G::HX, G::HY * G::HX)] + ((j & 1) ? 0u : 1u);
+    best = c > best ? c : best;
+  }
+  return best;
+}
+
+// LDS of the peeling pass: per owned point its masks (lower | inside upper
+// << 16), its count of unfinished lower neighbours inside the tile (bytes),
+// its level (bytes) and the ready list; three list counters.
+template <int TZ, int TY, int TX>
+struct KahnLds {
+  static constexpr int NPT = TZ * TY * TX;
+  static constexpr int kBytes = NPT * 4 + NPT + NPT + NPT * 2 + 16;
+};
+
+// First pass of a tile with the halo subbins at 0: peel the tile's points
+// level by level (a point joins the ready list when its last lower
+// neighbour inside the tile is done) and raise each as it is taken.  Leaves
+// the levels in lvb.  Every thread must call it; returns the number of
+// levels (block-uniform).
+template <int TZ, int TY, int TX>
+__device__ int kahn_relax(uint32_t* S, uint8_t* lds, const uint16_t* mk, const uint16_t* up,
+                          uint8_t*& lvb_out) {
+  using G = TileGeom<TZ, TY, TX>;
+  constexpr int NPT = G::NPT;
+  uint32_t* W = (uint32_t*)lds;
+  uint32_t* cnt4 = (uint32_t*)(lds + NPT * 4);
+  uint8_t* cnt = (uint8_t*)cnt4;
+  uint8_t* lvb = lds + NPT * 4 + NPT;
+  uint16_t* list = (uint16_t*)(lds + NPT * 6);
+  uint32_t* kc = (uint32_t*)(lds + NPT * 8);
+  lvb_out = lvb;
+  if (threadIdx.x < 3) kc[threadIdx.x] = 0;
+  uint32_t deg[G::PER], wk[G::PER];
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    const int i = threadIdx.x + k * kThreads;
+    const uint32_t inb = inside_bits<TZ, TY, TX>(i);
+    wk[k] = (uint32_t)mk[k] | (uint32_t)(up[k] & inb) << 16;
+    deg[k] = (uint32_t)__popc(mk[k] & inb);
+    W[i] = wk[k];
+    cnt[i] = (uint8_t)deg[k];
+    lvb[i] = 0;
+  }
+  __syncthreads();
+  // level 0: nothing below inside the tile, and something to do (a lower
+  // neighbour in the halo to raise from, or upper neighbours to release)
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    const bool go = deg[k] == 0 && wk[k] != 0;
+    const uint64_t rb = __ballot(go);
+    if (rb) {
+      uint32_t base = 0;
+      if (lane() == 0) base = atomicAdd(&kc[0], (uint32_t)__popcll(rb));
+      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+      if (go) list[base + lane_prefix(rb)] = (uint16_t)(threadIdx.x + k * kThreads);
+    }
+  }
+  __syncthreads();
+  int beg = 0, end = (int)kc[0], level = 0;
+  while (beg < end) {
+    const int nxt = (level + 1) % 3;
+    if (threadIdx.x == 0) kc[(level + 2) % 3] = 0;  // read two levels ago, appended next level
+    for (int e = beg + (int)threadIdx.x; e < end; e += kThreads) {
+      const int i = list[e];
+      const uint32_t w = W[i];
+      const uint32_t m = w & 0xffffu;
+      if (m) {
+        const int li = G::local(i);
+        const uint32_t cur = S[li];
+        const uint32_t b = raise_of<TZ, TY, TX>(S, li, m, cur);
+        if (b > cur) S[li] = b;
+      }
+      lvb[i] = (uint8_t)(level < 255 ? level : 255);
+      uint32_t u = w >> 16;
+      while (u) {
+        const int j = __builtin_ctz(u);
+        u &= u - 1;
+        const int q = i + own_off<TZ, TY, TX>(j);
+        const uint32_t sh = 8u * (uint32_t)(q & 3);
+        const uint32_t old = atomicSub(&cnt4[q >> 2], 1u << sh);
+        const bool ready = ((old >> sh) & 0xffu) == 1u;
+        const uint64_t rb = __ballot(ready);
+        if (rb) {
+          const int leader = __builtin_ctzll(rb);
+          uint32_t base = 0;
+          if (lane() == leader) base = atomicAdd(&kc[nxt], (uint32_t)__popcll(rb));
+          base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+          if (ready) list[end + base + lane_prefix(rb)] = (uint16_t)q;
+        }
+      }
+    }
+    __syncthreads();
+    beg = end;
+    end += (int)kc[nxt];
+    ++level;
+  }
+  return level;
+}
+
+// A later run of a tile: its points sorted by their kept levels (lv, 255 =
+// unknown), then raised level by level.  Levels of at most 64 points run on
+// wave 0 alone, with no block barrier between consecutive ones (a wave's
+// LDS accesses are ordered); a block barrier separates the rest.  Returns
+// the number of levels, or -1 (block-uniform) when some point's level is
+// unknown, before touching S.
+template <int TZ, int TY, int TX>
+__device__ int level_relax(uint32_t* S, const uint16_t* mk, const uint8_t* lv) {
+  using G = TileGeom<TZ, TY, TX>;
+  __shared__ uint32_t hist[257];
+  __shared__ uint32_t list[G::NPT];
+  for (int h = threadIdx.x; h < 257; h += kThreads) hist[h] = 0;
+  __syncthreads();
+  bool unknown = false;
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    if (mk[k]) {
+      if (lv[k] == 255) unknown = true;
+      else atomicAdd(&hist[lv[k]], 1u);
+    }
+  }
+  if (__syncthreads_or(unknown)) return -1;
+  if (threadIdx.x < 64) {
+    // exclusive scan of the 255 counts, four per lane; hist[256] = levels
+    uint32_t v[4], t = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = hist[4 * lane() + q];
+      t += v[q];
+    }
+    const uint32_t incl = wave_scan_u32(t);
+    uint32_t run = incl - t;
+    int top = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      hist[4 * lane() + q] = run;
+      run += v[q];
+      if (v[q]) top = 4 * lane() + q;
+    }
+    top = wave_reduce(top, OpMax{});
+    if (lane() == 0) hist[256] = (uint32_t)(top + 1);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < G::PER; ++k) {
+    if (mk[k]) {
+      const uint32_t pos = atomicAdd(&hist[lv[k]], 1u);
+      list[pos] = (uint32_t)(threadIdx.x + k * kThreads) | (uint32_t)mk[k] << 12;
+    }
+  }
+  __syncthreads();
+  // hist[l] is now the end of level l
+  const int nlev = (int)hist[256];
+  int beg = 0;
+  bool wide = false;
+  for (int l = 0; l < nlev; ++l) {
+    const int end = (int)hist[l];
+    const bool w = end - beg > 64;
+    if (w || wide) {
+      __syncthreads();
+      wide = false;
+    }
+    for (int e = beg + (int)threadIdx.x; e < end; e += kThreads) {
+      const uint32_t ent = list[e];
+      const int li = G::local((int)(ent & 4095u));
+      const uint32_t cur = S[li];
+      const uint32_t b = raise_of<TZ, TY, TX>(S, li, ent >> 12, cur);
+      if (b > cur) S[li] = b;
+    }
+    wide = wide || w;
+    beg = end;
+  }
+  __syncthreads();
+  return nlev;
+}
+
 // mark the neighbour tiles in `dirs` (27-bit set, see out_dirs) for sweep
 // `next`; one atomic per block adds the number of newly marked tiles to
 // counters[1 + next % 64]
@@ -686,7 +908,9 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
   using KB = typename std::conditional<K == 4, uint2, ulonglong2>::type;
   constexpr int NJ = TZ == 1 ? 6 : 14;  // 2D: only the in-plane offsets
   constexpr int kKB = G::H * (int)sizeof(KB);
-  constexpr int kBytes = kKB > G::H * 4 ? kKB : G::H * 4;
+  // the subbins of the halo, then (2D) the peeling state, reuse the buffer
+  constexpr int kS = G::H * 4 + (TZ == 1 ? KahnLds<TZ, TY, TX>::kBytes : 0);
+  constexpr int kBytes = kKB > kS ? kKB : kS;
   constexpr int HL = (G::H + kThreads - 1) / kThreads;  // halo loads per thread
   __shared__ __attribute__((aligned(16))) uint8_t buf[kBytes];
   KB* P = (KB*)buf;
@@ -780,7 +1004,13 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
   __syncthreads();
   for (int i = threadIdx.x; i < G::H; i += kThreads) S[i] = 0;
   __syncthreads();
-  relax<TZ, TY, TX>(S, mk, counters, itot, t);
+  uint8_t* lvb = nullptr;
+  if constexpr (TZ == 1) {
+    const int nlev = kahn_relax<TZ, TY, TX>(S, buf + G::H * 4, mk, up, lvb);
+    if (threadIdx.x == 0) atomicAdd(&itot[t % 64], (unsigned long long)(nlev + 1));
+  } else {
+    relax<TZ, TY, TX>(S, mk, counters, itot, t);
+  }
   uint32_t dirs = 0;
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
@@ -789,7 +1019,9 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
     const int z = c.z0 + iz, y = c.y0 + iy, xx = c.x0 + ix;
     if (z < box.nz && y < box.ny && xx < box.nx) {
       const uint32_t v = S[G::local(i)];
-      sub[((int64_t)z * box.ny + y) * box.nx + xx] = v;
+      const int64_t g = ((int64_t)z * box.ny + y) * box.nx + xx;
+      sub[g] = v;
+      if (TZ == 1 && tl.lev) tl.lev[g] = lvb[i];
       if (v && up[k]) dirs |= out_dirs<TZ, TY, TX>(i, up[k]);
     }
   }
@@ -830,7 +1062,9 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
 // With `blockers` given, thread 0 stores there the higher-index
 // neighbour tiles holding a same-bin lower neighbour of one of the tile's
 // points (the tiles its run depends on; bits 14..26 of the 27-direction set).
-template <int TZ, int TY, int TX, bool QM = false>
+// LV: a 2D tile relaxes in the order of the levels kept by the first pass
+// (tl.lev), if any and all known; otherwise relaxation passes.
+template <int TZ, int TY, int TX, bool QM = false, bool LV = false>
 __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16_t* __restrict__ mask,
                             uint32_t* __restrict__ sub, const uint32_t* stamp,
                             uint32_t* counters, unsigned long long* itot, uint32_t sweep,
@@ -881,7 +1115,21 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
     mk[k] = M[li];
     old[k] = S[li];
   }
-  relax<TZ, TY, TX>(S, mk, counters, itot, t);
+  int nlev = -1;
+  if constexpr (LV && TZ == 1) {
+    if (tl.lev) {
+      uint8_t lv[G::PER];
+#pragma unroll
+      for (int k = 0; k < G::PER; ++k) {
+        // a point with flags lies in the grid
+        const int i = threadIdx.x + k * kThreads;
+        lv[k] = mk[k] ? tl.lev[((int64_t)(c.y0 + i / TX)) * box.nx + c.x0 + i % TX] : 0;
+      }
+      nlev = level_relax<TZ, TY, TX>(S, mk, lv);
+    }
+  }
+  if (nlev < 0) relax<TZ, TY, TX>(S, mk, counters, itot, t);
+  else if (threadIdx.x == 0) atomicAdd(&itot[t % 64], (unsigned long long)(nlev + 1));
   uint32_t dirs = 0;
 #pragma unroll
   for (int k = 0; k < G::PER; ++k) {
@@ -929,7 +1177,7 @@ __global__ __launch_bounds__(kThreads) void k_repair(
     uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
     uint32_t sweep) {
   TileCoord c;
-  const uint32_t dirs = repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters,
+  const uint32_t dirs = repair_body<TZ, TY, TX, false, true>(box, tl, mask, sub, stamp, counters,
                                                 relax_total(counters), sweep,
                                                 xcd_tile(blockIdx.x, gridDim.x), c);
   if (dirs) mark_neighbours(dirs, c, tl, stamp, counters, sweep + 1);
@@ -952,7 +1200,7 @@ __device__ __noinline__ uint32_t sweep_run(Box box, Tiling tl, const uint16_t* _
                                            uint32_t* __restrict__ sub, const uint32_t* stamp,
                                            uint32_t* counters, uint32_t sweep, uint32_t t) {
   TileCoord c;
-  return repair_body<TZ, TY, TX>(box, tl, mask, sub, stamp, counters, relax_total(counters),
+  return repair_body<TZ, TY, TX, false, true>(box, tl, mask, sub, stamp, counters, relax_total(counters),
                                  sweep, t, c);
 }
 
@@ -995,7 +1243,7 @@ __device__ __noinline__ uint32_t repair_run(Box box, Tiling tl, const uint16_t* 
                                             uint32_t* __restrict__ sub, uint32_t* counters,
                                             uint32_t t, uint32_t* blockers) {
   TileCoord c;
-  return repair_body<TZ, TY, TX, true>(box, tl, mask, sub, nullptr, counters,
+  return repair_body<TZ, TY, TX, true, true>(box, tl, mask, sub, nullptr, counters,
                                        relax_total(counters), 0, t, c, blockers);
 }
 
