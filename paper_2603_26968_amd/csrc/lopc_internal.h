@@ -290,6 +290,10 @@ int repair_q_blocks_per_cu(int sid);
 // may be null); q (may be null): its repair queue.
 hipError_t launch_report(const Params* prm, const RepairQueue* q, uint64_t* d_size,
                          int32_t* d_status, hipStream_t s);
+// One host-driven sweep: the tiles marked for `sweep`, in two launches by
+// tile colour (checkerboard), so that a tile of the second colour sees the
+// changes of its face neighbours in the same sweep.  Ev: start of the first
+// launch, end of the second.
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask,
                          uint32_t* sub, uint32_t* stamp, uint32_t* counters,
                          uint32_t sweep, hipStream_t s, Ev ev = {});

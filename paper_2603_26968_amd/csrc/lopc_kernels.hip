@@ -1171,16 +1171,62 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
   return block_or32(dirs);
 }
 
+// Colour of a tile: the parity of the sum of its tile coordinates (a
+// checkerboard: the six face neighbours have the other colour).
+__device__ __forceinline__ uint32_t tile_colour(int tz, int ty, int tx) {
+  return (uint32_t)((tz + ty + tx) & 1);
+}
+
+// mark_neighbours for a sweep run colour by colour: a neighbour of the later
+// colour runs later in this same sweep (it is marked for `sweep`), others in
+// the next sweep (marked for sweep + 1; a neighbour of the same colour may
+// run in this same launch and have read the halo already); newly marked
+// tiles are counted in counters[1 + s % 64] of their sweep s
+__device__ void mark_neighbours_col(uint32_t dirs, const TileCoord& c, const Tiling& tl,
+                                    uint32_t* stamp, uint32_t* counters, uint32_t sweep,
+                                    uint32_t colour) {
+  bool now = false, later = false;
+  if (threadIdx.x < 27 && ((dirs >> threadIdx.x) & 1u)) {
+    const int dz = (int)threadIdx.x / 9 - 1, dy = ((int)threadIdx.x / 3) % 3 - 1,
+              dx = (int)threadIdx.x % 3 - 1;
+    const int nz = c.tz + dz, ny = c.ty + dy, nx = c.tx + dx;
+    if ((dz | dy | dx) != 0 && nz >= 0 && nz < tl.ntz && ny >= 0 && ny < tl.nty && nx >= 0 &&
+        nx < tl.ntx) {
+      const uint32_t u = ((uint32_t)nz * tl.nty + ny) * tl.ntx + nx;
+      const uint32_t next = tile_colour(nz, ny, nx) > colour ? sweep : sweep + 1;
+      const bool newly = atomicMax(&stamp[u], next) < next;
+      now = newly && next == sweep;
+      later = newly && next != sweep;
+    }
+  }
+  if (threadIdx.x < 64) {
+    const uint64_t a = __ballot(now), b = __ballot(later);
+    if (threadIdx.x == 0 && a) atomicAdd(&counters[1 + (sweep & 63)], (uint32_t)__popcll(a));
+    if (threadIdx.x == 0 && b)
+      atomicAdd(&counters[1 + ((sweep + 1) & 63)], (uint32_t)__popcll(b));
+  }
+}
+
+// One colour of a sweep: the tiles of colour `colour` marked for this sweep
+// run.  A sweep runs colour 0, then colour 1, so a tile of colour 1 sees
+// what its face neighbours changed earlier in the same sweep.  Block b takes
+// the (b mod hx)-th tile of that colour in row b / hx (hx = half a row of
+// tiles, rounded up; the last block of a row may have none).
 template <int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_repair(
     Box box, Tiling tl, const uint16_t* __restrict__ mask,
     uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
-    uint32_t sweep) {
+    uint32_t sweep, uint32_t colour) {
+  const uint32_t hx = (uint32_t)(tl.ntx + 1) / 2;
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t row = b / hx, tz = row / (uint32_t)tl.nty, ty = row % (uint32_t)tl.nty;
+  const uint32_t tx = ((colour + tz + ty) & 1u) + 2 * (b % hx);
+  if (tx >= (uint32_t)tl.ntx) return;
+  const uint32_t t = (tz * tl.nty + ty) * tl.ntx + tx;
   TileCoord c;
   const uint32_t dirs = repair_body<TZ, TY, TX, false, true>(box, tl, mask, sub, stamp, counters,
-                                                relax_total(counters), sweep,
-                                                xcd_tile(blockIdx.x, gridDim.x), c);
-  if (dirs) mark_neighbours(dirs, c, tl, stamp, counters, sweep + 1);
+                                                relax_total(counters), sweep, t, c);
+  if (dirs) mark_neighbours_col(dirs, c, tl, stamp, counters, sweep, colour);
 }
 
 // Device-driven repair of a single field: a persistent grid takes tiles from
@@ -1585,9 +1631,13 @@ int repair_q_blocks_per_cu(int sid) {
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
                          uint32_t* stamp, uint32_t* counters, uint32_t sweep,
                          hipStream_t s, Ev ev) {
-  const dim3 g(t.ntiles), b(kThreads);
-  LOPC_WITH_TILE(t, launch_ev(k_repair<TZ, TY, TX>, g, b, s, ev, box, t, mask, sub, stamp,
-                              counters, sweep));
+  // both colours; the events bracket the whole sweep
+  const uint32_t n = (uint32_t)t.ntz * (uint32_t)t.nty * (uint32_t)((t.ntx + 1) / 2);
+  for (uint32_t col = 0; col < 2; ++col) {
+    Ev e{col == 0 ? ev.a : nullptr, col == 1 ? ev.b : nullptr};
+    LOPC_WITH_TILE(t, launch_ev(k_repair<TZ, TY, TX>, dim3(n), dim3(kThreads), s, e, box, t,
+                                mask, sub, stamp, counters, sweep, col));
+  }
   return hipGetLastError();
 }
 
