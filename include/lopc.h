@@ -285,9 +285,18 @@ int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void
  *   LOPC_OPT_TILE_2D       tile of 2D fields: 0 (default) 32 x 64,
  *                          1: 16 x 128.
  *                          Neither the result nor the workspace size
- *                          (the largest over the shapes) depends on them. */
+ *                          (the largest over the shapes) depends on them.
+ *   LOPC_OPT_SWEEP_ORDER   order of the tiles in the host-driven sweeps of
+ *                          the single-field repair: 0 (default) as 1 for a
+ *                          field of at least 32768 tiles, else as 2;
+ *                          1: checkerboard (the first pass and every sweep
+ *                          run the tiles of one colour, then the other, so
+ *                          that the second sees the first's changes);
+ *                          2: all tiles in one launch.  The result does not
+ *                          depend on it. */
 enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT = 3,
-       LOPC_OPT_REPAIR = 4, LOPC_OPT_TILE_3D = 5, LOPC_OPT_TILE_2D = 6 };
+       LOPC_OPT_REPAIR = 4, LOPC_OPT_TILE_3D = 5, LOPC_OPT_TILE_2D = 6,
+       LOPC_OPT_SWEEP_ORDER = 7 };
 enum { LOPC_REPAIR_AUTO = 0, LOPC_REPAIR_HYBRID = 1, LOPC_REPAIR_QUEUE = 2,
        LOPC_REPAIR_SWEEPS = 3 };
 int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value);

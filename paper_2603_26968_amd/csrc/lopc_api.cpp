@@ -73,6 +73,7 @@ int lopc_ctx_create(int hip_device, lopc_ctx** out) {
   c->persist_pct = 0;
   c->sweep_hint = 4;
   c->repair_mode = LOPC_REPAIR_AUTO;
+  c->sweep_order = 0;
   for (int i = 0; i < kTileShapes; ++i) c->rq_per_cu[i] = c->sl_per_cu[i] = 0;
   c->tile2 = 0;
   c->tile3 = 0;
@@ -282,6 +283,7 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   const uint64_t nch = (s.n + W - 1) / W;
   Tiling tl = make_tiling(s.box, ctx->tile2, ctx->tile3);
   if (s.box.nz == 1) tl.lev = ws + L.lev;
+  tl.coloured = ctx->sweep_order == 1 || (ctx->sweep_order == 0 && tl.ntiles >= kColourMinTiles);
   const int rmode = ctx->repair_mode;
   QueueRef Q{};
   {
@@ -377,7 +379,8 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     // many tiles a few times per tile instead of once per sweep
     HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
                               (uint16_t*)(ws + L.mask), sub, stamp, counters, nullptr,
-                              QueueRef{}, hs, ev_only(ctx, LOPC_PHASE_QUANT)));
+                              QueueRef{}, hs, ev_only(ctx, LOPC_PHASE_QUANT),
+                              tl.coloured != 0));
     const uint64_t limit = rmode == LOPC_REPAIR_AUTO ? kAutoSweeps : s.n + 2;
     rc = repair_by_sweeps(ctx, s, L, dtype, ws, d_stream, stream_cap, tl, h_stats != nullptr,
                           hs, limit, &sweeps, &active);

@@ -679,6 +679,10 @@ int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value) {
       if (value < LOPC_REPAIR_AUTO || value > LOPC_REPAIR_SWEEPS) return LOPC_E_ARG;
       ctx->repair_mode = (int)value;
       return LOPC_OK;
+    case LOPC_OPT_SWEEP_ORDER:
+      if (value < 0 || value > 2) return LOPC_E_ARG;
+      ctx->sweep_order = (int)value;
+      return LOPC_OK;
     default:
       return LOPC_E_ARG;
   }
@@ -693,6 +697,7 @@ int lopc_ctx_get_option(lopc_ctx* ctx, int option, int64_t* h_value) {
     case LOPC_OPT_TILE_2D: *h_value = ctx->tile2; return LOPC_OK;
     case LOPC_OPT_TILE_3D: *h_value = ctx->tile3; return LOPC_OK;
     case LOPC_OPT_REPAIR: *h_value = ctx->repair_mode; return LOPC_OK;
+    case LOPC_OPT_SWEEP_ORDER: *h_value = ctx->sweep_order; return LOPC_OK;
     default: return LOPC_E_ARG;
   }
 }

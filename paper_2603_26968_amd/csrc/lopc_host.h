@@ -49,6 +49,7 @@ struct lopc_ctx {
   double ms[LOPC_PHASES];
   int sweep_hint;      // single field: repair sweeps enqueued before the first read
   int repair_mode;     // single field: LOPC_REPAIR_HYBRID, _QUEUE or _SWEEPS
+  int sweep_order;     // single field, host-driven sweeps: LOPC_OPT_SWEEP_ORDER
   int rq_per_cu[lopc::kTileShapes];  // resident repair-queue workgroups per CU, per tile shape
   int sl_per_cu[lopc::kTileShapes];  // resident list-sweep workgroups per CU, per tile shape
   int tile2, tile3;    // tile shape indices (kTile2 / kTile3)
@@ -121,6 +122,7 @@ inline Tiling make_tiling(const Box& b, int t2, int t3) {
   t.ntx = (b.nx + t.tx - 1) / t.tx;
   t.ntiles = (uint32_t)t.ntz * t.nty * t.ntx;
   t.lev = nullptr;
+  t.coloured = 0;
   return t;
 }
 

@@ -68,6 +68,7 @@ struct Tiling {
   uint8_t* lev;           // per point of a 2D field: its level inside its
                           // tile (255: unknown), kept by the first pass;
                           // null: not kept
+  int32_t coloured;       // host-driven sweeps in checkerboard order
 };
 
 // Run the statements after t with TZ, TY, TX the compile-time extents of
@@ -264,11 +265,13 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
 // Q.q null: marks tiles for host-driven sweeps (launch_repair); else lists
 // them in the repair queue drained by launch_repair_q.
 // lists (may be null): the marked tiles are also appended to the work list
-// of sweep 1.
+// of sweep 1.  coloured (host-driven sweeps only): two launches, the tiles
+// of the second checkerboard colour taking the results of the first as
+// their halo.
 hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
                         uint32_t* counters, uint32_t* lists, const QueueRef& Q, hipStream_t s,
-                        Ev ev = {});
+                        Ev ev = {}, bool coloured = false);
 // One sweep over the work list of sweep `sweep` (lists: two arrays of
 // t.ntiles items, sweep parity), appending the tiles it marks to the list
 // of the next sweep; a persistent grid of `grid` workgroups drains the list.
@@ -290,10 +293,16 @@ int repair_q_blocks_per_cu(int sid);
 // may be null); q (may be null): its repair queue.
 hipError_t launch_report(const Params* prm, const RepairQueue* q, uint64_t* d_size,
                          int32_t* d_status, hipStream_t s);
-// One host-driven sweep: the tiles marked for `sweep`, in two launches by
-// tile colour (checkerboard), so that a tile of the second colour sees the
-// changes of its face neighbours in the same sweep.  Ev: start of the first
-// launch, end of the second.
+// Host-driven sweeps of a field with many tiles run in checkerboard order
+// by default (two launches per sweep and for the first pass: fewer sweeps
+// and tile runs); on smaller fields the second launch costs more than it
+// saves.
+constexpr uint32_t kColourMinTiles = 32768;
+
+// One host-driven sweep: the tiles marked for `sweep`; with t.coloured,
+// in two launches by tile colour (checkerboard), so that a tile of the
+// second colour sees the changes of its face and corner neighbours in the
+// same sweep.  Ev: start of the first launch, end of the last.
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask,
                          uint32_t* sub, uint32_t* stamp, uint32_t* counters,
                          uint32_t sweep, hipStream_t s, Ev ev = {});

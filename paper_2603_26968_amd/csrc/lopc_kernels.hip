@@ -253,6 +253,34 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
   return x * per + (x < rem ? x : rem) + (b >> 3);
 }
 
+// Colour of a tile: the parity of the sum of its tile coordinates (a
+// checkerboard: face and corner neighbours have the other colour, edge
+// neighbours the same).
+__device__ __forceinline__ uint32_t tile_colour(int tz, int ty, int tx) {
+  return (uint32_t)((tz + ty + tx) & 1);
+}
+
+// neighbour directions (27-direction set, bit (dz+1)*9 + (dy+1)*3 + dx+1)
+// towards a tile of the same colour: two nonzero offsets
+constexpr uint32_t same_colour_dirs() {
+  uint32_t m = 0;
+  for (int d = 0; d < 27; ++d) {
+    const int nz = (d / 9 != 1) + ((d / 3) % 3 != 1) + (d % 3 != 1);
+    if (nz == 2) m |= 1u << d;
+  }
+  return m;
+}
+
+// Tile of block b in a launch over the tiles of one colour: the (b mod hx)-th
+// tile of that colour in tile row b / hx (hx: half a row, rounded up); none
+// (ntiles) for the last block of a row that has one tile fewer.
+__device__ __forceinline__ uint32_t colour_tile(uint32_t b, uint32_t colour, const Tiling& tl) {
+  const uint32_t hx = (uint32_t)(tl.ntx + 1) / 2;
+  const uint32_t row = b / hx, tz = row / (uint32_t)tl.nty, ty = row % (uint32_t)tl.nty;
+  const uint32_t tx = ((colour + tz + ty) & 1u) + 2 * (b % hx);
+  return tx < (uint32_t)tl.ntx ? (tz * tl.nty + ty) * tl.ntx + tx : tl.ntiles;
+}
+
 struct TileCoord {
   int tz, ty, tx, z0, y0, x0;
 };
@@ -898,7 +926,7 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
                            Tiling tl, Params* prm, typename Traits<K>::Bin* __restrict__ bins,
                            uint16_t* __restrict__ mask, uint32_t* __restrict__ sub,
                            uint32_t* counters, unsigned long long* itot, uint32_t t,
-                           TileCoord& c) {
+                           TileCoord& c, int hc = -1) {
   using Tr = Traits<K>;
   using G = TileGeom<TZ, TY, TX>;
   using Key = typename Tr::Bin;  // keys fit the signed type of the bins
@@ -1002,7 +1030,21 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
     up[k] = (uint16_t)(sm & ~lm);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < G::H; i += kThreads) S[i] = 0;
+  // halo subbins: 0, or (hc >= 0) those of the neighbour tiles of colour hc,
+  // final from an earlier launch
+  for (int i = threadIdx.x; i < G::H; i += kThreads) {
+    uint32_t v = 0;
+    if (hc >= 0) {
+      const int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+      const int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
+      const bool own = hz >= G::ZO && hz < G::ZO + TZ && hy >= 1 && hy <= TY && hx >= 1 &&
+                       hx <= TX;
+      if (!own && z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx &&
+          tile_colour(z / TZ, y / TY, xx / TX) == (uint32_t)hc)
+        v = sub[((int64_t)z * box.ny + y) * box.nx + xx];
+    }
+    S[i] = v;
+  }
   __syncthreads();
   uint8_t* lvb = nullptr;
   if constexpr (TZ == 1) {
@@ -1036,11 +1078,17 @@ __global__ __launch_bounds__(kThreads) void k_tile0(
     const typename Traits<K>::Raw* __restrict__ x, Box box, Tiling tl, Params* prm,
     typename Traits<K>::Bin* __restrict__ bins,
     uint16_t* __restrict__ mask, uint32_t* __restrict__ sub, uint32_t* stamp,
-    uint32_t* counters, uint32_t* lists, QueueRef Q) {
+    uint32_t* counters, uint32_t* lists, QueueRef Q, uint32_t colour) {
   TileCoord c;
-  const uint32_t dirs = tile0_body<K, TZ, TY, TX>(x, box, tl, prm, bins, mask, sub, counters,
-                                                  relax_total(counters),
-                                                  xcd_tile(blockIdx.x, gridDim.x), c);
+  // colour 2: every tile; 0 / 1: the tiles of that colour, those of colour 1
+  // taking the subbins of their neighbours of colour 0 as halo
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t t = colour < 2 ? colour_tile(b, colour, tl) : b;
+  if (t >= tl.ntiles) return;
+  uint32_t dirs = tile0_body<K, TZ, TY, TX>(x, box, tl, prm, bins, mask, sub, counters,
+                                            relax_total(counters), t, c, colour == 1 ? 0 : -1);
+  // tiles of colour 1 read the results of colour 0 in the next launch
+  if (colour == 0) dirs &= same_colour_dirs();
   if (Q.q) {
     if (threadIdx.x < 27 && ((dirs >> threadIdx.x) & 1u) && dir_inside((int)threadIdx.x, c, tl))
       q_push(Q, dir_tile((int)threadIdx.x, c, tl, 0), 1);
@@ -1171,16 +1219,10 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
   return block_or32(dirs);
 }
 
-// Colour of a tile: the parity of the sum of its tile coordinates (a
-// checkerboard: the six face neighbours have the other colour).
-__device__ __forceinline__ uint32_t tile_colour(int tz, int ty, int tx) {
-  return (uint32_t)((tz + ty + tx) & 1);
-}
-
 // mark_neighbours for a sweep run colour by colour: a neighbour of the later
 // colour runs later in this same sweep (it is marked for `sweep`), others in
-// the next sweep (marked for sweep + 1; a neighbour of the same colour may
-// run in this same launch and have read the halo already); newly marked
+// the next sweep (marked for sweep + 1; an edge neighbour has the same colour
+// and may have read the halo already in this same launch); newly marked
 // tiles are counted in counters[1 + s % 64] of their sweep s
 __device__ void mark_neighbours_col(uint32_t dirs, const TileCoord& c, const Tiling& tl,
                                     uint32_t* stamp, uint32_t* counters, uint32_t sweep,
@@ -1207,26 +1249,24 @@ __device__ void mark_neighbours_col(uint32_t dirs, const TileCoord& c, const Til
   }
 }
 
-// One colour of a sweep: the tiles of colour `colour` marked for this sweep
-// run.  A sweep runs colour 0, then colour 1, so a tile of colour 1 sees
-// what its face neighbours changed earlier in the same sweep.  Block b takes
-// the (b mod hx)-th tile of that colour in row b / hx (hx = half a row of
-// tiles, rounded up; the last block of a row may have none).
+// One sweep (colour 2: every tile) or one colour of a sweep: the tiles of
+// colour `colour` marked for this sweep run.  A coloured sweep runs colour
+// 0, then colour 1, so a tile of colour 1 sees what its face and corner
+// neighbours changed earlier in the same sweep.
 template <int TZ, int TY, int TX>
 __global__ __launch_bounds__(kThreads) void k_repair(
     Box box, Tiling tl, const uint16_t* __restrict__ mask,
     uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
     uint32_t sweep, uint32_t colour) {
-  const uint32_t hx = (uint32_t)(tl.ntx + 1) / 2;
   const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t row = b / hx, tz = row / (uint32_t)tl.nty, ty = row % (uint32_t)tl.nty;
-  const uint32_t tx = ((colour + tz + ty) & 1u) + 2 * (b % hx);
-  if (tx >= (uint32_t)tl.ntx) return;
-  const uint32_t t = (tz * tl.nty + ty) * tl.ntx + tx;
+  const uint32_t t = colour < 2 ? colour_tile(b, colour, tl) : b;
+  if (t >= tl.ntiles) return;
   TileCoord c;
   const uint32_t dirs = repair_body<TZ, TY, TX, false, true>(box, tl, mask, sub, stamp, counters,
                                                 relax_total(counters), sweep, t, c);
-  if (dirs) mark_neighbours_col(dirs, c, tl, stamp, counters, sweep, colour);
+  if (!dirs) return;
+  if (colour < 2) mark_neighbours_col(dirs, c, tl, stamp, counters, sweep, colour);
+  else mark_neighbours(dirs, c, tl, stamp, counters, sweep + 1);
 }
 
 // Device-driven repair of a single field: a persistent grid takes tiles from
@@ -1548,16 +1588,23 @@ hipError_t launch_params(int dtype, int mode, double eb, const double* part,
 hipError_t launch_tile0(int dtype, const void* x, Box box, Tiling t, Params* prm, void* bins,
                         uint16_t* mask, uint32_t* sub, uint32_t* stamp,
                         uint32_t* counters, uint32_t* lists, const QueueRef& Q, hipStream_t s,
-                        Ev ev) {
-  const dim3 g(t.ntiles), b(kThreads);
-  LOPC_WITH_TILE(t, {
-    if (dtype == 0)
-      launch_ev(k_tile0<4, TZ, TY, TX>, g, b, s, ev, (const uint32_t*)x, box, t, prm,
-                (int32_t*)bins, mask, sub, stamp, counters, lists, Q);
-    else
-      launch_ev(k_tile0<8, TZ, TY, TX>, g, b, s, ev, (const uint64_t*)x, box, t, prm,
-                (int64_t*)bins, mask, sub, stamp, counters, lists, Q);
-  });
+                        Ev ev, bool coloured) {
+  const int nl = coloured ? 2 : 1;
+  const dim3 b(kThreads);
+  const dim3 g(coloured ? (uint32_t)t.ntz * (uint32_t)t.nty * (uint32_t)((t.ntx + 1) / 2)
+                        : t.ntiles);
+  for (int l = 0; l < nl; ++l) {
+    const Ev e{l == 0 ? ev.a : nullptr, l == nl - 1 ? ev.b : nullptr};
+    const uint32_t col = coloured ? (uint32_t)l : 2u;
+    LOPC_WITH_TILE(t, {
+      if (dtype == 0)
+        launch_ev(k_tile0<4, TZ, TY, TX>, g, b, s, e, (const uint32_t*)x, box, t, prm,
+                  (int32_t*)bins, mask, sub, stamp, counters, lists, Q, col);
+      else
+        launch_ev(k_tile0<8, TZ, TY, TX>, g, b, s, e, (const uint64_t*)x, box, t, prm,
+                  (int64_t*)bins, mask, sub, stamp, counters, lists, Q, col);
+    });
+  }
   return hipGetLastError();
 }
 
@@ -1631,12 +1678,15 @@ int repair_q_blocks_per_cu(int sid) {
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
                          uint32_t* stamp, uint32_t* counters, uint32_t sweep,
                          hipStream_t s, Ev ev) {
-  // both colours; the events bracket the whole sweep
-  const uint32_t n = (uint32_t)t.ntz * (uint32_t)t.nty * (uint32_t)((t.ntx + 1) / 2);
-  for (uint32_t col = 0; col < 2; ++col) {
-    Ev e{col == 0 ? ev.a : nullptr, col == 1 ? ev.b : nullptr};
+  // both colours, or every tile at once; the events bracket the sweep
+  const bool col2 = t.coloured != 0;
+  const uint32_t n =
+      col2 ? (uint32_t)t.ntz * (uint32_t)t.nty * (uint32_t)((t.ntx + 1) / 2) : t.ntiles;
+  const uint32_t nl = col2 ? 2 : 1;
+  for (uint32_t l = 0; l < nl; ++l) {
+    Ev e{l == 0 ? ev.a : nullptr, l == nl - 1 ? ev.b : nullptr};
     LOPC_WITH_TILE(t, launch_ev(k_repair<TZ, TY, TX>, dim3(n), dim3(kThreads), s, e, box, t,
-                                mask, sub, stamp, counters, sweep, col));
+                                mask, sub, stamp, counters, sweep, col2 ? l : 2u));
   }
   return hipGetLastError();
 }

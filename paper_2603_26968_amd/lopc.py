@@ -35,7 +35,7 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_ctx_last_batch_headers", "lopc_batch_autotune", "lopc_verify",
            "lopc_verify_workspace_size", "lopc_decompress_static")
 LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT, LOPC_OPT_REPAIR = 1, 2, 3, 4
-LOPC_OPT_TILE_3D, LOPC_OPT_TILE_2D = 5, 6
+LOPC_OPT_TILE_3D, LOPC_OPT_TILE_2D, LOPC_OPT_SWEEP_ORDER = 5, 6, 7
 LOPC_REPAIR_AUTO, LOPC_REPAIR_HYBRID, LOPC_REPAIR_QUEUE, LOPC_REPAIR_SWEEPS = 0, 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
