@@ -56,9 +56,13 @@ def counters(path, copy=None):
     factor = {}
     if copy:
         cname_k, nbytes = copy[0], float(copy[1])
+        # the copy is the matching kernel with the largest reading (other
+        # element-wise kernels of the run move little)
+        best = {}
         for (kname, cname), v in per.items():
-            if cname_k in kname and v > 0:
-                factor[cname] = nbytes / v
+            if cname_k in kname and v > best.get(cname, 0.0):
+                best[cname] = v
+        factor = {c: nbytes / v for c, v in best.items()}
     print(f"{'kernel':60s} {'counter':>12s} {'avg/dispatch':>14s} {'scaled_bytes':>14s}")
     for (kname, cname), v in sorted(per.items()):
         sc = f"{v * factor[cname]:14.0f}" if cname in factor else f"{'':>14s}"
