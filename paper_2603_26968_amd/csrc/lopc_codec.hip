@@ -1086,7 +1086,10 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
   const uint32_t rsize = ((const uint32_t*)(stream + kHeaderBytes))[c];
   const uint64_t roff = offsets[c];
   if (threadIdx.x == 0) s_bad = 0;
-  if (__syncthreads_or(threadIdx.x == 0 && (prm->status & ST_FORMAT))) return;
+  __shared__ uint32_t s_fail;
+  if (threadIdx.x == 0) s_fail = prm->status & ST_FORMAT;
+  __syncthreads();
+  if (s_fail) return;
   const uint8_t* rec = stream + body + roff;
   if (rsize < kRecordHeaderBytes || (rsize & 3)) {
     if (threadIdx.x == 0) set_status(prm, ST_FORMAT);

@@ -418,12 +418,19 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
     my_pt = wl_pt[wave() * 64 + lane()];
     my_cd = wl_cd[wave() * 64 + lane()];
   }
-  // slots: neighbour code of each owned point, fixed for the call (unused
-  // when the wave is listed); slot k lies kSlot LDS words after slot 0
+  // slot k of this thread lies kSlot LDS words after slot 0
   const int li0 = G::local(threadIdx.x);
+  // whether any point rose in pass p: flag[p % 3], set by the waves that
+  // raised one, read by all after the pass's barrier; thread 0 clears
+  // flag[(p + 1) % 3] during pass p (last read after the barrier of pass
+  // p - 2, next set in pass p + 1), so one barrier per pass suffices
+  __shared__ uint32_t flag[3];
+  if (threadIdx.x < 3) flag[threadIdx.x] = 0;
+  __syncthreads();
   int iters = 0;
   for (;;) {
     int changed = 0;
+    if (threadIdx.x == 0) flag[(iters + 1) % 3] = 0;
     if (listed) {
       if (my_pt && step((int)(my_pt & 4095u), my_pt >> 12, my_cd)) changed = 1;
     } else {
@@ -457,7 +464,9 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
         }
       }
     }
-    if (!__syncthreads_or(changed)) break;
+    if (__ballot(changed) && lane() == 0) flag[iters % 3] = 1;
+    __syncthreads();
+    if (!flag[iters % 3]) break;
     if (++iters > G::NPT + 2) {  // unreachable: the order inside a tile is acyclic
       if (threadIdx.x == 0) atomicOr(&counters[0], 1u);
       break;
@@ -1123,7 +1132,12 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
   __shared__ uint16_t M[G::H];  // flags of the halo and the owned points
   // one read decides for the whole block (a neighbour may raise the stamp
   // concurrently)
-  if (!QM && !__syncthreads_or(threadIdx.x == 0 && stamp[t] >= sweep)) return 0;
+  if constexpr (!QM) {
+    __shared__ uint32_t go;
+    if (threadIdx.x == 0) go = stamp[t] >= sweep;
+    __syncthreads();
+    if (!go) return 0;
+  }
   c = tile_coord<TZ, TY, TX>(t, tl);
   constexpr int HL = (G::H + kThreads - 1) / kThreads;
   {
