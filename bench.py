@@ -518,6 +518,15 @@ def bench_batch(args):
         P.decompress_batch(streams, outs=ys, headers=hdrs)
         return streams, st
 
+    # the autotuner picks the grid mode and the repair tile shapes of this
+    # batch (kept in the context for the timed steps)
+    t0 = time.perf_counter()
+    pct = P.autotune_compress_batch(xs, ebs, "noa", out=out, ctx=ctx, reps=1)
+    tuned = {"persist_pct": pct,
+             "tile_2d": lopc.kTile2Names[lopc.lopc_ctx_get_option(ctx, lopc.LOPC_OPT_TILE_2D)],
+             "tile_3d": lopc.kTile3Names[lopc.lopc_ctx_get_option(ctx, lopc.LOPC_OPT_TILE_3D)],
+             "tuning_s": round(time.perf_counter() - t0, 2)}
+    _log("autotuned", tuned)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -566,6 +575,7 @@ def bench_batch(args):
         "one_call_per_field_GBps": round(nbytes / t_single / 1e9, 2),
         "hbm_frac_algorithmic": round(2 * (nbytes + S) / (tc + td) / 1e9 / HBM_PEAK_GBPS, 4),
         "identity_batch_vs_single": ident,
+        "autotuned": tuned,
     }
     if not args.no_cpu_baseline:
         from concurrent.futures import ProcessPoolExecutor

@@ -36,6 +36,9 @@ EXPORTS = ("lopc_ctx_create", "lopc_ctx_destroy", "lopc_compress_bound",
            "lopc_verify_workspace_size", "lopc_decompress_static")
 LOPC_OPT_BATCH_GRAPH, LOPC_OPT_GRAPH_SWEEPS, LOPC_OPT_PERSIST_PCT, LOPC_OPT_REPAIR = 1, 2, 3, 4
 LOPC_OPT_TILE_3D, LOPC_OPT_TILE_2D, LOPC_OPT_SWEEP_ORDER = 5, 6, 7
+# the repair tile shapes behind LOPC_OPT_TILE_2D / _3D values (z x y x x)
+kTile2Names = ("1x32x64", "1x16x128")
+kTile3Names = ("4x8x32", "8x8x32", "8x16x16")
 LOPC_REPAIR_AUTO, LOPC_REPAIR_HYBRID, LOPC_REPAIR_QUEUE, LOPC_REPAIR_SWEEPS = 0, 1, 2, 3
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
