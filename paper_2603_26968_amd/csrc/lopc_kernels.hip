@@ -446,18 +446,8 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
         if (!m) continue;
         const int li = li0 + k * G::kSlot;
         const uint32_t cur = S[li];
-        uint32_t best = cur;
-        if (__ballot(__popc(m) > 3)) {
-          best = dense_best<NJ, G::HX, G::HY * G::HX>(S, li, m, cur);
-        } else {
-          uint32_t mm = m;
-          while (mm) {
-            const int j = __builtin_ctz(mm);
-            mm &= mm - 1;
-            const uint32_t c = S[li + off_lin(j, G::HX, G::HY * G::HX)] + ((j & 1) ? 0u : 1u);
-            best = c > best ? c : best;
-          }
-        }
+        // every stencil neighbour at once (one LDS round trip), masked
+        const uint32_t best = dense_best<NJ, G::HX, G::HY * G::HX>(S, li, m, cur);
         if (best > cur) {
           S[li] = best;
           changed = 1;
