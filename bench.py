@@ -416,32 +416,34 @@ def bench_repair_study(args):
     """The single-field repair schedulers side by side (LOPC_OPT_REPAIR):
     for each field and scheduler, the median repair-phase time (library
     dispatch events), the compress time, sweeps, tile runs, queue runs and
-    parks; the streams of all schedulers of a field must be identical."""
+    parks (for the point worklists: iterations and listed points); the
+    streams of all schedulers of a field must be identical."""
     import torch
 
     import paper_2603_26968_amd as P
     from paper_2603_26968_amd import lopc, synth
     modes = {"sweeps": lopc.LOPC_REPAIR_SWEEPS, "hybrid": lopc.LOPC_REPAIR_HYBRID,
-             "queue": lopc.LOPC_REPAIR_QUEUE, "auto": lopc.LOPC_REPAIR_AUTO}
+             "queue": lopc.LOPC_REPAIR_QUEUE, "auto": lopc.LOPC_REPAIR_AUTO,
+             "points": lopc.LOPC_REPAIR_POINTS}
 
     def chain(n):
         return (np.arange(n, 0, -1, dtype=np.float64) / n).astype(np.float32).reshape(1, n)
 
     cases = [
         ("turb3d 256^3 f32 NOA 1e-3", lambda: synth.turbulence_field(), 1e-3, "noa", 5,
-         ("sweeps", "hybrid", "queue", "auto")),
+         ("sweeps", "hybrid", "queue", "points", "auto")),
         ("turb3d 256^3 f32 NOA 1e-2", lambda: synth.turbulence_field(), 1e-2, "noa", 5,
-         ("sweeps", "hybrid", "queue", "auto")),
+         ("sweeps", "hybrid", "queue", "points", "auto")),
         ("turb3d 256^3 f32 NOA 1e0", lambda: synth.turbulence_field(), 1.0, "noa", 3,
-         ("sweeps", "hybrid", "queue", "auto")),
+         ("sweeps", "hybrid", "queue", "points", "auto")),
         ("fronts2d 1800x3600 f32 NOA 1e-3", lambda: synth.fronts_field(), 1e-3, "noa", 5,
-         ("sweeps", "hybrid", "queue", "auto")),
+         ("sweeps", "hybrid", "queue", "points", "auto")),
         ("smooth2d 512^2 f32 NOA 1e-3", lambda: synth.smooth_field(), 1e-3, "noa", 5,
-         ("sweeps", "hybrid", "queue", "auto")),
+         ("sweeps", "hybrid", "queue", "points", "auto")),
         ("lognormal3d 512^3 f64 NOA 1e-3", lambda: synth.lognormal_field(), 1e-3, "noa", 3,
-         ("sweeps", "hybrid", "queue", "auto")),
+         ("sweeps", "hybrid", "queue", "points", "auto")),
         ("falling chain (1, 2^16) f32 ABS 10", lambda: chain(1 << 16), 10.0, "abs", 2,
-         ("sweeps", "queue", "auto")),
+         ("sweeps", "queue", "points", "auto")),
         ("falling chain (1, 2^20) f32 ABS 10", lambda: chain(1 << 20), 10.0, "abs", 1,
          ("queue", "auto")),
     ]

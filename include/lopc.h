@@ -277,7 +277,18 @@ int lopc_batch_autotune(lopc_ctx* ctx, int op, int n, const lopc_job* jobs, void
  *                          first pass on;
  *                          LOPC_REPAIR_SWEEPS: global sweeps over the marked
  *                          tiles, launched by the host in groups, until no
- *                          tile is marked (not available to enqueued calls).
+ *                          tile is marked (not available to enqueued calls);
+ *                          LOPC_REPAIR_POINTS: the paper's point worklists
+ *                          [Sec. IV-D]: after the first tile pass, every
+ *                          point with a same-bin lower neighbour is listed;
+ *                          each iteration recomputes the listed points and
+ *                          lists, once per iteration (a per-point stamp of
+ *                          the last iteration it was listed for), the upper
+ *                          neighbours of those that rose, in the other of
+ *                          two lists; host-driven like the sweeps (not
+ *                          available to enqueued calls).  It needs 12 more
+ *                          workspace bytes per point: query
+ *                          lopc_workspace_size after setting it.
  *   LOPC_OPT_TILE_3D       tile of the repair of 3D fields (each workgroup
  *                          holds one tile and a one-point halo in LDS):
  *                          0 (default) 4 x 8 x 32, 1: 8 x 8 x 32,
@@ -298,7 +309,7 @@ enum { LOPC_OPT_BATCH_GRAPH = 1, LOPC_OPT_GRAPH_SWEEPS = 2, LOPC_OPT_PERSIST_PCT
        LOPC_OPT_REPAIR = 4, LOPC_OPT_TILE_3D = 5, LOPC_OPT_TILE_2D = 6,
        LOPC_OPT_SWEEP_ORDER = 7 };
 enum { LOPC_REPAIR_AUTO = 0, LOPC_REPAIR_HYBRID = 1, LOPC_REPAIR_QUEUE = 2,
-       LOPC_REPAIR_SWEEPS = 3 };
+       LOPC_REPAIR_SWEEPS = 3, LOPC_REPAIR_POINTS = 4 };
 int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value);
 /* The current value of a context option into *h_value; LOPC_E_ARG for an
  * unknown option or a NULL argument. */

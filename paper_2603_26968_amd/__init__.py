@@ -19,7 +19,7 @@ _BINDING = (
     "lopc_ctx_set_option", "lopc_ctx_get_option", "LOPC_OPT_BATCH_GRAPH", "LOPC_OPT_GRAPH_SWEEPS",
     "LOPC_OPT_PERSIST_PCT", "lopc_ctx_last_batch_headers", "lopc_batch_autotune",
     "autotune_compress_batch", "verify", "VerifyReport", "lopc_verify",
-    "compress_enqueue", "LOPC_OPT_REPAIR", "LOPC_REPAIR_QUEUE", "LOPC_REPAIR_SWEEPS", "LOPC_REPAIR_HYBRID", "LOPC_REPAIR_AUTO", "LOPC_OPT_TILE_3D", "LOPC_OPT_TILE_2D", "LOPC_OPT_SWEEP_ORDER",
+    "compress_enqueue", "LOPC_OPT_REPAIR", "LOPC_REPAIR_QUEUE", "LOPC_REPAIR_SWEEPS", "LOPC_REPAIR_HYBRID", "LOPC_REPAIR_AUTO", "LOPC_REPAIR_POINTS", "LOPC_OPT_TILE_3D", "LOPC_OPT_TILE_2D", "LOPC_OPT_SWEEP_ORDER",
 )
 
 

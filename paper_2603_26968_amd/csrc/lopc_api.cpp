@@ -143,13 +143,14 @@ int lopc_workspace_size(lopc_ctx* ctx, int dtype, int ndim,
   Shape s;
   int st = make_shape(ndim, dims, &s);
   if (st) return st;
-  (void)ctx;
   // the largest over every tile shape, so that a workspace stays valid when
-  // the context's tile options change
+  // the context's tile options change; the point worklists when selected
+  const bool points = ctx && ctx->repair_mode == LOPC_REPAIR_POINTS;
   size_t b = 0;
   if (op == 0)
     for (int t2 = 0; t2 < kTiles2; ++t2)
-      for (int t3 = 0; t3 < kTiles3; ++t3) b = std::max(b, compress_layout(s, dtype, t2, t3).total);
+      for (int t3 = 0; t3 < kTiles3; ++t3)
+        b = std::max(b, compress_layout(s, dtype, t2, t3, points).total);
   else
     b = decompress_ws(s, dtype);
   *bytes = b;
@@ -250,6 +251,72 @@ static int repair_by_sweeps(lopc_ctx* ctx, const Shape& s, const CompressLayout&
   return LOPC_OK;
 }
 
+// The paper's point worklists (LOPC_REPAIR_POINTS), driven from the host:
+// after the first tile pass every point with flags is listed; iterations are
+// enqueued in groups (4, 8, 16), each reading its list length on the
+// device, with one read of the length ring per group; the repair ends with
+// the first empty list.  Every iteration that runs raises a subbin, so
+// n + 1 iterations always reach the fixed point (past that: an error).
+static int repair_by_points(lopc_ctx* ctx, const Shape& s, const CompressLayout& L, int dtype,
+                            uint8_t* ws, void* d_stream, size_t stream_cap, bool want_parts,
+                            hipStream_t hs, uint64_t* iters_out, uint64_t* listed_out) {
+  uint32_t* sub = (uint32_t*)(ws + L.sub);
+  uint32_t* counters = (uint32_t*)(ws + L.counters);
+  uint32_t* ring = counters + kCursorWord;  // the work-list cursors are unused here
+  uint32_t* wl[2] = {(uint32_t*)(ws + L.pw0), (uint32_t*)(ws + L.pw1)};
+  uint32_t* pstamp = (uint32_t*)(ws + L.pstamp);
+  const uint16_t* mask = (const uint16_t*)(ws + L.mask);
+  Params* prm = (Params*)(ws + L.prm);
+  const uint64_t k = dtype == 0 ? 4 : 8, W = kChunkBytes / k;
+  const uint32_t nch = (uint32_t)((s.n + W - 1) / W);
+  // grid-stride kernels of 256-thread workgroups, 8 per CU at most
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((s.n + 255) / 256,
+                                                                  (uint64_t)ctx->num_cu * 8));
+  const size_t report = L.queue + sizeof(RepairQueue);
+  HIP_CTX(ctx, launch_zero_n(pstamp, s.n, hs, ev_first(ctx, LOPC_PHASE_REPAIR)));
+  HIP_CTX(ctx, launch_point_seed(mask, (uint32_t)s.n, wl[0], ring, grid, hs));
+  uint32_t it = 0, batch = 4;
+  uint64_t listed = 0;
+  for (;;) {
+    for (uint32_t b = 0; b < batch; ++b, ++it)
+      HIP_CTX(ctx, launch_point_iter(s.box, mask, sub, wl[it & 1], wl[(it + 1) & 1], ring, pstamp,
+                                     it, grid, hs,
+                                     b + 1 == batch ? ev_last(ctx, LOPC_PHASE_REPAIR) : Ev{}));
+    HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, ws, report, hipMemcpyDeviceToHost, hs));
+    HIP_CTX(ctx, hipStreamSynchronize(hs));
+    const uint32_t* hc = (const uint32_t*)((const uint8_t*)ctx->h_prm + L.counters) + kCursorWord;
+    const int code = status_code(ctx->h_prm->status);
+    if (code != LOPC_OK && code != LOPC_E_CAPACITY) return code;
+    // lists it - batch .. it ran; the list of iteration it is still to run
+    bool done = false;
+    for (uint32_t t = it - batch; t <= it; ++t) {
+      const uint32_t m = hc[t & 63];
+      if (m == 0) {
+        done = true;
+        *iters_out = t + 1;  // the first pass counts as one
+        break;
+      }
+      if (t < it) listed += m;
+    }
+    if (done) break;
+    if ((uint64_t)it > s.n + 2) return LOPC_E_INTERNAL;  // unreachable
+    // clear the slots of the lists consumed by this group (the list of
+    // iteration it stays: the next group starts with it)
+    for (uint32_t t = it - batch; t < it; ++t) HIP_CTX(ctx, launch_zero_n(ring + (t & 63), 1, hs));
+    batch = std::min<uint32_t>(batch * 2, 16);
+  }
+  *listed_out = listed;
+  HIP_CTX(ctx, launch_encode(dtype, (uint32_t)s.n, ws + L.bins, sub, (uint16_t*)(ws + L.mask),
+                             ws + L.tail, (uint64_t*)(ws + L.offs), (uint32_t*)(ws + L.parts), prm,
+                             (uint8_t*)d_stream, stream_cap, nullptr, hs,
+                             ev_only(ctx, LOPC_PHASE_ENCODE)));
+  if (want_parts)
+    HIP_CTX(ctx, launch_sum_parts((const uint32_t*)(ws + L.parts), nch, prm, hs));
+  HIP_CTX(ctx, hipMemcpyAsync(ctx->h_prm, prm, sizeof(Params), hipMemcpyDeviceToHost, hs));
+  HIP_CTX(ctx, hipStreamSynchronize(hs));
+  return LOPC_OK;
+}
+
 int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
                   const int64_t* dims, double error_bound, int mode,
                   void* d_stream, size_t stream_cap, size_t* h_stream_size,
@@ -259,7 +326,8 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   if (!ctx || !d_field || !d_stream || !d_ws) return LOPC_E_ARG;
   const bool enqueue_only = h_stream_size == nullptr;
   // enqueued calls report on the device only, through a device-driven repair
-  if (enqueue_only && (!d_stream_size || h_stats || ctx->repair_mode == LOPC_REPAIR_SWEEPS))
+  if (enqueue_only && (!d_stream_size || h_stats || ctx->repair_mode == LOPC_REPAIR_SWEEPS ||
+                       ctx->repair_mode == LOPC_REPAIR_POINTS))
     return LOPC_E_ARG;
   if ((dtype != 0 && dtype != 1) || (mode != 0 && mode != 1)) return LOPC_E_ARG;
   Shape s;
@@ -268,7 +336,8 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   if (!std::isfinite(error_bound) || !(error_bound > 0)) return LOPC_E_BOUND;
   if (((uintptr_t)d_field & 15) || ((uintptr_t)d_stream & 3)) return LOPC_E_ARG;
   if (((uintptr_t)d_stream_size & 7) || ((uintptr_t)d_status & 3)) return LOPC_E_ARG;
-  CompressLayout L = compress_layout(s, dtype, ctx->tile2, ctx->tile3);
+  CompressLayout L = compress_layout(s, dtype, ctx->tile2, ctx->tile3,
+                                     ctx->repair_mode == LOPC_REPAIR_POINTS);
   if (ws_bytes < L.total || ((uintptr_t)d_ws & 255)) return LOPC_E_ARG;
   hipStream_t hs = (hipStream_t)stream;
   HIP_CTX(ctx, hipSetDevice(ctx->device));
@@ -370,6 +439,14 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
   int rc;
   if (rmode == LOPC_REPAIR_QUEUE) {
     rc = device_repair(0);
+  } else if (rmode == LOPC_REPAIR_POINTS) {
+    HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
+                              (uint16_t*)(ws + L.mask), sub, stamp, counters, nullptr,
+                              QueueRef{}, hs, ev_only(ctx, LOPC_PHASE_QUANT)));
+    rc = repair_by_points(ctx, s, L, dtype, ws, d_stream, stream_cap, h_stats != nullptr, hs,
+                          &sweeps, &active);
+    if (rc == LOPC_OK && (d_stream_size || d_status))
+      HIP_CTX(ctx, launch_report(prm, nullptr, d_stream_size, d_status, hs));
   } else if (rmode == LOPC_REPAIR_HYBRID || (rmode == LOPC_REPAIR_AUTO && enqueue_only)) {
     rc = device_repair((uint32_t)std::min<int>(std::max(ctx->sweep_hint, 1), (int)kMaxListSweeps));
   } else {

@@ -676,7 +676,7 @@ int lopc_ctx_set_option(lopc_ctx* ctx, int option, int64_t value) {
       ctx->tile3 = (int)value;
       return LOPC_OK;
     case LOPC_OPT_REPAIR:
-      if (value < LOPC_REPAIR_AUTO || value > LOPC_REPAIR_SWEEPS) return LOPC_E_ARG;
+      if (value < LOPC_REPAIR_AUTO || value > LOPC_REPAIR_POINTS) return LOPC_E_ARG;
       ctx->repair_mode = (int)value;
       return LOPC_OK;
     case LOPC_OPT_SWEEP_ORDER:

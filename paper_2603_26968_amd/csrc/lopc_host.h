@@ -129,6 +129,7 @@ inline Tiling make_tiling(const Box& b, int t2, int t3) {
 struct CompressLayout {
   size_t prm, counters, queue, stamp, qstate, parked, depth, ring, zero_end;  // zeroed prefix
   size_t blockers, lists, offs, parts, part, bins, mask, sub, lev, tail, total;
+  size_t pw0, pw1, pstamp;  // point worklists and stamps (LOPC_REPAIR_POINTS; else 0)
   uint32_t cap_log2;  // repair queue ring: 2^cap_log2 slots
 };
 
@@ -136,7 +137,8 @@ struct CompressLayout {
 // [1 + s % 64] tiles marked for sweep s (a ring the host clears after
 // reading), [kRelaxWord] 64-bit relaxation iteration total
 
-inline CompressLayout compress_layout(const Shape& s, int dtype, int t2, int t3) {
+inline CompressLayout compress_layout(const Shape& s, int dtype, int t2, int t3,
+                                      bool points = false) {
   const size_t k = dtype == 0 ? 4 : 8;
   const uint64_t W = kChunkBytes / k;
   const uint64_t nch = (s.n + W - 1) / W;
@@ -165,6 +167,12 @@ inline CompressLayout compress_layout(const Shape& s, int dtype, int t2, int t3)
   L.sub = o; o += align256(s.n * 4);
   L.lev = o; o += align256(s.box.nz == 1 ? s.n : 0);
   L.tail = o; o += align256(kRecordTailBytes);
+  L.pw0 = L.pw1 = L.pstamp = 0;
+  if (points) {
+    L.pw0 = o; o += align256(s.n * 4);
+    L.pw1 = o; o += align256(s.n * 4);
+    L.pstamp = o; o += align256(s.n * 4);
+  }
   L.total = o;
   return L;
 }

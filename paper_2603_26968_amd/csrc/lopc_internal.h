@@ -306,6 +306,15 @@ constexpr uint32_t kColourMinTiles = 32768;
 hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask,
                          uint32_t* sub, uint32_t* stamp, uint32_t* counters,
                          uint32_t sweep, hipStream_t s, Ev ev = {});
+// Point worklists (LOPC_REPAIR_POINTS): list every point with flags for
+// iteration 0 (its length in ring[0]); one iteration `it` over the list win
+// (length ring[it % 64]) appending to wout (length ring[(it + 1) % 64]).
+// Grid-stride kernels of `grid` workgroups.
+hipError_t launch_point_seed(const uint16_t* mask, uint32_t n, uint32_t* wl, uint32_t* ring,
+                             int grid, hipStream_t s, Ev ev = {});
+hipError_t launch_point_iter(Box box, const uint16_t* mask, uint32_t* sub, const uint32_t* win,
+                             uint32_t* wout, uint32_t* ring, uint32_t* pstamp, uint32_t it,
+                             int grid, hipStream_t s, Ev ev = {});
 // Encoder of a single field: encodes every chunk, parking its record in the
 // chunk's rows of bins / sub / mask (which it overwrites) or, for the last
 // chunk, in tail (kRecordTailBytes); then the record offsets (into offs, one

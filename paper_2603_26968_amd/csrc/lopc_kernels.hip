@@ -1314,6 +1314,90 @@ __global__ __launch_bounds__(kThreads) void k_sweep_list(
   }
 }
 
+// ---------------------------------------------------------- point worklists
+// The paper's schedule of the repair, for comparison [Sec. IV-D, the loop of
+// Alg. 1]: worklists of single points instead of tiles.  Iteration `it`
+// recomputes the points listed for it from their lower neighbours in global
+// memory and lists, for iteration it + 1, the upper neighbours of those that
+// rose, each at most once per iteration (a per-point stamp holds the last
+// iteration the point was listed for).  The two lists alternate; the list
+// lengths sit in a 64-slot ring of counters.  Subbins only rise and stay
+// below the least fixed point, so concurrent reads of stale values are
+// harmless: a point that reads a value before it rises is listed again.
+
+// list every point with a same-bin lower neighbour for iteration 0
+__global__ __launch_bounds__(kThreads) void k_point_seed(const uint16_t* __restrict__ mask,
+                                                         uint32_t n, uint32_t* wl,
+                                                         uint32_t* ring) {
+  for (uint32_t base = blockIdx.x * kThreads; base < n; base += gridDim.x * kThreads) {
+    const uint32_t i = base + threadIdx.x;
+    const bool go = i < n && mask[i] != 0;
+    const uint64_t b = __ballot(go);
+    if (!b) continue;  // wave-uniform
+    uint32_t pos = 0;
+    if (lane() == 0) pos = atomicAdd(&ring[0], (uint32_t)__popcll(b));
+    pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)pos);
+    if (go) wl[pos + lane_prefix(b)] = i;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_point_iter(Box box, const uint16_t* __restrict__ mask,
+                                                         uint32_t* sub, const uint32_t* win,
+                                                         uint32_t* wout, uint32_t* ring,
+                                                         uint32_t* pstamp, uint32_t it) {
+  const uint32_t nin = ring[it & 63];
+  const uint32_t nx = (uint32_t)box.nx, nxy = (uint32_t)box.nx * (uint32_t)box.ny;
+  for (uint32_t base = blockIdx.x * kThreads; base < nin; base += gridDim.x * kThreads) {
+    const uint32_t e = base + threadIdx.x;
+    bool rose = false;
+    uint32_t p = 0;
+    int z = 0, y = 0, x = 0;
+    if (e < nin) {
+      p = win[e];
+      z = (int)(p / nxy);
+      y = (int)((p / nx) % (uint32_t)box.ny);
+      x = (int)(p % nx);
+      const uint32_t m = mask[p];
+      const uint32_t cur = sub[p];
+      uint32_t best = cur;
+#pragma unroll
+      for (int j = 0; j < 14; ++j) {
+        if ((m >> j) & 1u) {  // a flagged neighbour lies in the grid
+          const uint32_t q = p + (uint32_t)(kOff[j][0] * (int)nxy + kOff[j][1] * (int)nx + kOff[j][2]);
+          const uint32_t c = sub[q] + ((j & 1) ? 0u : 1u);
+          best = c > best ? c : best;
+        }
+      }
+      if (best > cur) {
+        atomicMax(&sub[p], best);
+        rose = true;
+      }
+    }
+    // list the upper neighbours of the points that rose: q at offset j from
+    // p whose flags name p (flag j ^ 1)
+#pragma unroll
+    for (int j = 0; j < 14; ++j) {
+      bool app = false;
+      uint32_t q = 0;
+      if (rose) {
+        const int zz = z + kOff[j][0], yy = y + kOff[j][1], xx = x + kOff[j][2];
+        if (zz >= 0 && zz < box.nz && yy >= 0 && yy < box.ny && xx >= 0 && xx < box.nx) {
+          q = ((uint32_t)zz * (uint32_t)box.ny + (uint32_t)yy) * nx + (uint32_t)xx;
+          app = ((mask[q] >> (j ^ 1)) & 1u) && atomicMax(&pstamp[q], it + 1) < it + 1;
+        }
+      }
+      const uint64_t b = __ballot(app);
+      if (b) {
+        const int leader = __builtin_ctzll(b);
+        uint32_t pos = 0;
+        if (lane() == leader) pos = atomicAdd(&ring[(it + 1) & 63], (uint32_t)__popcll(b));
+        pos = (uint32_t)__builtin_amdgcn_readlane((int)pos, leader);
+        if (app) wout[pos + lane_prefix(b)] = q;
+      }
+    }
+  }
+}
+
 // The tiles listed for sweep `sweep` become the first items of the queue.
 __global__ __launch_bounds__(kThreads) void k_seed_queue(const uint32_t* counters,
                                                          const uint32_t* lists, uint32_t ntiles,
@@ -1692,6 +1776,20 @@ hipError_t launch_repair(Box box, Tiling t, const uint16_t* mask, uint32_t* sub,
     LOPC_WITH_TILE(t, launch_ev(k_repair<TZ, TY, TX>, dim3(n), dim3(kThreads), s, e, box, t,
                                 mask, sub, stamp, counters, sweep, col2 ? l : 2u));
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_point_seed(const uint16_t* mask, uint32_t n, uint32_t* wl, uint32_t* ring,
+                             int grid, hipStream_t s, Ev ev) {
+  launch_ev(k_point_seed, dim3(grid), dim3(kThreads), s, ev, mask, n, wl, ring);
+  return hipGetLastError();
+}
+
+hipError_t launch_point_iter(Box box, const uint16_t* mask, uint32_t* sub, const uint32_t* win,
+                             uint32_t* wout, uint32_t* ring, uint32_t* pstamp, uint32_t it,
+                             int grid, hipStream_t s, Ev ev) {
+  launch_ev(k_point_iter, dim3(grid), dim3(kThreads), s, ev, box, mask, sub, win, wout, ring,
+            pstamp, it);
   return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ LOPC_OPT_TILE_3D, LOPC_OPT_TILE_2D, LOPC_OPT_SWEEP_ORDER = 5, 6, 7
 kTile2Names = ("1x32x64", "1x16x128")
 kTile3Names = ("4x8x32", "8x8x32", "8x16x16")
 LOPC_REPAIR_AUTO, LOPC_REPAIR_HYBRID, LOPC_REPAIR_QUEUE, LOPC_REPAIR_SWEEPS = 0, 1, 2, 3
+LOPC_REPAIR_POINTS = 4
 PHASES = ("range", "quant", "repair", "encode", "offsets", "decode")
 
 
@@ -412,8 +413,11 @@ _sizes = {}
 
 
 def _sizes_for(ctx, shape, dtype):
-    """(compress bound, compress workspace, decompress workspace), cached."""
-    key = (tuple(shape), dtype)
+    """(compress bound, compress workspace, decompress workspace), cached
+    (the compress workspace also depends on whether the context's repair
+    scheduler is the point worklists)."""
+    key = (tuple(shape), dtype,
+           lopc_ctx_get_option(ctx, LOPC_OPT_REPAIR) == LOPC_REPAIR_POINTS)
     v = _sizes.get(key)
     if v is None:
         v = (lopc_compress_bound(shape, dtype), lopc_workspace_size(ctx, shape, dtype, 0),

@@ -92,7 +92,8 @@ def test_schedulers_agree(P, ref, name, gen, eb):
     ctx = lopc.lopc_ctx_create(0)
     try:
         for mode in (lopc.LOPC_REPAIR_SWEEPS, lopc.LOPC_REPAIR_QUEUE, lopc.LOPC_REPAIR_HYBRID,
-                     lopc.LOPC_REPAIR_HYBRID, lopc.LOPC_REPAIR_AUTO, lopc.LOPC_REPAIR_SWEEPS):
+                     lopc.LOPC_REPAIR_HYBRID, lopc.LOPC_REPAIR_AUTO, lopc.LOPC_REPAIR_POINTS,
+                     lopc.LOPC_REPAIR_SWEEPS):
             for order in (1, 2):
                 lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_REPAIR, mode)
                 lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_SWEEP_ORDER, order)
@@ -126,7 +127,8 @@ def test_tile_shapes_agree(P, ref, t2, t3):
             t = torch.from_numpy(x).cuda()
             for m, order in ((lopc.LOPC_REPAIR_AUTO, 0), (lopc.LOPC_REPAIR_AUTO, 1),
                              (lopc.LOPC_REPAIR_QUEUE, 0), (lopc.LOPC_REPAIR_HYBRID, 0),
-                             (lopc.LOPC_REPAIR_SWEEPS, 1), (lopc.LOPC_REPAIR_SWEEPS, 2)):
+                             (lopc.LOPC_REPAIR_SWEEPS, 1), (lopc.LOPC_REPAIR_SWEEPS, 2),
+                             (lopc.LOPC_REPAIR_POINTS, 0)):
                 lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_REPAIR, m)
                 lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_SWEEP_ORDER, order)
                 s = P.compress(t, eb, mode, ctx=ctx)
@@ -136,6 +138,34 @@ def test_tile_shapes_agree(P, ref, t2, t3):
             out, size, status = P.compress_enqueue(t, eb, mode, ctx=ctx)
             torch.cuda.synchronize()
             assert status.item() == 0 and out[:size.item()].cpu().numpy().tobytes() == want
+    finally:
+        lopc.lopc_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("shape,dt", [((1, 5000), np.float32), ((300, 1, 1), np.float64),
+                                      ((20, 30, 7), np.float32)],
+                         ids=["row", "column", "block"])
+def test_point_worklists_on_falling_chains(P, ref, shape, dt):
+    """The point-worklist scheduler on the worst case (one more iteration per
+    point of the chain) gives the oracle's bytes, and s = n-1 .. 0 along a
+    single chain."""
+    from paper_2603_26968_amd import lopc
+    x = _falling(shape, dt)
+    _say("point worklists, falling chain", shape)
+    want = ref.compress(x, 10.0, ref.ABS)
+    t = torch.from_numpy(x).cuda()
+    ctx = lopc.lopc_ctx_create(0)
+    try:
+        lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_REPAIR, lopc.LOPC_REPAIR_POINTS)
+        s, st = P.compress(t, 10.0, "abs", stats=True, ctx=ctx)
+        assert s.cpu().numpy().tobytes() == want
+        assert st["repair_sweeps"] >= 2
+        if sum(d > 1 for d in shape) == 1:  # a single chain through every point
+            _, sub = ref.decode_codes(want)
+            assert np.array_equal(sub.ravel().astype(np.int64), np.arange(x.size - 1, -1, -1))
+        # host-driven: not for enqueued calls
+        with pytest.raises(lopc.LopcError):
+            P.compress_enqueue(t, 10.0, "abs", ctx=ctx)
     finally:
         lopc.lopc_ctx_destroy(ctx)
 
