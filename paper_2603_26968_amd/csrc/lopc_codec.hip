@@ -1237,10 +1237,13 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
     bmin = min(bmin, s_mm[0][w]);
     bmax = max(bmax, s_mm[1][w]);
   }
-  const bool table = (uint64_t)bmax - (uint64_t)bmin < kTab;
+  // the table also holds the floor of bin bmax + 1: the keys of bin b are
+  // those from floor(b) up to floor(b + 1) (the bins are monotone in the
+  // value), so a point whose next bin has a floor needs no re-quantization
+  const bool table = (uint64_t)bmax - (uint64_t)bmin < kTab - 1;
   Key* T = (Key*)spare;
   if (table) {
-    const uint32_t R = (uint32_t)((uint64_t)bmax - (uint64_t)bmin) + 1;
+    const uint32_t R = (uint32_t)((uint64_t)bmax - (uint64_t)bmin) + 2;
     for (uint32_t e = threadIdx.x; e < R; e += kCT) {
       int64_t klo;
       T[e] = bin_floor_key<K>(bmin + (int64_t)e, inv, winv, klo) ? (Key)klo : kNoKey;
@@ -1256,8 +1259,11 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
     const uint64_t s = (uint64_t)sv[i];
     int64_t klo;
     bool have;
+    Key next = kNoKey;  // floor of bin b + 1, when known
     if (table) {
-      const Key t = T[(uint32_t)((uint64_t)b - (uint64_t)bmin)];
+      const uint32_t e = (uint32_t)((uint64_t)b - (uint64_t)bmin);
+      const Key t = T[e];
+      next = T[e + 1];
       have = t != kNoKey;
       klo = (int64_t)t;
     } else {
@@ -1269,7 +1275,12 @@ __device__ __forceinline__ void decode_body(const uint8_t* __restrict__ stream, 
       bad = true;
     } else {
       v = Tr::unkey(klo + (int64_t)s);
-      if (s && Tr::q(Tr::to_double(v), inv) != b) bad = true;
+      if (next != kNoKey) {
+        // inside bin b iff below the floor of bin b + 1
+        if (s >= (uint64_t)((int64_t)next - klo)) bad = true;
+      } else if (s && Tr::q(Tr::to_double(v), inv) != b) {
+        bad = true;
+      }
     }
     out[p0 + j] = v;
   }
