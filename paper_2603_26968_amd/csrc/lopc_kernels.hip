@@ -914,6 +914,25 @@ __device__ void q_finish(uint32_t dirs, uint32_t t, const TileCoord& c, const Ti
     __hip_atomic_fetch_add(&Q.q->pending, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Same-bin flags of an owned point of a float64 tile whose halo bins span
+// 2^31 or more: every neighbour in the grid re-quantized from its key (one
+// at a time; a rare path).
+template <int K, int TZ, int TY, int TX>
+__device__ __forceinline__ uint32_t wide_same(const int64_t* Pk, int li, int64_t b, double inv,
+                                              int z, int y, int x, const Box& box) {
+  using G = TileGeom<TZ, TY, TX>;
+  constexpr int NJ = TZ == 1 ? 6 : 14;
+  uint32_t sm = 0;
+#pragma unroll 1
+  for (int j = 0; j < NJ; ++j) {
+    const int zz = z + off_z(j), yy = y + off_y(j), xx = x + off_x(j);
+    if (zz < 0 || zz >= box.nz || yy < 0 || yy >= box.ny || xx < 0 || xx >= box.nx) continue;
+    const int64_t kq = Pk[li + off_lin(j, G::HX, G::HY * G::HX)];
+    sm |= (uint32_t)(Traits<8>::q(Traits<8>::to_double(Traits<8>::unkey(kq)), inv) == b) << j;
+  }
+  return sm;
+}
+
 // First pass, fused: build the order flags of the owned points (a2, the
 // flags of Alg. 1) from the bins and values of the tile and its halo, write
 // them, then relax with halo subbins 0 (the first sweep of a3).
@@ -930,18 +949,26 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
   using G = TileGeom<TZ, TY, TX>;
   using Key = typename Tr::Bin;  // keys fit the signed type of the bins
   using Bin = typename Tr::Bin;
-  // key and bin of a halo point side by side: one LDS read per neighbour
-  // (one 8-byte read for float32, one 16-byte read for float64)
-  using KB = typename std::conditional<K == 4, uint2, ulonglong2>::type;
+  // float32: key and bin of a halo point side by side, one 8-byte LDS read
+  // per neighbour.  float64: the 8-byte key, and the low 32 bits of the bin
+  // (12 instead of 16 bytes per point), which decide equality of two bins
+  // exactly whenever the halo's bins span less than 2^31; a tile whose bins
+  // span more ("wide") re-quantizes a neighbour's value to compare bins.
+  using KB = uint2;
   constexpr int NJ = TZ == 1 ? 6 : 14;  // 2D: only the in-plane offsets
-  constexpr int kKB = G::H * (int)sizeof(KB);
+  constexpr int kKB = G::H * (K == 4 ? 8 : 12);
   // the subbins of the halo, then (2D) the peeling state, reuse the buffer
   constexpr int kS = G::H * 4 + (TZ == 1 ? KahnLds<TZ, TY, TX>::kBytes : 0);
   constexpr int kBytes = kKB > kS ? kKB : kS;
   constexpr int HL = (G::H + kThreads - 1) / kThreads;  // halo loads per thread
   __shared__ __attribute__((aligned(16))) uint8_t buf[kBytes];
-  KB* P = (KB*)buf;
+  KB* P = (KB*)buf;                                  // float32
+  int64_t* Pk = (int64_t*)buf;                       // float64: keys
+  int32_t* Pb = (int32_t*)(buf + (K == 8 ? G::H * 8 : 0));  // float64: bin offsets
   uint32_t* S = (uint32_t*)buf;  // reused once the flags are built
+  __shared__ int64_t s_rng[2][kWaves];  // float64: per-wave least / greatest bin
+  int64_t bref = 0;   // float64: the halo's lowest bin
+  bool wide = false;  // float64: the halo's bins span 2^31 or more
 
   c = tile_coord<TZ, TY, TX>(t, tl);
   {
@@ -961,23 +988,71 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
     }
     const double inv = prm->inv;
     bool bad_v = false, bad_r = false;
+    if constexpr (K == 4) {
 #pragma unroll
-    for (int q = 0; q < HL; ++q) {
-      const int i = threadIdx.x + q * kThreads;
-      if (i < G::H) {
-        bad_v |= !Tr::finite(u[q]);
-        const int64_t bq = Tr::q(Tr::to_double(u[q]), inv);
-        bad_r |= bq > Tr::kBinLimit || bq < -Tr::kBinLimit;
-        KB e;
-        e.x = (decltype(e.x))(Key)Tr::key(u[q]);
-        e.y = (decltype(e.y))(Bin)bq;
-        P[i] = e;
+      for (int q = 0; q < HL; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        if (i < G::H) {
+          bad_v |= !Tr::finite(u[q]);
+          const int64_t bq = Tr::q(Tr::to_double(u[q]), inv);
+          bad_r |= bq > Tr::kBinLimit || bq < -Tr::kBinLimit;
+          KB e;
+          e.x = (uint32_t)(Key)Tr::key(u[q]);
+          e.y = (uint32_t)(Bin)bq;
+          P[i] = e;
+        }
       }
+    } else {
+      // bins of the halo points in the grid (others are never compared),
+      // their least and greatest over the block, then keys and offsets
+      int64_t lo = INT64_MAX, hi = INT64_MIN;
+#pragma unroll
+      for (int q = 0; q < HL; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        if (i < G::H) {
+          bad_v |= !Tr::finite(u[q]);
+          const int64_t bq = Tr::q(Tr::to_double(u[q]), inv);
+          bad_r |= bq > Tr::kBinLimit || bq < -Tr::kBinLimit;
+          Pk[i] = Tr::key(u[q]);
+          Pb[i] = (int32_t)(uint32_t)(uint64_t)bq;
+          const int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+          const int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
+          if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx) {
+            lo = bq < lo ? bq : lo;
+            hi = bq > hi ? bq : hi;
+          }
+        }
+      }
+      lo = wave_reduce(lo, OpMin{});
+      hi = wave_reduce(hi, OpMax{});
+      if (lane() == 0) {
+        s_rng[0][wave()] = lo;
+        s_rng[1][wave()] = hi;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        lo = s_rng[0][w] < lo ? s_rng[0][w] : lo;
+        hi = s_rng[1][w] > hi ? s_rng[1][w] : hi;
+      }
+      // hi >= lo: the tile's owned points lie in the grid
+      bref = lo;
+      wide = (uint64_t)hi - (uint64_t)lo >= (1ull << 31);
     }
     if (bad_v) set_status(prm, ST_NONFINITE);
     if (bad_r) set_status(prm, ST_RANGE);
   }
   __syncthreads();
+  // key and bin of the halo point at LDS index l (the bin compared with
+  // another point's only for equality, so float64 uses its offset)
+  auto key_at = [&](int l) -> Key {
+    if constexpr (K == 4) return (Key)(int32_t)P[l].x;
+    else return (Key)Pk[l];
+  };
+  auto bin_at = [&](int l) -> int64_t {
+    if constexpr (K == 4) return (int64_t)(int32_t)P[l].y;
+    else return (int64_t)Pb[l];  // low 32 bits: equality only (not wide)
+  };
 
   // the halo lies inside the grid: no neighbour needs a bounds check
   const bool inner = c.z0 - G::ZO >= 0 && c.z0 + TZ - 1 + G::ZO < box.nz && c.y0 >= 1 &&
@@ -992,22 +1067,27 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
     const int z = c.z0 + iz, y = c.y0 + iy, xx = c.x0 + ix;
     uint32_t sm = 0, lm = 0;
     const int li = G::local(i);
-    const KB ep = P[li];
-    const Key kp = (Key)ep.x;
-    const Bin bp = (Bin)ep.y;
-    if (z < box.nz && y < box.ny && xx < box.nx)
-      bins[((int64_t)z * box.ny + y) * box.nx + xx] = bp;  // for the encoder
+    const Key kp = key_at(li);
+    const int64_t bp = bin_at(li);  // float64: low 32 bits
+    // float64: the whole bin (from its low bits and the halo's lowest bin,
+    // or re-quantized when the halo is wide)
+    int64_t bfull = bp;
+    if constexpr (K == 8)
+      bfull = wide ? Tr::q(Tr::to_double(Tr::unkey(kp)), prm->inv)
+                   : bref + (int64_t)(uint32_t)((uint32_t)bp - (uint32_t)bref);
+    if (z < box.nz && y < box.ny && xx < box.nx)  // for the encoder
+      bins[((int64_t)z * box.ny + y) * box.nx + xx] = (Bin)bfull;
     if (inner) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int ln = li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2];
-        const KB eq = P[ln];
-        const Key kq = (Key)eq.x;
+        const Key kq = key_at(ln);
         // branch-free: same bin, and lower in (value, index) order
         const bool lower = (kq < kp) | ((kq == kp) & ((j & 1) != 0));
-        sm |= (uint32_t)((Bin)eq.y == bp) << j;
+        sm |= (uint32_t)(bin_at(ln) == bp) << j;
         lm |= (uint32_t)lower << j;
       }
+      if (K == 8 && wide) sm = wide_same<K, TZ, TY, TX>(Pk, li, bfull, prm->inv, z, y, xx, box);
       mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)(sm & lm);
     } else if (z < box.nz && y < box.ny && xx < box.nx) {
 #pragma unroll
@@ -1016,13 +1096,13 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
         if (zz < 0 || zz >= box.nz || yy < 0 || yy >= box.ny || xq < 0 || xq >= box.nx)
           continue;
         const int ln = li + kOff[j][0] * (G::HY * G::HX) + kOff[j][1] * G::HX + kOff[j][2];
-        const KB eq = P[ln];
-        const Key kq = (Key)eq.x;
+        const Key kq = key_at(ln);
         // odd j: the neighbour has the lower index
         const bool lower = (kq < kp) | ((kq == kp) & ((j & 1) != 0));
-        sm |= (uint32_t)((Bin)eq.y == bp) << j;
+        sm |= (uint32_t)(bin_at(ln) == bp) << j;
         lm |= (uint32_t)lower << j;
       }
+      if (K == 8 && wide) sm = wide_same<K, TZ, TY, TX>(Pk, li, bfull, prm->inv, z, y, xx, box);
       mask[((int64_t)z * box.ny + y) * box.nx + xx] = (uint16_t)(sm & lm);
     }
     mk[k] = (uint16_t)(sm & lm);

@@ -131,6 +131,20 @@ def test_special_values(P, ref):
     check(P, ref, big, 0.25, "abs", "large_bins_f64")
 
 
+def test_wide_bin_range_f64(P, ref):
+    # float64 tiles whose bins span far more than 2^31, with neighbours whose
+    # bins agree in their low 32 bits but differ; the left half of the 3D
+    # field keeps a narrow range, so narrow and wide tiles meet
+    rng = np.random.default_rng(31)
+    for shape in [(12, 20, 70), (70, 140), (6, 9, 300)]:
+        hi = rng.integers(0, 3, shape).astype(np.float64)
+        if len(shape) == 3:
+            hi[..., : shape[-1] // 2] = 0
+        x = hi * 2.0**32 + rng.integers(0, 3, shape) + rng.random(shape)
+        check(P, ref, x, 2.0, "abs", f"wide{shape}")  # bins up to 2^32 + 1
+        check(P, ref, x, 2e-10, "noa", f"wide{shape}")
+
+
 def _code(fn):
     import paper_2603_26968_amd as P
     try:
