@@ -1111,18 +1111,44 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
   __syncthreads();
   // halo subbins: 0, or (hc >= 0) those of the neighbour tiles of colour hc,
   // final from an earlier launch
-  for (int i = threadIdx.x; i < G::H; i += kThreads) {
-    uint32_t v = 0;
-    if (hc >= 0) {
+  if (TZ > 1 && hc >= 0) {
+    // loads in flight four at a time (points not taken read point 0)
+#pragma unroll
+    for (int q0 = 0; q0 < HL; q0 += 4) {
+    uint32_t hv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = q0 + r;
+      const int i = threadIdx.x + q * kThreads;
       const int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
       const int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
       const bool own = hz >= G::ZO && hz < G::ZO + TZ && hy >= 1 && hy <= TY && hx >= 1 &&
                        hx <= TX;
-      if (!own && z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx &&
-          tile_colour(z / TZ, y / TY, xx / TX) == (uint32_t)hc)
-        v = sub[((int64_t)z * box.ny + y) * box.nx + xx];
+      const bool take = i < G::H && !own && z >= 0 && z < box.nz && y >= 0 && y < box.ny &&
+                        xx >= 0 && xx < box.nx &&
+                        tile_colour(z / TZ, y / TY, xx / TX) == (uint32_t)hc;
+      const uint32_t v = sub[take ? ((int64_t)z * box.ny + y) * box.nx + xx : 0];
+      hv[r] = take ? v : 0u;
     }
-    S[i] = v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = threadIdx.x + (q0 + r) * kThreads;
+      if (i < G::H) S[i] = hv[r];
+    }
+    }
+  } else {
+    for (int i = threadIdx.x; i < G::H; i += kThreads) {
+      uint32_t v = 0;
+      if (hc >= 0) {  // 2D tiles: one load at a time (fewer registers)
+        const int hy = i / G::HX, hx = i % G::HX;
+        const int y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
+        const bool own = hy >= 1 && hy <= TY && hx >= 1 && hx <= TX;
+        if (!own && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx &&
+            tile_colour(c.z0, y / TY, xx / TX) == (uint32_t)hc)
+          v = sub[((int64_t)c.z0 * box.ny + y) * box.nx + xx];
+      }
+      S[i] = v;
+    }
   }
   __syncthreads();
   uint8_t* lvb = nullptr;
@@ -1213,20 +1239,41 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
   {
     uint32_t hv[HL];
     uint16_t hm[HL];
+    // every load issued unconditionally (points outside the grid or the
+    // halo read point 0 and are zeroed afterwards), so that all of them are
+    // in flight together instead of one wait per halo point
+    auto take = [&](int q, int64_t g, bool in) {
+      const uint32_t v =
+          QM ? __hip_atomic_load(sub + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : sub[g];
+      const uint16_t m = mask[g];
+      hv[q] = in ? v : 0u;
+      hm[q] = in ? m : (uint16_t)0;
+    };
+    // a halo inside the grid (most tiles): 32-bit offsets from the halo's
+    // first point, no bounds checks
+    const bool inner = c.z0 - G::ZO >= 0 && c.z0 + TZ - 1 + G::ZO < box.nz && c.y0 >= 1 &&
+                       c.y0 + TY < box.ny && c.x0 >= 1 && c.x0 + TX < box.nx &&
+                       (uint64_t)box.ny * (uint64_t)box.nx * G::HZ < (1ull << 31);
+    if (inner) {
+      const int64_t g0 = ((int64_t)(c.z0 - G::ZO) * box.ny + (c.y0 - 1)) * box.nx + (c.x0 - 1);
+      const uint32_t nyx = (uint32_t)box.ny * (uint32_t)box.nx;
 #pragma unroll
-    for (int q = 0; q < HL; ++q) {
-      const int i = threadIdx.x + q * kThreads;
-      hv[q] = 0;
-      hm[q] = 0;
-      if (i < G::H) {
-        int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
-        int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, x = c.x0 + hx - 1;
-        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 && x < box.nx) {
-          const int64_t g = ((int64_t)z * box.ny + y) * box.nx + x;
-          hv[q] = QM ? __hip_atomic_load(sub + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : sub[g];
-          hm[q] = mask[g];
-        }
+      for (int q = 0; q < HL; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        const uint32_t hz = (uint32_t)i / (G::HY * G::HX), hy = ((uint32_t)i / G::HX) % G::HY,
+                       hx = (uint32_t)i % G::HX;
+        const bool in = i < G::H;
+        take(q, in ? g0 + (int64_t)(hz * nyx + hy * (uint32_t)box.nx + hx) : 0, in);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < HL; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        const int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+        const int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, x = c.x0 + hx - 1;
+        const bool in = i < G::H && z >= 0 && z < box.nz && y >= 0 && y < box.ny && x >= 0 &&
+                        x < box.nx;
+        take(q, in ? ((int64_t)z * box.ny + y) * box.nx + x : 0, in);
       }
     }
 #pragma unroll
