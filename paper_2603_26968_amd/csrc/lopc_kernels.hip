@@ -398,20 +398,28 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
   // gather this wave's candidate points (3D tiles; in 2D fields same-bin
   // neighbours are common and the lists rarely fit)
   constexpr bool kList = TZ > 1;
-  uint32_t n = kList ? 0u : 65u;  // wave-uniform
+  constexpr int LP = kList ? G::PER : 1;
+  uint64_t act[LP];  // wave-uniform
+  uint32_t n = kList ? 0u : 65u;
 #pragma unroll
   for (int k = 0; k < (kList ? G::PER : 0); ++k) {
-    const uint64_t act = __ballot(mk[k] != 0);
-    const uint32_t c = (uint32_t)__popcll(act);
-    if (n + c <= 64 && mk[k]) {
-      const uint32_t pos = n + (uint32_t)__popcll(act & ((1ull << lane()) - 1ull));
-      wl_pt[wave() * 64 + pos] =
-          (uint32_t)G::local(threadIdx.x + k * kThreads) | (uint32_t)mk[k] << 12;
-      wl_cd[wave() * 64 + pos] = walk_code<TZ, TY, TX>(mk[k]);
-    }
-    n += c;
+    act[k] = __ballot(mk[k] != 0);
+    n += (uint32_t)__popcll(act[k]);
   }
   const bool listed = n <= 64;
+  if (kList && listed) {
+    uint32_t base = 0;
+#pragma unroll
+    for (int k = 0; k < LP; ++k) {
+      if (mk[k]) {
+        const uint32_t pos = base + (uint32_t)__popcll(act[k] & ((1ull << lane()) - 1ull));
+        wl_pt[wave() * 64 + pos] =
+            (uint32_t)G::local(threadIdx.x + k * kThreads) | (uint32_t)mk[k] << 12;
+        wl_cd[wave() * 64 + pos] = walk_code<TZ, TY, TX>(mk[k]);
+      }
+      base += (uint32_t)__popcll(act[k]);
+    }
+  }
   uint32_t my_pt = 0, my_cd = 0;
   __builtin_amdgcn_wave_barrier();
   if (listed && (uint32_t)lane() < n) {
@@ -975,15 +983,35 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
     // the values of the halo (every load issued first); their bins are
     // computed here (Sec. IV-A), not read back from a separate pass
     typename Tr::Raw u[HL];
+    // a halo inside the grid (most tiles): 32-bit offsets from the halo's
+    // first point, every load unconditional, no bounds checks
+    const bool hin = c.z0 - G::ZO >= 0 && c.z0 + TZ - 1 + G::ZO < box.nz && c.y0 >= 1 &&
+                     c.y0 + TY < box.ny && c.x0 >= 1 && c.x0 + TX < box.nx &&
+                     (uint64_t)box.ny * (uint64_t)box.nx * G::HZ < (1ull << 31);
+    if (hin) {
+      const int64_t g0 = ((int64_t)(c.z0 - G::ZO) * box.ny + (c.y0 - 1)) * box.nx + (c.x0 - 1);
+      const uint32_t nyx = (uint32_t)box.ny * (uint32_t)box.nx;
 #pragma unroll
-    for (int q = 0; q < HL; ++q) {
-      const int i = threadIdx.x + q * kThreads;
-      u[q] = 0;
-      if (i < G::H) {
-        int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
-        int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
-        if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx)
-          u[q] = x[((int64_t)z * box.ny + y) * box.nx + xx];
+      for (int q = 0; q < HL; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        const uint32_t hz = (uint32_t)i / (G::HY * G::HX), hy = ((uint32_t)i / G::HX) % G::HY,
+                       hx = (uint32_t)i % G::HX;
+        const bool in = i < G::H;
+        const typename Tr::Raw v =
+            x[in ? g0 + (int64_t)(hz * nyx + hy * (uint32_t)box.nx + hx) : 0];
+        u[q] = in ? v : (typename Tr::Raw)0;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < HL; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        u[q] = 0;
+        if (i < G::H) {
+          int hz = i / (G::HY * G::HX), hy = (i / G::HX) % G::HY, hx = i % G::HX;
+          int z = c.z0 + hz - G::ZO, y = c.y0 + hy - 1, xx = c.x0 + hx - 1;
+          if (z >= 0 && z < box.nz && y >= 0 && y < box.ny && xx >= 0 && xx < box.nx)
+            u[q] = x[((int64_t)z * box.ny + y) * box.nx + xx];
+        }
       }
     }
     const double inv = prm->inv;
