@@ -356,6 +356,76 @@ __device__ __forceinline__ uint32_t dense_best(const uint32_t* S, int li, uint32
   return r;
 }
 
+// Mask bits j of a point's flags spread over bytes: byte b of word r is
+// 0xff when bit 4r + b is set, so that an SDWA operand sign-extends byte b
+// to the all-ones / zero word dense_best builds with one instruction per
+// neighbour.
+template <int NW>
+__device__ __forceinline__ void spread_mask(uint32_t m, uint32_t (&pk)[NW]) {
+#pragma unroll
+  for (int r = 0; r < NW; ++r) {
+    const uint32_t x = (m >> (4 * r)) & 0xfu;
+    const uint32_t y = (x * 0x00204081u) & 0x01010101u;  // bit b of x to bit 8b
+    pk[r] = (y << 8) - y;                                  // 0x01 -> 0xff
+  }
+}
+// v & sext(byte B of p), and (v & sext(byte B of p)) - sext(byte B of p)
+template <int B>
+__device__ __forceinline__ uint32_t and_sext(uint32_t v, uint32_t p) {
+  uint32_t r;
+  if constexpr (B == 0)
+    asm("v_and_b32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(v), "v"(p));
+  else if constexpr (B == 1)
+    asm("v_and_b32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1" : "=v"(r) : "v"(v), "v"(p));
+  else if constexpr (B == 2)
+    asm("v_and_b32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2" : "=v"(r) : "v"(v), "v"(p));
+  else
+    asm("v_and_b32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3" : "=v"(r) : "v"(v), "v"(p));
+  return r;
+}
+template <int B>
+__device__ __forceinline__ uint32_t sub_sext(uint32_t v, uint32_t p) {
+  uint32_t r;
+  if constexpr (B == 0)
+    asm("v_sub_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0" : "=v"(r) : "v"(v), "v"(p));
+  else if constexpr (B == 1)
+    asm("v_sub_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1" : "=v"(r) : "v"(v), "v"(p));
+  else if constexpr (B == 2)
+    asm("v_sub_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2" : "=v"(r) : "v"(v), "v"(p));
+  else
+    asm("v_sub_u32_sdwa %0, %1, sext(%2) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3" : "=v"(r) : "v"(v), "v"(p));
+  return r;
+}
+// the masked candidates of neighbours J.. (J a compile-time constant)
+template <int J, int NJ, int HX, int HXY, int NW>
+__device__ __forceinline__ void pk_cands(const uint32_t* S, int li, const uint32_t (&pk)[NW],
+                                         uint32_t* c) {
+  if constexpr (J < NJ) {
+    const uint32_t v = S[li + kOff[J][0] * HXY + kOff[J][1] * HX + kOff[J][2]];
+    const uint32_t vw = and_sext<J & 3>(v, pk[J >> 2]);
+    if constexpr (J & 1) c[J] = vw;
+    else c[J] = sub_sext<J & 3>(vw, pk[J >> 2]);
+    pk_cands<J + 1, NJ, HX, HXY, NW>(S, li, pk, c);
+  }
+}
+// dense_best with the mask spread over bytes (spread_mask)
+template <int NJ, int HX, int HXY, int NW>
+__device__ __forceinline__ uint32_t dense_best_pk(const uint32_t* S, int li, const uint32_t (&pk)[NW],
+                                                  uint32_t cur) {
+  uint32_t c[NJ];
+  pk_cands<0, NJ, HX, HXY, NW>(S, li, pk, c);
+  uint32_t a = max(max(cur, c[0]), c[1]);
+  uint32_t b = max(max(c[2], c[3]), c[4]);
+  uint32_t r = max(max(a, b), c[5]);
+  if constexpr (NJ > 6) {
+    const uint32_t d = max(max(c[6], c[7]), c[8]);
+    const uint32_t e = max(max(c[9], c[10]), c[11]);
+    const uint32_t f = max(max(c[12], c[13]), d);
+    r = max(max(r, e), f);
+  }
+  return r;
+}
+
 // Local fixed point of the tile (masks of the owned points in registers):
 // Gauss-Seidel passes over the owned points until none rises; the halo is
 // fixed.  Only points with a same-bin lower neighbour can rise; in a 3D
@@ -367,8 +437,11 @@ __device__ __forceinline__ uint32_t dense_best(const uint32_t* S, int li, uint32
 // slots and walks the mask bits.  When some lane of the wave has more than
 // three lower neighbours, the wave loads all stencil neighbours and selects
 // under the mask.  Adds the pass count to one of 64 statistics slots
-// itot[t % 64].
-template <int TZ, int TY, int TX>
+// itot[t % 64].  PK (3D tiles): the slots' masks are spread over bytes once
+// (spread_mask) and the dense visit masks with one SDWA instruction per
+// neighbour: fewer vector instructions, 16 more registers (the float64
+// first pass gains; where the registers cost occupancy it loses).
+template <int TZ, int TY, int TX, bool PK = false>
 __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
                       unsigned long long* itot, uint32_t t) {
   using G = TileGeom<TZ, TY, TX>;
@@ -435,6 +508,12 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
   __shared__ uint32_t flag[3];
   if (threadIdx.x < 3) flag[threadIdx.x] = 0;
   __syncthreads();
+  constexpr int NW = (NJ + 3) / 4;
+  uint32_t pk[PK && TZ > 1 ? G::PER : 1][NW];
+  if constexpr (PK && TZ > 1) {
+#pragma unroll
+    for (int k = 0; k < G::PER; ++k) spread_mask<NW>(mk[k], pk[k]);
+  }
   int iters = 0;
   for (;;) {
     int changed = 0;
@@ -446,6 +525,27 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
       // z in a 3D tile, one row in four in a 2D tile), in alternating
       // directions from pass to pass, so a chain along that axis crosses
       // the tile in a pass or two whichever way it runs
+      if constexpr (PK && TZ > 1) {
+        // the slots' masks spread over bytes once per run (below), slot
+        // order fixed at compile time in both directions
+        auto visit = [&](int k) {
+          if (!mk[k]) return;
+          const int li = li0 + k * G::kSlot;
+          const uint32_t cur = S[li];
+          const uint32_t best = dense_best_pk<NJ, G::HX, G::HY * G::HX>(S, li, pk[k], cur);
+          if (best > cur) {
+            S[li] = best;
+            changed = 1;
+          }
+        };
+        if (iters & 1) {
+#pragma unroll
+          for (int kk = 0; kk < G::PER; ++kk) visit(G::PER - 1 - kk);
+        } else {
+#pragma unroll
+          for (int kk = 0; kk < G::PER; ++kk) visit(kk);
+        }
+      } else {
       const bool rev = iters & 1;
 #pragma unroll 2
       for (int kk = 0; kk < G::PER; ++kk) {
@@ -460,6 +560,7 @@ __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
           S[li] = best;
           changed = 1;
         }
+      }
       }
     }
     if (__ballot(changed) && lane() == 0) flag[iters % 3] = 1;
@@ -1184,7 +1285,7 @@ __device__ __forceinline__ uint32_t tile0_body(const typename Traits<K>::Raw* __
     const int nlev = kahn_relax<TZ, TY, TX>(S, buf + G::H * 4, mk, up, lvb);
     if (threadIdx.x == 0) atomicAdd(&itot[t % 64], (unsigned long long)(nlev + 1));
   } else {
-    relax<TZ, TY, TX>(S, mk, counters, itot, t);
+    relax<TZ, TY, TX, K == 8>(S, mk, counters, itot, t);
   }
   uint32_t dirs = 0;
 #pragma unroll
