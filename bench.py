@@ -175,10 +175,16 @@ def run_steps(P, lopc, ctx, x, eb, steps, bufs, timing):
     tc, td = [], []
     s = stats = None
     torch.cuda.synchronize()
-    for _ in range(steps):
+    for i in range(steps):
+        # the statistics (sweeps, stream part sizes: one more small kernel)
+        # are taken from the last step only
+        last = i == steps - 1
         t0 = time.perf_counter()
-        s, stats, hdr = P.compress(x, eb, "noa", stats=True, header=True, out=stream_buf,
-                                   workspace=ws_c)
+        r = P.compress(x, eb, "noa", stats=last, header=True, out=stream_buf, workspace=ws_c)
+        if last:
+            s, stats, hdr = r
+        else:
+            s, hdr = r
         t1 = time.perf_counter()
         if timing:
             ph = lopc.lopc_ctx_last_timings(ctx)
