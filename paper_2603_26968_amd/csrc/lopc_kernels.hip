@@ -439,8 +439,9 @@ __device__ __forceinline__ uint32_t dense_best_pk(const uint32_t* S, int li, con
 // under the mask.  Adds the pass count to one of 64 statistics slots
 // itot[t % 64].  PK (3D tiles): the slots' masks are spread over bytes once
 // (spread_mask) and the dense visit masks with one SDWA instruction per
-// neighbour: fewer vector instructions, 16 more registers (the float64
-// first pass gains; where the registers cost occupancy it loses).
+// neighbour: fewer vector instructions, 16 more registers (used by the
+// float64 first pass and the repair of four-slot tiles; the float32 first
+// pass loses more occupancy than it saves).
 template <int TZ, int TY, int TX, bool PK = false>
 __device__ void relax(uint32_t* S, const uint16_t* mk, uint32_t* counters,
                       unsigned long long* itot, uint32_t t) {
@@ -1436,7 +1437,9 @@ __device__ __forceinline__ uint32_t repair_body(Box box, Tiling tl, const uint16
       nlev = level_relax<TZ, TY, TX>(S, mk, lv);
     }
   }
-  if (nlev < 0) relax<TZ, TY, TX>(S, mk, counters, itot, t);
+  // four-slot 3D tiles relax with the masks spread over bytes (k_repair is
+  // held to six workgroups per CU for the registers that takes)
+  if (nlev < 0) relax<TZ, TY, TX, (TZ > 1 && G::PER <= 4)>(S, mk, counters, itot, t);
   else if (threadIdx.x == 0) atomicAdd(&itot[t % 64], (unsigned long long)(nlev + 1));
   uint32_t dirs = 0;
 #pragma unroll
@@ -1514,7 +1517,7 @@ __device__ void mark_neighbours_col(uint32_t dirs, const TileCoord& c, const Til
 // 0, then colour 1, so a tile of colour 1 sees what its face and corner
 // neighbours changed earlier in the same sweep.
 template <int TZ, int TY, int TX>
-__global__ __launch_bounds__(kThreads) void k_repair(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_repair(
     Box box, Tiling tl, const uint16_t* __restrict__ mask,
     uint32_t* __restrict__ sub, uint32_t* stamp, uint32_t* counters,
     uint32_t sweep, uint32_t colour) {
