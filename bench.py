@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--oracle-job", help=argparse.SUPPRESS)
     ap.add_argument("--oracle-out", help=argparse.SUPPRESS)
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
+    ap.add_argument("--sweep-whole", action="store_true",
+                    help="eb sweep of a field above 16M points: oracle parity on the whole "
+                         "field at every bound (one oracle process per bound, beside the GPU)")
     ap.add_argument("--eb-sweep", action="store_true",
                     help="single-field workloads: also run NOA bounds 1e0 .. 1e-6 (CR, "
                          "throughput, sweeps, bins/subbins byte split)")
@@ -119,6 +122,10 @@ def measured_traffic(workload, phase):
     return None
 
 
+# the error-bound sweep: NOA bounds 10^-e
+SWEEP_EXPONENTS = range(0, 7)
+
+
 def oracle_job(path, eb, out):
     """The CPU baseline leg, run as a child process: the oracle compresses and
     decompresses the field stored at `path` (single thread) and writes the
@@ -143,10 +150,13 @@ def oracle_job(path, eb, out):
         json.dump(res, f)
 
 
-def _start_oracle(xh, eb, tmp, tag):
+def _start_oracle(xh, eb, tmp, tag, path=None):
+    """Start one oracle job on `xh` at bound `eb` (a child process); `path`:
+    the field already saved there."""
     import subprocess
-    path = os.path.join(tmp, f"{tag}.npy")
-    np.save(path, xh, allow_pickle=False)
+    if path is None:
+        path = os.path.join(tmp, f"{tag}.npy")
+        np.save(path, xh, allow_pickle=False)
     out = os.path.join(tmp, f"{tag}.json")
     cmd = [sys.executable, os.path.abspath(__file__), "--oracle-job", path, "--eb", repr(eb),
            "--oracle-out", out]
@@ -250,6 +260,13 @@ def bench_single(args, name):
         jobs["sample"] = _start_oracle(sample, args.eb, tmp, "sample")
         if sample is not xh and not args.no_parity:
             jobs["full"] = _start_oracle(xh, args.eb, tmp, "full")
+        if args.eb_sweep and args.sweep_whole and sample is not xh:
+            # whole-field parity at every bound of the sweep: one oracle
+            # process per bound, all beside the GPU run
+            fpath = os.path.join(tmp, "field.npy")
+            np.save(fpath, xh, allow_pickle=False)
+            for e in SWEEP_EXPONENTS:
+                jobs[f"sweep{e}"] = _start_oracle(xh, 10.0 ** (-e), tmp, f"sweep{e}", fpath)
 
     import torch
 
@@ -333,9 +350,10 @@ def bench_single(args, name):
     gpu_recon_sha = hashlib.sha256(bufs[3].cpu().numpy().view(np.uint8).tobytes()).hexdigest()
 
     extra_sweep = None
+    sweep_sha = {}
     if args.eb_sweep:
         extra_sweep = {}
-        for e in range(0, 7):
+        for e in SWEEP_EXPONENTS:
             eb = 10.0 ** (-e)
             _log("eb sweep", eb)
             try:
@@ -345,7 +363,14 @@ def bench_single(args, name):
                 continue
             Se = int(se.numel())
             par = None
-            if not args.no_cpu_baseline:
+            if f"sweep{e}" in jobs:
+                # compared with the whole-field oracle job when it ends
+                ye = P.decompress(se)
+                sweep_sha[e] = (hashlib.sha256(se.cpu().numpy().tobytes()).hexdigest(), Se,
+                                hashlib.sha256(ye.cpu().numpy().view(np.uint8).tobytes())
+                                .hexdigest())
+                del ye
+            elif not args.no_cpu_baseline:
                 par = _sweep_parity(P, xh, eb, se if sample is xh else None)
             extra_sweep[f"1e-{e}"] = {
                 "CR": round(n * k / Se, 3),
@@ -412,6 +437,17 @@ def bench_single(args, name):
             if "full" in jobs:
                 out["cpu_baseline"]["whole_field_s"] = round(full["compress_s"] +
                                                              full["decompress_s"], 1)
+        for e in SWEEP_EXPONENTS:
+            if f"sweep{e}" not in jobs:
+                continue
+            res = _finish_oracle(jobs[f"sweep{e}"])
+            if e not in sweep_sha:  # the GPU refused this bound
+                continue
+            sha, Se, rsha = sweep_sha[e]
+            out["eb_sweep"][f"1e-{e}"]["parity"] = {
+                "scope": "whole field",
+                "stream_identical": res["stream_sha256"] == sha and res["stream_bytes"] == Se,
+                "reconstruction_identical": res["recon_sha256"] == rsha}
     import shutil
     shutil.rmtree(tmp, ignore_errors=True)
     return out

@@ -265,3 +265,35 @@ def test_enqueued_compress_in_a_graph(P, ref, dt, shape):
         assert status.item() == 0 and size.item() == len(want), rep
         assert out[:len(want)].cpu().numpy().tobytes() == want, rep
         del junk
+
+
+REPEATS = [
+    ("turb3d_1e0", lambda: synth.turbulence_field((64, 96, 96), seed=7), 1.0, "noa"),
+    ("fronts2d_1e-1", lambda: synth.fronts_field((300, 500), seed=8), 1e-1, "noa"),
+    ("falling_chain", lambda: _falling((1, 1 << 16), np.float32), 10.0, "abs"),
+]
+
+
+@pytest.mark.parametrize("name,gen,eb,mode", REPEATS, ids=[r[0] for r in REPEATS])
+def test_repeated_compressions_on_one_context(P, ref, name, gen, eb, mode):
+    """A context learns from each compression how many sweeps to enqueue
+    before its first read on the next; call after call, in both sweep
+    orders, the bytes stay the oracle's."""
+    from paper_2603_26968_amd import lopc
+    x = gen()
+    _say("repeated compressions", name, x.shape)
+    want = ref.compress(x, eb, ref.ABS if mode == "abs" else ref.NOA)
+    t = torch.from_numpy(x).cuda()
+    ctx = lopc.lopc_ctx_create(0)
+    try:
+        lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_REPAIR, lopc.LOPC_REPAIR_SWEEPS)
+        for order in (1, 2):
+            lopc.lopc_ctx_set_option(ctx, lopc.LOPC_OPT_SWEEP_ORDER, order)
+            sweeps = []
+            for _ in range(3):
+                s, st = P.compress(t, eb, mode, stats=True, ctx=ctx)
+                assert s.cpu().numpy().tobytes() == want, (name, order)
+                sweeps.append(st["repair_sweeps"])
+            assert min(sweeps) > 1, sweeps
+    finally:
+        lopc.lopc_ctx_destroy(ctx)
