@@ -165,8 +165,10 @@ int lopc_workspace_size(lopc_ctx* ctx, int dtype, int ndim,
 // the encoder runs after them.  A sweep with no marked tile costs one empty
 // launch.  Every sweep that runs raises a subbin, and a dependency chain
 // crosses at most n tiles, so n + 1 sweeps always reach the fixed point.
-// Past `limit` sweeps it returns kRestartOnQueue (the encoder has not run).
+// Past `limit` sweeps, once the tile runs exceed kChainRuns per tile, it
+// returns kRestartOnQueue (the encoder has not run).
 constexpr int kRestartOnQueue = 1;
+constexpr uint64_t kChainRuns = 16;
 static int repair_by_sweeps(lopc_ctx* ctx, const Shape& s, const CompressLayout& L, int dtype,
                             uint8_t* ws, void* d_stream, size_t stream_cap, const Tiling& tl,
                             bool want_parts, hipStream_t hs, uint64_t limit,
@@ -221,11 +223,19 @@ static int repair_by_sweeps(lopc_ctx* ctx, const Shape& s, const CompressLayout&
       HIP_CTX(ctx, launch_zero_n(counters + 1 + (t & 63), 1, hs));
     next += batch;
     batch = next == K + 1 ? 4 : std::min<uint32_t>(batch * 2, 16);
-    if ((uint64_t)next + batch > limit) {
+    // a limit below n + 2 (the default's) holds only while the tile runs so
+    // far exceed kChainRuns per tile: a chain across T tiles reruns nearly
+    // every tile it has not settled yet in each sweep, so it passes that mark
+    // within the limit and goes to the queue, while a field that merely needs
+    // many sweeps keeps sweeping
+    const uint64_t cap =
+        limit < s.n + 2 && active <= kChainRuns * (uint64_t)tl.ntiles ? s.n + 2 : limit;
+    if (next > cap) {
       *sweeps_out = sweeps;
       *active_out = active;
-      return limit >= s.n + 2 ? LOPC_E_INTERNAL : kRestartOnQueue;  // the former unreachable
+      return cap >= s.n + 2 ? LOPC_E_INTERNAL : kRestartOnQueue;  // the former unreachable
     }
+    batch = (uint32_t)std::min<uint64_t>(batch, cap + 1 - next);  // the last group ends at cap
     for (uint32_t b = 0; b < batch; ++b)
       HIP_CTX(ctx, launch_repair(s.box, tl, (const uint16_t*)(ws + L.mask), sub, stamp,
                                  counters, next + b, hs,
@@ -451,9 +461,10 @@ int lopc_compress(lopc_ctx* ctx, const void* d_field, int dtype, int ndim,
     rc = device_repair((uint32_t)std::min<int>(std::max(ctx->sweep_hint, 1), (int)kMaxListSweeps));
   } else {
     // host-driven sweeps (the fastest schedule when dependencies cross few
-    // tiles); the default gives up after kAutoSweeps sweeps and restarts the
-    // repair from the first pass on the queue, which runs a chain across
-    // many tiles a few times per tile instead of once per sweep
+    // tiles); the default gives up after kAutoSweeps sweeps if by then the
+    // sweeps have run more than kChainRuns tiles per tile of the field, and
+    // restarts the repair from the first pass on the queue, which runs a
+    // chain across many tiles a few times per tile instead of once per sweep
     HIP_CTX(ctx, launch_tile0(dtype, d_field, s.box, tl, prm, ws + L.bins,
                               (uint16_t*)(ws + L.mask), sub, stamp, counters, nullptr,
                               QueueRef{}, hs, ev_only(ctx, LOPC_PHASE_QUANT),
